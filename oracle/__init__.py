@@ -20,7 +20,7 @@ OK, WARN_MAX_ROUNDS, ERR_ARG, ERR_DOMAIN = 0, 1, -1, -2
 def build():
     """Compile liboracle.so with g++ (always recompiles)."""
     cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
-           "-fno-fast-math", "-o", _LIB + ".tmp", _SRC]
+           "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lquadmath"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
 

@@ -2,8 +2,8 @@
 // Kullback-Leibler comparator.
 //
 // TEST INFRASTRUCTURE ONLY.  This file defines what the GPU library must
-// compute, in plain, slow, obviously-correct C++ (FP64, C library log, explicit
-// fma, std::sort).  It shares no code with the GPU library and is loaded only by
+// compute, in plain, slow, obviously-correct C++ (FP64, correctly rounded log,
+// explicit fma, std::sort).  It shares no code with the GPU library and is loaded only by
 // the tests, by the smoke check and by the benchmark's CPU-baseline leg.
 //
 // Paper: Baron & Darling, "Empirical complexity of comparator-based nearest
@@ -18,6 +18,8 @@
 // Parity unpinned: the round counts, FCR values and update counts at the
 // benchmark sizes have no printed value in the paper; only GPU-vs-oracle
 // parity and the paper's soft round bound apply there.
+
+#include <quadmath.h>
 
 #include <algorithm>
 #include <chrono>
@@ -85,9 +87,10 @@ void parallel_ranges(int64_t n, int threads, Fn f) {
 // y ranks before z for x when D(x||y) < D(x||z), with
 // D(x||y) = sum_i x_i log(x_i / y_i) summed over every stored coordinate.
 // log(x_i / y_i) is written as log x_i - log y_i (exact algebra) with the logs
-// taken once per coordinate from the C library, and the sum is folded in
-// ascending coordinate order with one fused multiply-add per term.  This fixes
-// every rounding, so the value is a reproducible FP64 number.
+// taken once per coordinate and rounded correctly to FP64, and the sum is
+// folded in ascending coordinate order with one fused multiply-add per term.
+// This fixes every rounding, so the value is a reproducible FP64 number that
+// does not depend on any math library's accuracy.
 // Ties between equal keys go to the lower point index (the paper is silent).
 // ---------------------------------------------------------------------------
 double kl_key(const double* P, const double* L, int D, int64_t x, int64_t y) {
@@ -189,10 +192,11 @@ uint64_t oracle_mix64(uint64_t z) { return mix64(z); }
 uint64_t oracle_hash(uint64_t s, uint64_t t, uint64_t a, uint64_t b) { return hash4(s, t, a, b); }
 uint64_t oracle_bound(uint64_t h, uint64_t m) { return bound(h, m); }
 
-// L = log(P), elementwise, C library log.
+// L = log(P), elementwise, rounded correctly to FP64: the natural log is taken
+// in binary128 (113-bit significand) and rounded once to the nearest double.
 void oracle_log_table(const double* P, int64_t count, double* L, int threads) {
   parallel_ranges(count, threads, [&](int64_t lo, int64_t hi, int) {
-    for (int64_t i = lo; i < hi; ++i) L[i] = std::log(P[i]);
+    for (int64_t i = lo; i < hi; ++i) L[i] = (double)logq((__float128)P[i]);
   });
 }
 

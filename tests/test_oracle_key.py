@@ -15,11 +15,21 @@ def _table(P):
     return P64, oracle.log_table(P64)
 
 
-def test_log_table_is_c_library_log():
-    P64 = synth.dirichlet(5, 50, 7, np.float64)
-    L = oracle.log_table(P64)
-    for v, l in zip(P64.ravel()[:200], L.ravel()[:200]):
-        assert l == math.log(v)  # CPython's math.log calls the C library log
+def test_log_table_is_correctly_rounded():
+    # Reference: the natural log to 45 significant digits in Python's decimal
+    # module, then rounded to the nearest double.  Includes FP32-widened values
+    # and the region near 1 where log loses relative accuracy most easily.
+    from decimal import Decimal, getcontext
+    getcontext().prec = 45
+    vals = np.concatenate([
+        synth.dirichlet(5, 300, 20, np.float32).ravel().astype(np.float64),
+        synth.dirichlet(6, 100, 7, np.float64).ravel(),
+        1.0 - 2.0 ** -np.arange(1, 53, dtype=np.float64),
+        np.array([1e-12, 1.0, 0.5, 0.75, 2.0 ** -30, 0.7071067811865476, 0.7071067811865475]),
+    ])
+    L = oracle.log_table(vals)
+    for v, l in zip(vals, L):
+        assert l == float(Decimal(float(v)).ln()), v
 
 
 def test_self_divergence_is_exact_zero():
