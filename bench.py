@@ -1,0 +1,156 @@
+"""Benchmark: comparator evaluations per second and time-to-graph of
+comparator-based K-NN descent with the KL comparator, n=1e6 points of the
+20-simplex (21 FP32 coordinates), K=30, on one MI355X.
+
+One step = one whole descent through the C ABI (knnd_build_ex) on points
+already resident in HBM: validation and log table, random K-out start, every
+round (reverse neighbors, candidate join, KL keys, merge, FCR sample) until
+the stop test fires, lists copied to the caller's device buffer.
+
+value = sum over rounds of evals_alg (one KL key per receiver and distinct
+non-friend candidate, the oracle's count) / time-to-graph.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision plain]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "comparator evals/sec + time-to-graph (n=1e6,d=20,K=30), mixed vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def join_bytes_per_eval(D):
+    # gather of the candidate's FP64 log row plus its 4-byte index
+    return 8 * D + 4
+
+
+def cpu_baseline(P, d, K, seed, receivers, threads):
+    """The oracle's round 1 on a sample of receivers of the same workload."""
+    import oracle
+    import synth
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64, threads)
+    F0, k0 = oracle.initial_graph(P64, L, K, seed, threads)
+    xs = synth.subsample(seed, P.shape[0], receivers)
+    t = time.perf_counter()
+    _, _, _, ev = oracle.round_subset(P64, L, F0, k0, xs, threads)
+    secs = time.perf_counter() - t
+    return {"value": float(ev.sum()) / secs, "unit": "evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"round 1 of this workload for {receivers} receivers drawn without "
+                      f"replacement ({int(ev.sum())} evaluations, {secs:.1f} s, "
+                      f"{threads} threads; log table and start graph not timed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="plain", choices=["plain"])
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-receivers", type=int, default=60_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2202_00517_amd as knnd
+    import synth
+
+    cfg = dict(synth.CONFIGS[3])
+    cfg["n"] = args.n
+    n, d, K, seed = cfg["n"], cfg["d"], cfg["K"], cfg["seed"]
+    D = d + 1
+    log(f"generating {n} x {D} Dirichlet points")
+    P = synth.dirichlet(cfg["data_seed"], n, d, np.float32)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    Pd = torch.from_numpy(P).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    prm = knnd.default_params(precision=knnd.KNND_PREC_FP64)
+
+    def step():
+        return knnd.knnd_build_ex(Pd, d, K, seed, prm, stream=stream.cuda_stream)
+
+    for i in range(args.warmup):
+        out = step()
+        log(f"warmup {i}: rounds={out['rounds']}")
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        out = step()
+        torch.cuda.synchronize()
+        results.append((out, time.perf_counter() - ts))
+        log(f"step {i}: {1e3 * results[-1][1]:.1f} ms, rounds={out['rounds']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    evals = [sum(s["evals_alg"] for s in o["stats"]) for o, _ in results]
+    assert len(set(evals)) == 1, "evaluation counts differ between identical runs"
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = evals[0] / (elapsed / args.steps)
+    last = results[-1][0]
+
+    # roofline of the dominant kernel: the join (steps a2-a5), all launches of
+    # one round; algorithmic bytes = keys computed x (8 D + 4) bytes
+    join_ms = sum(s["ms_join"] for o, _ in results for s in o["stats"][1:])
+    join_rounds = sum(o["rounds"] for o, _ in results)
+    perf = sum(s["evals_performed"] for o, _ in results for s in o["stats"][1:])
+    bytes_alg = perf * join_bytes_per_eval(D)
+    achieved = bytes_alg / (join_ms * 1e-3) / 1e9 if join_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "k_join (all receiver classes of one round)",
+                "avg_launch_ms": round(join_ms / max(join_rounds, 1), 3),
+                "bytes_per_launch": int(bytes_alg / max(join_rounds, 1))}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Dirichlet(1^{D}) points on the {d}-simplex, FP32 storage, "
+                               f"n={n}, K={K}, seed={seed}, whole descent to the stop test",
+                   "n": n, "d": d, "K": K, "precision": args.precision},
+        "time_to_graph_ms": ms_per_step,
+        "rounds": last["rounds"],
+        "evals_alg": evals[0],
+        "per_round_ms": [round(s["ms"], 3) for s in last["stats"]],
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"cpu baseline: oracle round 1 on {args.cpu_receivers} receivers, {threads} threads")
+        line["cpu_baseline"] = cpu_baseline(P, d, K, seed, args.cpu_receivers, threads)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * knnd.h -- C ABI of libknnd.so: comparator-based K-nearest-neighbor descent
+ * with the Kullback-Leibler comparator, on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: Baron & Darling, "Empirical complexity of comparator-based nearest
+ * neighbor descent" (arXiv 2202.00517).
+ *   - Problem statement (Abstract; Section 2.3): n points, each point x gets
+ *     the K other points most similar to it in x's own order.
+ *   - Comparator (Section 2.2; Section 4 scaling experiment): y ranks before z
+ *     for x when D(x||y) < D(x||z), D(x||y) = sum_i x_i log(x_i / y_i),
+ *     summed over all d+1 stored coordinates.  Asymmetric, not a metric.
+ *   - Descent (Section 3.1): rounds of friend-of-a-friend candidate generation
+ *     ("Meet": co-friends, friends of friends, friends of co-friends) and
+ *     best-K selection ("Update"), each round computed from the round-start
+ *     snapshot (Section 4.2).
+ *   - Start (Section 3.2): a random K-out digraph without self-loops.
+ *   - Stop (Section 3.3): after the first round whose sampled friend
+ *     clustering rate does not increase.
+ *
+ * Exact conventions fixed by this library (the paper leaves them open):
+ *   key(x,y)   : logs are the correctly rounded FP64 natural logs of the
+ *                coordinates (FP32 inputs widened exactly); the key folds
+ *                acc = fma(x_i, log x_i - log y_i, acc) for i = 0..d in
+ *                ascending order, from acc = +0.0, all in FP64.
+ *   order      : (key, index) lexicographic; ties go to the lower index.
+ *   start      : draw a of point x is r = floor(H(seed,1,x,a) * (n-1) / 2^64),
+ *                y = r + (r >= x); the first K distinct draws are the friends.
+ *   FCR sample : s = 0..M-1 of round r: x = bnd(H(seed,2,r,s), n),
+ *                a = bnd(H(seed,3,r,s), K), b' = bnd(H(seed,4,r,s), K-1),
+ *                b = b' + (b' >= a); hit when F(x)[b] is a friend of
+ *                F(x)[a] or F(x)[a] is a friend of F(x)[b].
+ *   stop       : after round r when hits_r <= hits_{r-1}, or no list changed
+ *                (fixed point), or r == max_rounds.
+ *   H          : SplitMix64-finalizer hash
+ *                H(s,t,a,b) = mix64(mix64(mix64(s ^ t*0x9E3779B97F4A7C15) ^ a) ^ b).
+ * Results depend only on (points, K, seed, fcr_samples, max_rounds): not on
+ * the precision mode, on tiling or on scheduling.
+ *
+ * Threading: calls on distinct contexts/outputs may run concurrently.
+ * Nothing is retained between calls except inside a knnd_ctx.  No C++
+ * exception crosses this ABI.  On error, outputs are unspecified.
+ */
+#ifndef KNND_H
+#define KNND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KNND_ABI_VERSION 1
+
+typedef enum {
+    KNND_OK = 0,
+    KNND_WARN_MAX_ROUNDS = 1,   /* stopped by the round cap, not by the stop test */
+    KNND_ERR_ARG = -1,          /* null pointer, n < 2, d < 1, K < 2, K > n-1, K > 64,
+                                   n >= 2^30, max_rounds < 1, unknown enum value */
+    KNND_ERR_DOMAIN = -2,       /* a coordinate is NaN, infinite or <= 0 */
+    KNND_ERR_NOMEM = -3,        /* device allocation failed */
+    KNND_ERR_DEVICE = -4,       /* a HIP call failed, or no gfx950 device */
+    KNND_ERR_UNSUPPORTED = -5   /* valid request this build does not implement */
+} knnd_status;
+
+typedef enum { KNND_F32 = 0, KNND_F64 = 1 } knnd_dtype;
+
+typedef enum {
+    KNND_PREC_FP64 = 0,         /* every key computed in canonical FP64 */
+    KNND_PREC_MIXED_BF16 = 1,   /* reserved: BF16 cross term with FP64 recheck */
+    KNND_PREC_MIXED_FP16 = 2    /* reserved: FP16 cross term with FP64 recheck */
+} knnd_precision;
+
+/* flags */
+#define KNND_FLAG_NO_SKIP 0x1   /* also evaluate candidates reached only through
+                                   edges that were already present one round
+                                   earlier (same result, more work) */
+
+typedef struct {
+    int32_t precision;          /* knnd_precision */
+    int32_t dtype;              /* knnd_dtype of `points` */
+    int64_t fcr_samples;        /* M; <= 0 selects min(n, 10000) */
+    int32_t max_rounds;         /* <= 0 selects 100 */
+    int32_t flags;              /* KNND_FLAG_* */
+} knnd_params;
+
+/* Per-round record.  Entry 0 describes the initial graph (fcr_hits only). */
+typedef struct {
+    int64_t updates;            /* sum over x of |F_r(x) \ F_{r-1}(x)| */
+    int64_t fcr_hits;           /* friend clustering hits out of M samples */
+    int64_t evals_alg;          /* sum over x of |candidates of x|: one KL key per
+                                   (x, distinct non-friend candidate) */
+    int64_t evals_performed;    /* keys actually computed on the device */
+    int64_t rescues;            /* FP64 rechecks (mixed precision only) */
+    double ms;                  /* device time of the round (HIP events) */
+    double ms_join;             /* device time of the join kernels (steps a2-a5) */
+} knnd_round_stats;
+
+/* Fill *p with the defaults (FP64, F32 points, M = min(n,10000), 100 rounds). */
+void knnd_default_params(knnd_params* p);
+
+/* Human-readable name of a knnd_status value (static storage). */
+const char* knnd_status_string(int status);
+
+int knnd_abi_version(void);
+
+/*
+ * The basic call (Abstract; Section 2.3 problem statement).
+ *   points      host, [n][d+1] FP32 row-major, every coordinate finite and > 0
+ *               (points of the open simplex; the library never clamps)
+ *   out_idx     host, caller-allocated [n][K] int32: row x lists x's friends
+ *               best first in (key, index) order
+ *   out_updates host, caller-allocated [max_rounds] int64: entry r-1 is the
+ *               number of list changes in round r
+ *   max_rounds  round cap (>= 1)
+ *   out_rounds  host, rounds executed
+ * Uses the current HIP device and its null stream.  Returns a knnd_status.
+ */
+int knnd_build(const float* points, int64_t n, int32_t d, int32_t K, uint64_t seed,
+               int32_t* out_idx, int64_t* out_updates, int32_t max_rounds,
+               int32_t* out_rounds);
+
+/*
+ * Extended form.
+ *   points      [n][d+1] in p->dtype; host memory when on_device == 0,
+ *               device memory of the current HIP device when on_device != 0
+ *   p           parameters (NULL = defaults)
+ *   stream      hipStream_t as void* (NULL = null stream); all device work is
+ *               enqueued on it; the host synchronises once per round (stop
+ *               test) and fully before returning
+ *   out_idx     [n][K] int32, same memory kind as points
+ *   out_kl      optional [n][K] FP64 keys of out_idx, same memory kind
+ *   stats       optional host array [max_rounds + 1]
+ *   out_rounds  host
+ */
+int knnd_build_ex(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed,
+                  const knnd_params* p, int32_t on_device, void* stream,
+                  int32_t* out_idx, double* out_kl, knnd_round_stats* stats,
+                  int32_t* out_rounds);
+
+/*
+ * Step-by-step interface (the same path, one call per step).  A context owns
+ * its device buffers until knnd_ctx_destroy.  Pointers marked "kind" are host
+ * memory when on_device == 0 and device memory when on_device != 0.
+ */
+typedef struct knnd_ctx knnd_ctx;
+
+/* Validate and upload points, build the log table.  points: [n][d+1] of kind. */
+int knnd_ctx_create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed,
+                    const knnd_params* p, int32_t on_device, void* stream, knnd_ctx** out);
+
+/* Random K-out start (Section 3.2), sorted lists, FCR of round 0 into st. */
+int knnd_ctx_init_graph(knnd_ctx* c, knnd_round_stats* st);
+
+/* Replace the current lists by idx [n][K] int32 and kl [n][K] FP64 (kind).
+ * Rows must hold K distinct indices != x, sorted by (kl, index), with kl the
+ * canonical keys.  Every edge counts as new at the next round.  The round
+ * counter becomes `round`. */
+int knnd_ctx_set_graph(knnd_ctx* c, const int32_t* idx, const double* kl, int32_t round,
+                       int32_t on_device);
+
+/* One synchronous round (Sections 3.1, 4.2) and its FCR sample (Section 3.3).
+ * Fills st (host) and synchronises the context's stream. */
+int knnd_ctx_round(knnd_ctx* c, knnd_round_stats* st);
+
+/* Copy the current lists out: idx [n][K] int32, kl optional [n][K] FP64 (kind). */
+int knnd_ctx_get_graph(knnd_ctx* c, int32_t* idx, double* kl, int32_t on_device);
+
+/* Copy the log table out: L [n][d+1] FP64 (kind). */
+int knnd_ctx_get_log_table(knnd_ctx* c, double* L, int32_t on_device);
+
+/* Rounds completed so far. */
+int knnd_ctx_rounds(const knnd_ctx* c);
+
+int knnd_ctx_destroy(knnd_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNND_H */

@@ -1,0 +1,275 @@
+"""Python binding of libknnd.so: comparator-based K-nearest-neighbor descent
+with the Kullback-Leibler comparator on an AMD MI355X (gfx950).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Host inputs are numpy arrays; device inputs are torch tensors on the
+current HIP device (torch supplies memory and the stream).  The names mirror
+the C ABI in include/knnd.h.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libknnd.so")
+
+KNND_OK = 0
+KNND_WARN_MAX_ROUNDS = 1
+KNND_ERR_ARG = -1
+KNND_ERR_DOMAIN = -2
+KNND_ERR_NOMEM = -3
+KNND_ERR_DEVICE = -4
+KNND_ERR_UNSUPPORTED = -5
+
+KNND_F32, KNND_F64 = 0, 1
+KNND_PREC_FP64, KNND_PREC_MIXED_BF16, KNND_PREC_MIXED_FP16 = 0, 1, 2
+KNND_FLAG_NO_SKIP = 0x1
+
+EXPORTED = [
+    "knnd_default_params", "knnd_status_string", "knnd_abi_version", "knnd_build",
+    "knnd_build_ex", "knnd_ctx_create", "knnd_ctx_init_graph", "knnd_ctx_set_graph",
+    "knnd_ctx_round", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
+    "knnd_ctx_destroy",
+]
+
+
+class knnd_params(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("fcr_samples", ctypes.c_int64), ("max_rounds", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class knnd_round_stats(ctypes.Structure):
+    _fields_ = [("updates", ctypes.c_int64), ("fcr_hits", ctypes.c_int64),
+                ("evals_alg", ctypes.c_int64), ("evals_performed", ctypes.c_int64),
+                ("rescues", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("ms_join", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KnndError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    P = ctypes.POINTER
+    sig = {
+        "knnd_default_params": (None, [P(knnd_params)]),
+        "knnd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "knnd_abi_version": (ctypes.c_int, []),
+        "knnd_build": (ctypes.c_int, [vp, i64, i32, i32, u64, vp, vp, i32, vp]),
+        "knnd_build_ex": (ctypes.c_int, [vp, i64, i32, i32, u64, P(knnd_params), i32, vp, vp, vp,
+                                         P(knnd_round_stats), vp]),
+        "knnd_ctx_create": (ctypes.c_int, [vp, i64, i32, i32, u64, P(knnd_params), i32, vp,
+                                           P(vp)]),
+        "knnd_ctx_init_graph": (ctypes.c_int, [vp, P(knnd_round_stats)]),
+        "knnd_ctx_set_graph": (ctypes.c_int, [vp, vp, vp, i32, i32]),
+        "knnd_ctx_round": (ctypes.c_int, [vp, P(knnd_round_stats)]),
+        "knnd_ctx_get_graph": (ctypes.c_int, [vp, vp, vp, i32]),
+        "knnd_ctx_get_log_table": (ctypes.c_int, [vp, vp, i32]),
+        "knnd_ctx_rounds": (ctypes.c_int, [vp]),
+        "knnd_ctx_destroy": (ctypes.c_int, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def status_string(status):
+    return lib().knnd_status_string(status).decode()
+
+
+def default_params(**kw):
+    p = knnd_params()
+    lib().knnd_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _is_device(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.data_ptr() if _is_device(a) else a.ctypes.data
+
+
+def _stream_of(a, stream):
+    if stream is not None:
+        return stream
+    if _is_device(a):
+        import torch
+        return torch.cuda.current_stream(a.device).cuda_stream
+    return None
+
+
+def _dtype_code(points):
+    name = str(points.dtype)
+    if name.endswith("float32"):
+        return KNND_F32
+    if name.endswith("float64"):
+        return KNND_F64
+    raise TypeError("points must be float32 or float64")
+
+
+def _empty(like, shape, kind):
+    """Output buffer of numpy dtype `kind` on the same side as `like`."""
+    if _is_device(like):
+        import torch
+        tdt = {np.int32: torch.int32, np.float64: torch.float64}[kind]
+        return torch.empty(shape, dtype=tdt, device=like.device)
+    return np.empty(shape, dtype=kind)
+
+
+def _check_points(points, d):
+    if points.ndim != 2 or points.shape[1] != d + 1:
+        raise ValueError(f"points must have shape [n][{d + 1}]")
+    if _is_device(points):
+        if not points.is_contiguous():
+            raise ValueError("device points must be contiguous")
+        return points
+    return np.ascontiguousarray(points)
+
+
+def knnd_build(points, d, K, seed, max_rounds=100):
+    """Basic call: host FP32 points [n][d+1] -> (idx [n][K] int32, per-round
+    update counts, rounds)."""
+    points = np.ascontiguousarray(points, dtype=np.float32)
+    if points.ndim != 2 or points.shape[1] != d + 1:
+        raise ValueError(f"points must have shape [n][{d + 1}]")
+    n = points.shape[0]
+    idx = np.empty((n, K), dtype=np.int32)
+    upd = np.zeros(max(max_rounds, 1), dtype=np.int64)
+    rounds = ctypes.c_int32(0)
+    st = lib().knnd_build(points.ctypes.data, n, d, K, seed, idx.ctypes.data, upd.ctypes.data,
+                          max_rounds, ctypes.byref(rounds))
+    if st < 0:
+        raise KnndError(st, "knnd_build")
+    return idx, upd[:rounds.value].copy(), rounds.value, st
+
+
+def knnd_build_ex(points, d, K, seed, params=None, stream=None, with_kl=True):
+    """Extended call.  points: numpy array (host) or torch tensor on the GPU
+    (device); outputs are on the same side.  Returns a dict with status, idx,
+    kl, stats (one dict per round, entry 0 = start) and rounds."""
+    points = _check_points(points, d)
+    n = points.shape[0]
+    p = params if params is not None else default_params()
+    p.dtype = _dtype_code(points)
+    R = (p.max_rounds if p.max_rounds > 0 else 100) + 1
+    stats = (knnd_round_stats * R)()
+    idx = _empty(points, (n, K), np.int32)
+    kl = _empty(points, (n, K), np.float64) if with_kl else None
+    rounds = ctypes.c_int32(0)
+    dev = 1 if _is_device(points) else 0
+    st = lib().knnd_build_ex(_ptr(points), n, d, K, seed, ctypes.byref(p), dev,
+                             _stream_of(points, stream), _ptr(idx), _ptr(kl), stats,
+                             ctypes.byref(rounds))
+    if st < 0:
+        raise KnndError(st, "knnd_build_ex")
+    r = rounds.value
+    return {"status": st, "idx": idx, "kl": kl, "rounds": r,
+            "stats": [stats[i].as_dict() for i in range(r + 1)]}
+
+
+class Context:
+    """The step-by-step interface (knnd_ctx_*)."""
+
+    def __init__(self, points, d, K, seed, params=None, stream=None):
+        points = _check_points(points, d)
+        self.points = points
+        self.n, self.d, self.K = points.shape[0], d, K
+        self.device = _is_device(points)
+        p = params if params is not None else default_params()
+        p.dtype = _dtype_code(points)
+        self._stream = _stream_of(points, stream)
+        h = ctypes.c_void_p()
+        st = lib().knnd_ctx_create(_ptr(points), self.n, d, K, seed, ctypes.byref(p),
+                                   1 if self.device else 0, self._stream, ctypes.byref(h))
+        if st != KNND_OK:
+            raise KnndError(st, "knnd_ctx_create")
+        self.h = h
+
+    def init_graph(self):
+        s = knnd_round_stats()
+        st = lib().knnd_ctx_init_graph(self.h, ctypes.byref(s))
+        if st != KNND_OK:
+            raise KnndError(st, "knnd_ctx_init_graph")
+        return s.as_dict()
+
+    def set_graph(self, idx, kl, rnd=0):
+        if self.device:
+            st = lib().knnd_ctx_set_graph(self.h, _ptr(idx), _ptr(kl), rnd, 1)
+        else:
+            idx = np.ascontiguousarray(idx, dtype=np.int32)
+            kl = np.ascontiguousarray(kl, dtype=np.float64)
+            st = lib().knnd_ctx_set_graph(self.h, idx.ctypes.data, kl.ctypes.data, rnd, 0)
+        if st != KNND_OK:
+            raise KnndError(st, "knnd_ctx_set_graph")
+
+    def round(self):
+        s = knnd_round_stats()
+        st = lib().knnd_ctx_round(self.h, ctypes.byref(s))
+        if st != KNND_OK:
+            raise KnndError(st, "knnd_ctx_round")
+        return s.as_dict()
+
+    def get_graph(self, with_kl=True):
+        idx = _empty(self.points, (self.n, self.K), np.int32)
+        kl = _empty(self.points, (self.n, self.K), np.float64) if with_kl else None
+        st = lib().knnd_ctx_get_graph(self.h, _ptr(idx), _ptr(kl), 1 if self.device else 0)
+        if st != KNND_OK:
+            raise KnndError(st, "knnd_ctx_get_graph")
+        return idx, kl
+
+    def log_table(self):
+        L = _empty(self.points, (self.n, self.d + 1), np.float64)
+        st = lib().knnd_ctx_get_log_table(self.h, _ptr(L), 1 if self.device else 0)
+        if st != KNND_OK:
+            raise KnndError(st, "knnd_ctx_get_log_table")
+        return L
+
+    @property
+    def rounds(self):
+        return lib().knnd_ctx_rounds(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().knnd_ctx_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,349 @@
+// Host orchestrator and C ABI of libknnd.so (declared in include/knnd.h).
+//
+// A context owns the device copy of the points, the log table, a double-
+// buffered snapshot (lists and keys of round r-1 are read, round r written to
+// the other half), the reverse-neighbor CSR, receiver bins and the per-round
+// counters.  Each round enqueues every kernel on the caller's stream and
+// synchronises once, to read the counters the stop test needs (Section 3.3).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "knnd.h"
+#include "knnd_internal.h"
+
+struct knnd_ctx {
+  knnd::Ctx c;
+};
+
+namespace {
+
+using knnd::Ctx;
+
+int map_err(hipError_t e) { return e == hipErrorOutOfMemory ? KNND_ERR_NOMEM : KNND_ERR_DEVICE; }
+
+#define KNND_HIP(x)                                   \
+  do {                                                \
+    hipError_t e_ = (x);                              \
+    if (e_ != hipSuccess) return map_err(e_);         \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T) + 16);
+}
+
+void free_ctx(Ctx& c) {
+  void* bufs[] = {c.P,  c.L,      c.F[0],    c.F[1],   c.keys[0],     c.keys[1],    c.deg,   c.fill,
+                  c.rowptr, c.col, c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.dstats,
+                  c.dflag};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (c.hstats) (void)hipHostFree(c.hstats);
+  if (c.ev0) (void)hipEventDestroy(c.ev0);
+  if (c.ev1) (void)hipEventDestroy(c.ev1);
+  if (c.evj0) (void)hipEventDestroy(c.evj0);
+  if (c.evj1) (void)hipEventDestroy(c.evj1);
+  c = Ctx();
+}
+
+int64_t next_pow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+int resolve_params(const knnd_params* p, int64_t n, knnd_params* out) {
+  knnd_default_params(out);
+  if (p) *out = *p;
+  if (out->fcr_samples <= 0) out->fcr_samples = n < 10000 ? n : 10000;
+  if (out->max_rounds <= 0) out->max_rounds = 100;
+  if (out->dtype != KNND_F32 && out->dtype != KNND_F64) return KNND_ERR_ARG;
+  if (out->precision < KNND_PREC_FP64 || out->precision > KNND_PREC_MIXED_FP16) return KNND_ERR_ARG;
+  if (out->precision != KNND_PREC_FP64) return KNND_ERR_UNSUPPORTED;
+  return KNND_OK;
+}
+
+int check_shape(int64_t n, int32_t d, int32_t K) {
+  if (n < 2 || d < 1 || K < 2 || K > n - 1 || K > 64) return KNND_ERR_ARG;
+  if (n >= (int64_t)knnd::IDMASK_HOST) return KNND_ERR_ARG;
+  if (d > 1 << 20) return KNND_ERR_ARG;
+  return KNND_OK;
+}
+
+int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,
+           int32_t on_device, void* stream, Ctx& c) {
+  int st = check_shape(n, d, K);
+  if (st != KNND_OK) return st;
+  knnd_params prm;
+  st = resolve_params(p, n, &prm);
+  if (st != KNND_OK) return st;
+
+  KNND_HIP(hipGetDevice(&c.device));
+  hipDeviceProp_t prop;
+  KNND_HIP(hipGetDeviceProperties(&prop, c.device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return KNND_ERR_DEVICE;
+  c.num_cu = prop.multiProcessorCount;
+  c.stream = reinterpret_cast<hipStream_t>(stream);
+  c.n = n;
+  c.d = d;
+  c.D = d + 1;
+  c.Dp = (c.D + 1) & ~1;
+  c.K = K;
+  c.seed = seed;
+  c.dtype = prm.dtype;
+  c.precision = prm.precision;
+  c.flags = prm.flags;
+  c.M = prm.fcr_samples;
+  c.max_rounds = prm.max_rounds;
+
+  const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
+  const size_t nK = (size_t)n * K;
+  const int64_t ntiles = (n + 2047) / 2048;
+  c.gblocks = 32;
+  c.gstride = next_pow2(2 * n) < 1024 ? 1024 : next_pow2(2 * n);
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc(&c.P, (size_t)n * c.D * esz + 16);
+  if (e == hipSuccess) e = dalloc(&c.L, (size_t)n * c.Dp);
+  for (int b = 0; b < 2; ++b) {
+    if (e == hipSuccess) e = dalloc(&c.F[b], nK);
+    if (e == hipSuccess) e = dalloc(&c.keys[b], nK);
+  }
+  if (e == hipSuccess) e = dalloc(&c.deg, (size_t)n);
+  if (e == hipSuccess) e = dalloc(&c.fill, (size_t)n);
+  if (e == hipSuccess) e = dalloc(&c.rowptr, (size_t)n + 1);
+  if (e == hipSuccess) e = dalloc(&c.col, nK);
+  if (e == hipSuccess) e = dalloc(&c.tilesum, (size_t)ntiles + 1);
+  if (e == hipSuccess) e = dalloc(&c.class_count, (size_t)knnd::NCLASS);
+  if (e == hipSuccess) e = dalloc(&c.class_list, (size_t)knnd::NCLASS * n);
+  if (e == hipSuccess) e = dalloc(&c.gtab, (size_t)c.gblocks * c.gstride);
+  if (e == hipSuccess) e = dalloc(&c.gcand, (size_t)c.gblocks * (c.gstride / 2));
+  if (e == hipSuccess) e = dalloc(&c.dstats, (size_t)knnd::STAT_N);
+  if (e == hipSuccess) e = dalloc(&c.dflag, (size_t)4);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c.hstats), knnd::STAT_N * sizeof(int64_t));
+  if (e == hipSuccess) e = hipEventCreate(&c.ev0);
+  if (e == hipSuccess) e = hipEventCreate(&c.ev1);
+  if (e == hipSuccess) e = hipEventCreate(&c.evj0);
+  if (e == hipSuccess) e = hipEventCreate(&c.evj1);
+  if (e != hipSuccess) return map_err(e);
+
+  const size_t pbytes = (size_t)n * c.D * esz;
+  KNND_HIP(hipMemcpyAsync(c.P, points, pbytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          c.stream));
+  KNND_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int32_t), c.stream));
+  KNND_HIP(knnd::launch_log_table(c, c.dflag));
+  int32_t bad = 0;
+  KNND_HIP(hipMemcpyAsync(&bad, c.dflag, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+  KNND_HIP(hipStreamSynchronize(c.stream));
+  if (bad) return KNND_ERR_DOMAIN;
+  return KNND_OK;
+}
+
+int read_stats(Ctx& c, knnd_round_stats* st, bool joined) {
+  KNND_HIP(hipMemcpyAsync(c.hstats, c.dstats, knnd::STAT_N * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+  KNND_HIP(hipStreamSynchronize(c.stream));
+  float ms = 0.f, msj = 0.f;
+  KNND_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+  if (joined) KNND_HIP(hipEventElapsedTime(&msj, c.evj0, c.evj1));
+  if (st) {
+    st->updates = c.hstats[knnd::STAT_UPDATES];
+    st->fcr_hits = c.hstats[knnd::STAT_HITS];
+    st->evals_alg = c.hstats[knnd::STAT_EVALS];
+    st->evals_performed = c.hstats[knnd::STAT_PERF];
+    st->rescues = c.hstats[knnd::STAT_RESCUES];
+    st->ms = ms;
+    st->ms_join = msj;
+  }
+  return KNND_OK;
+}
+
+int init_graph(Ctx& c, knnd_round_stats* st) {
+  KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
+  KNND_HIP(hipEventRecord(c.ev0, c.stream));
+  KNND_HIP(knnd::launch_init_graph(c));
+  KNND_HIP(knnd::launch_fcr(c, c.F[c.cur], 0, c.dstats + knnd::STAT_HITS));
+  KNND_HIP(hipEventRecord(c.ev1, c.stream));
+  c.round = 0;
+  c.have_graph = true;
+  return read_stats(c, st, false);
+}
+
+int run_round(Ctx& c, knnd_round_stats* st) {
+  if (!c.have_graph) return KNND_ERR_ARG;
+  KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
+  KNND_HIP(hipEventRecord(c.ev0, c.stream));
+  KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
+  KNND_HIP(knnd::launch_bin(c));
+  KNND_HIP(hipEventRecord(c.evj0, c.stream));
+  KNND_HIP(knnd::launch_join(c, c.dstats));
+  KNND_HIP(hipEventRecord(c.evj1, c.stream));
+  KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], c.round + 1, c.dstats + knnd::STAT_HITS));
+  KNND_HIP(hipEventRecord(c.ev1, c.stream));
+  c.cur ^= 1;
+  c.round += 1;
+  return read_stats(c, st, true);
+}
+
+int get_graph(Ctx& c, int32_t* idx, double* kl, int32_t on_device) {
+  const size_t nK = (size_t)c.n * c.K;
+  if (on_device) {
+    KNND_HIP(knnd::launch_strip(c, c.F[c.cur], idx));
+    if (kl) KNND_HIP(hipMemcpyAsync(kl, c.keys[c.cur], nK * 8, hipMemcpyDeviceToDevice, c.stream));
+  } else {
+    // strip into the idle half of the double buffer, then copy out
+    int32_t* staging = reinterpret_cast<int32_t*>(c.F[c.cur ^ 1]);
+    KNND_HIP(knnd::launch_strip(c, c.F[c.cur], staging));
+    KNND_HIP(hipMemcpyAsync(idx, staging, nK * 4, hipMemcpyDeviceToHost, c.stream));
+    if (kl) KNND_HIP(hipMemcpyAsync(kl, c.keys[c.cur], nK * 8, hipMemcpyDeviceToHost, c.stream));
+  }
+  KNND_HIP(hipStreamSynchronize(c.stream));
+  return KNND_OK;
+}
+
+bool should_stop(int64_t hits_prev, int64_t hits, int64_t updates, int r, int max_rounds) {
+  return hits <= hits_prev || updates == 0 || r >= max_rounds;
+}
+
+}  // namespace
+
+extern "C" {
+
+void knnd_default_params(knnd_params* p) {
+  if (!p) return;
+  p->precision = KNND_PREC_FP64;
+  p->dtype = KNND_F32;
+  p->fcr_samples = 0;
+  p->max_rounds = 100;
+  p->flags = 0;
+}
+
+const char* knnd_status_string(int s) {
+  switch (s) {
+    case KNND_OK: return "KNND_OK";
+    case KNND_WARN_MAX_ROUNDS: return "KNND_WARN_MAX_ROUNDS";
+    case KNND_ERR_ARG: return "KNND_ERR_ARG";
+    case KNND_ERR_DOMAIN: return "KNND_ERR_DOMAIN";
+    case KNND_ERR_NOMEM: return "KNND_ERR_NOMEM";
+    case KNND_ERR_DEVICE: return "KNND_ERR_DEVICE";
+    case KNND_ERR_UNSUPPORTED: return "KNND_ERR_UNSUPPORTED";
+    default: return "KNND_UNKNOWN_STATUS";
+  }
+}
+
+int knnd_abi_version(void) { return KNND_ABI_VERSION; }
+
+int knnd_ctx_create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,
+                    int32_t on_device, void* stream, knnd_ctx** out) {
+  if (!points || !out) return KNND_ERR_ARG;
+  *out = nullptr;
+  knnd_ctx* h = new (std::nothrow) knnd_ctx();
+  if (!h) return KNND_ERR_NOMEM;
+  const int st = create(points, n, d, K, seed, p, on_device, stream, h->c);
+  if (st != KNND_OK) {
+    free_ctx(h->c);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return KNND_OK;
+}
+
+int knnd_ctx_init_graph(knnd_ctx* h, knnd_round_stats* st) {
+  if (!h) return KNND_ERR_ARG;
+  return init_graph(h->c, st);
+}
+
+int knnd_ctx_set_graph(knnd_ctx* h, const int32_t* idx, const double* kl, int32_t round, int32_t on_device) {
+  if (!h || !idx || !kl || round < 0) return KNND_ERR_ARG;
+  Ctx& c = h->c;
+  const size_t nK = (size_t)c.n * c.K;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  int32_t* staging = reinterpret_cast<int32_t*>(c.F[c.cur ^ 1]);
+  KNND_HIP(hipMemcpyAsync(staging, idx, nK * 4, kind, c.stream));
+  KNND_HIP(knnd::launch_load_idx(c, staging, c.F[c.cur]));
+  KNND_HIP(hipMemcpyAsync(c.keys[c.cur], kl, nK * 8, kind, c.stream));
+  KNND_HIP(hipStreamSynchronize(c.stream));
+  c.round = round;
+  c.have_graph = true;
+  return KNND_OK;
+}
+
+int knnd_ctx_round(knnd_ctx* h, knnd_round_stats* st) {
+  if (!h) return KNND_ERR_ARG;
+  return run_round(h->c, st);
+}
+
+int knnd_ctx_get_graph(knnd_ctx* h, int32_t* idx, double* kl, int32_t on_device) {
+  if (!h || !idx || !h->c.have_graph) return KNND_ERR_ARG;
+  return get_graph(h->c, idx, kl, on_device);
+}
+
+int knnd_ctx_get_log_table(knnd_ctx* h, double* L, int32_t on_device) {
+  if (!h || !L) return KNND_ERR_ARG;
+  Ctx& c = h->c;
+  KNND_HIP(hipMemcpy2DAsync(L, (size_t)c.D * 8, c.L, (size_t)c.Dp * 8, (size_t)c.D * 8, (size_t)c.n,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c.stream));
+  KNND_HIP(hipStreamSynchronize(c.stream));
+  return KNND_OK;
+}
+
+int knnd_ctx_rounds(const knnd_ctx* h) { return h ? h->c.round : -1; }
+
+int knnd_ctx_destroy(knnd_ctx* h) {
+  if (!h) return KNND_ERR_ARG;
+  (void)hipStreamSynchronize(h->c.stream);
+  free_ctx(h->c);
+  delete h;
+  return KNND_OK;
+}
+
+int knnd_build_ex(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,
+                  int32_t on_device, void* stream, int32_t* out_idx, double* out_kl, knnd_round_stats* stats,
+                  int32_t* out_rounds) {
+  if (!points || !out_idx || !out_rounds) return KNND_ERR_ARG;
+  knnd_ctx* h = nullptr;
+  int st = knnd_ctx_create(points, n, d, K, seed, p, on_device, stream, &h);
+  if (st != KNND_OK) return st;
+  Ctx& c = h->c;
+  knnd_round_stats rs;
+  st = init_graph(c, &rs);
+  if (st == KNND_OK) {
+    if (stats) stats[0] = rs;
+    int64_t hits_prev = rs.fcr_hits;
+    for (;;) {
+      st = run_round(c, &rs);
+      if (st != KNND_OK) break;
+      if (stats) stats[c.round] = rs;
+      if (should_stop(hits_prev, rs.fcr_hits, rs.updates, c.round, c.max_rounds)) {
+        if (c.round >= c.max_rounds && rs.fcr_hits > hits_prev && rs.updates != 0) st = KNND_WARN_MAX_ROUNDS;
+        break;
+      }
+      hits_prev = rs.fcr_hits;
+    }
+  }
+  if (st == KNND_OK || st == KNND_WARN_MAX_ROUNDS) {
+    const int gst = get_graph(c, out_idx, out_kl, on_device);
+    if (gst != KNND_OK) st = gst;
+    *out_rounds = c.round;
+  }
+  knnd_ctx_destroy(h);
+  return st;
+}
+
+int knnd_build(const float* points, int64_t n, int32_t d, int32_t K, uint64_t seed, int32_t* out_idx,
+               int64_t* out_updates, int32_t max_rounds, int32_t* out_rounds) {
+  if (!points || !out_idx || !out_updates || !out_rounds || max_rounds < 1) return KNND_ERR_ARG;
+  knnd_params p;
+  knnd_default_params(&p);
+  p.max_rounds = max_rounds;
+  knnd_round_stats* stats = new (std::nothrow) knnd_round_stats[(size_t)max_rounds + 1];
+  if (!stats) return KNND_ERR_NOMEM;
+  const int st = knnd_build_ex(points, n, d, K, seed, &p, 0, nullptr, out_idx, nullptr, stats, out_rounds);
+  if (st == KNND_OK || st == KNND_WARN_MAX_ROUNDS)
+    for (int r = 1; r <= *out_rounds; ++r) out_updates[r - 1] = stats[r].updates;
+  delete[] stats;
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+// Device-side building blocks for gfx950 (wave64): counter-based hashing, the
+// correctly rounded FP64 log, the canonical KL key, order-preserving key bits
+// and wave-level bitonic sort/merge of (key, index) pairs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knnd {
+
+constexpr int WAVE = 64;
+constexpr uint32_t IDMASK = 0x3FFFFFFFu;   // point index (n < 2^30)
+constexpr uint32_t EXCLBIT = 0x40000000u;  // hash-table entry: x itself or a current friend
+constexpr uint32_t NEWBIT = 0x80000000u;   // list entry / edge that is new this round
+constexpr uint32_t EMPTY = 0xFFFFFFFFu;    // free hash-table slot
+constexpr uint64_t KEY_SENTINEL = ~0ull;   // sorts after every finite key
+
+// ---------------------------------------------------------------------------
+// Counter-based randomness: SplitMix64 finalizer (Steele, Lea & Flood 2014;
+// Stafford's variant-13 constants) chained over (seed, tag, a, b).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t hash4(uint64_t s, uint64_t t, uint64_t a, uint64_t b) {
+  return mix64(mix64(mix64(s ^ (t * 0x9E3779B97F4A7C15ull)) ^ a) ^ b);
+}
+
+// floor(h * m / 2^64)
+__device__ __forceinline__ uint64_t bound(uint64_t h, uint64_t m) { return __umul64hi(h, m); }
+
+// ---------------------------------------------------------------------------
+// Correctly rounded natural log in FP64.
+// x = 2^e * m with m in [sqrt(2)/2, sqrt(2)]; log m = 2 atanh(s),
+// s = (m-1)/(m+1), |s| <= 0.1716, and 2 atanh(s) = 2 s sum_k s^(2k)/(2k+1).
+// Everything after the exact reduction runs in double-double (about 104
+// significant bits), so the final rounding to FP64 is the correct one unless
+// log x lies within ~2^-100 (relative) of a rounding boundary.
+// ---------------------------------------------------------------------------
+struct dd {
+  double h, l;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ __forceinline__ dd quick_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.h, b.h);
+  dd t = two_sum(a.l, b.l);
+  double e = s.l + t.h;
+  s = quick_two_sum(s.h, e);
+  return quick_two_sum(s.h, s.l + t.l);
+}
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.h, b.h);
+  double e = p.l + (a.h * b.l + a.l * b.h);
+  return quick_two_sum(p.h, e);
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double b) {
+  dd p = two_prod(a.h, b);
+  return quick_two_sum(p.h, p.l + a.l * b);
+}
+
+__device__ inline double crlog(double x) {
+  // x is finite and > 0 (validated by the caller).
+  int e = 0;
+  if (x < 0x1p-1022) {  // subnormal: scale into the normal range first
+    x *= 0x1p54;
+    e = -54;
+  }
+  uint64_t b = (uint64_t)__double_as_longlong(x);
+  e += (int)((b >> 52) & 0x7ff) - 1023;
+  double m = __longlong_as_double((long long)((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+  if (m > 0x1.6a09e667f3bcdp+0) {  // sqrt(2)
+    m *= 0.5;
+    e += 1;
+  }
+  const double f = m - 1.0;       // exact (Sterbenz)
+  const dd den = two_sum(m, 1.0);  // m + 1 exactly
+  // s = f / (m+1) in double-double
+  const double q1 = f / den.h;
+  const dd p = dd_mul_d(den, q1);
+  const dd r = dd_add(dd{f, 0.0}, dd{-p.h, -p.l});
+  const double q2 = r.h / den.h;
+  const dd s = quick_two_sum(q1, q2);
+  const dd w = dd_mul(s, s);
+  // Horner on sum_{k=0}^{22} w^k / (2k+1); w <= 0.0295, so the first omitted
+  // term is below 2^-114 of the sum.
+  const int N = 22;
+  dd acc;
+  {
+    const double c = 2.0 * N + 1.0;
+    const double hi = 1.0 / c;
+    acc = {hi, fma(-hi, c, 1.0) / c};
+  }
+  for (int k = N - 1; k >= 0; --k) {
+    const double c = 2.0 * k + 1.0;
+    const double hi = 1.0 / c;
+    const dd ck = {hi, fma(-hi, c, 1.0) / c};
+    acc = dd_add(dd_mul(acc, w), ck);
+  }
+  dd y = dd_mul(s, acc);
+  y.h *= 2.0;
+  y.l *= 2.0;
+  // ln 2 as the nearest double plus the nearest double to the remainder
+  const dd ln2 = {0x1.62e42fefa39efp-1, 0x1.abc9e3b39803fp-56};
+  const dd E = dd_mul_d(ln2, (double)e);
+  const dd t = dd_add(E, y);
+  return t.h + t.l;
+}
+
+// ---------------------------------------------------------------------------
+// Canonical key: acc = fma(x_i, Lx_i - Lz_i, acc), i ascending, from +0.0.
+// Adding +0.0 at the end turns a -0.0 into +0.0 so that the bit order below
+// agrees with FP64 comparison.
+// ---------------------------------------------------------------------------
+template <typename PT>
+__device__ __forceinline__ double canonical_key(const PT* __restrict__ px,
+                                                const double* __restrict__ lx,
+                                                const double* __restrict__ lz, int D) {
+  double acc = 0.0;
+  int i = 0;
+  const double2* lz2 = reinterpret_cast<const double2*>(lz);
+  for (; i + 1 < D; i += 2) {
+    const double2 v = lz2[i >> 1];
+    acc = fma((double)px[i], lx[i] - v.x, acc);
+    acc = fma((double)px[i + 1], lx[i + 1] - v.y, acc);
+  }
+  if (i < D) acc = fma((double)px[i], lx[i] - lz[i], acc);
+  return acc + 0.0;
+}
+
+// Order-preserving map FP64 -> uint64 (for non-NaN values, with -0 == +0
+// already canonicalised): a < b  <=>  key_bits(a) < key_bits(b).
+__device__ __forceinline__ uint64_t key_bits(double k) {
+  const uint64_t u = (uint64_t)__double_as_longlong(k);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double bits_key(uint64_t u) {
+  return __longlong_as_double((long long)((u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u));
+}
+
+// (key, index) order; flag bits above IDMASK are ignored.
+__device__ __forceinline__ bool ke_less(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
+  return ka < kb || (ka == kb && (ia & IDMASK) < (ib & IDMASK));
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level primitives (64 lanes).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, WAVE);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) {
+  return (uint32_t)__shfl((int)v, src, WAVE);
+}
+__device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t v, int m) {
+  return (uint32_t)__shfl_xor((int)v, m, WAVE);
+}
+
+// One compare-exchange step between lane and lane^stride; `keep_min` says
+// whether this lane keeps the smaller element.
+__device__ __forceinline__ void cx_step(uint64_t& k, uint32_t& id, int stride, bool keep_min) {
+  const uint64_t pk = shfl_xor_u64(k, stride);
+  const uint32_t pid = shfl_xor_u32(id, stride);
+  const bool take = keep_min ? ke_less(pk, pid, k, id) : ke_less(k, id, pk, pid);
+  if (take) {
+    k = pk;
+    id = pid;
+  }
+}
+
+// Ascending bitonic sort of one (key, id) per lane across the wave.
+__device__ __forceinline__ void wave_sort(uint64_t& k, uint32_t& id) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int size = 2; size <= WAVE; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const bool asc = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      cx_step(k, id, stride, lower == asc);
+    }
+  }
+}
+
+// a (ascending across lanes) <- the 64 smallest of a and b (b ascending).
+__device__ __forceinline__ void wave_merge(uint64_t& ak, uint32_t& aid, uint64_t bk, uint32_t bid) {
+  const int lane = lane_id();
+  const uint64_t rk = shfl_u64(bk, WAVE - 1 - lane);
+  const uint32_t rid = shfl_u32(bid, WAVE - 1 - lane);
+  if (ke_less(rk, rid, ak, aid)) {
+    ak = rk;
+    aid = rid;
+  }
+#pragma unroll
+  for (int stride = WAVE / 2; stride > 0; stride >>= 1) cx_step(ak, aid, stride, (lane & stride) == 0);
+}
+
+}  // namespace knnd

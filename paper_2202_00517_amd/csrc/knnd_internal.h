@@ -1,0 +1,86 @@
+// Internal interface between the host orchestrator and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace knnd {
+
+// Receiver classes by hash-table capacity: 512 << k slots for k = 0..5 in LDS,
+// class 6 in global memory for very large co-friend lists.
+constexpr int NCLASS = 7;
+constexpr uint32_t IDMASK_HOST = 0x3FFFFFFFu;  // point indices are below this
+constexpr uint32_t CLASS_CAP_MIN = 512;
+
+// Per-round device counters
+enum { STAT_UPDATES = 0, STAT_HITS = 1, STAT_EVALS = 2, STAT_PERF = 3, STAT_RESCUES = 4, STAT_N = 8 };
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  int64_t n = 0;
+  int d = 0, D = 0, Dp = 0, K = 0;
+  uint64_t seed = 0;
+  int dtype = 0;      // 0 F32, 1 F64
+  int precision = 0;
+  int flags = 0;
+  int64_t M = 0;
+  int max_rounds = 100;
+  int round = 0;      // rounds completed
+  bool have_graph = false;
+
+  // device buffers
+  void* P = nullptr;          // [n][D] points (copy owned by the context)
+  double* L = nullptr;        // [n][Dp]
+  uint32_t* F[2] = {nullptr, nullptr};
+  double* keys[2] = {nullptr, nullptr};
+  int cur = 0;                // F[cur], keys[cur] hold the current snapshot
+  int32_t* deg = nullptr;     // [n]
+  int32_t* fill = nullptr;    // [n]
+  int64_t* rowptr = nullptr;  // [n+1]
+  uint32_t* col = nullptr;    // [nK]
+  int64_t* tilesum = nullptr;
+  int32_t* class_count = nullptr;  // [NCLASS]
+  int32_t* class_list = nullptr;   // [NCLASS][n]
+  uint32_t* gtab = nullptr;        // [gblocks][gstride]
+  uint32_t* gcand = nullptr;       // [gblocks][gstride/2]
+  int64_t gstride = 0;
+  int gblocks = 0;
+  int64_t* dstats = nullptr;  // [STAT_N] device
+  int64_t* hstats = nullptr;  // [STAT_N] pinned host
+  int32_t* dflag = nullptr;   // device scratch flag
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evj0 = nullptr, evj1 = nullptr;
+};
+
+struct JoinArgs {
+  const void* P;
+  const double* L;
+  int64_t n;
+  int D, Dp, K;
+  const uint32_t* F;
+  const double* keys;
+  const int64_t* rowptr;
+  const uint32_t* col;
+  uint32_t* Fn;
+  double* keysn;
+  int64_t* stats;
+  int skip;
+  uint32_t* gtab;
+  uint32_t* gcand;
+  int64_t gstride;
+};
+
+hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
+hipError_t launch_log_table(const Ctx& c, int32_t* bad);
+hipError_t launch_init_graph(const Ctx& c);
+hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits);
+hipError_t launch_csr(const Ctx& c, const uint32_t* F);
+hipError_t launch_bin(const Ctx& c);
+hipError_t launch_join(const Ctx& c, int64_t* stats);
+hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out);
+hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F);
+
+}  // namespace knnd

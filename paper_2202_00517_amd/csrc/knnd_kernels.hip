@@ -1,0 +1,564 @@
+// gfx950 kernels for one round of comparator-based K-NN descent with the
+// Kullback-Leibler comparator (Baron & Darling, arXiv 2202.00517).
+//
+// Data layout in HBM (all row-major):
+//   P     [n][D]   points as given (FP32 or FP64), D = d+1
+//   L     [n][Dp]  FP64 correctly rounded log of P, Dp = D rounded up to even
+//                  (16-byte aligned rows for dwordx4 gathers), pad = 0
+//   F     [n][K]   uint32: point index | NEWBIT when the edge is new this round
+//   keys  [n][K]   FP64 canonical keys of F, ascending per row
+//   rowptr[n+1]    int64, col[nK] uint32: co-friend (reverse) lists; col holds
+//                  the source index | NEWBIT of that edge
+#include "knnd_device.h"
+#include "knnd_internal.h"
+
+namespace knnd {
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+__global__ void k_zero_i64(int64_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+// out = F without flag bits
+__global__ void k_strip(const uint32_t* __restrict__ F, int64_t cnt, int32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int32_t)(F[i] & IDMASK);
+}
+// F = idx | NEWBIT (an externally supplied snapshot: every edge counts as new)
+__global__ void k_load_idx(const int32_t* __restrict__ idx, int64_t cnt, uint32_t* __restrict__ F) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    F[i] = ((uint32_t)idx[i] & IDMASK) | NEWBIT;
+}
+
+// ---------------------------------------------------------------------------
+// a0: log table (and domain check of every coordinate)
+// ---------------------------------------------------------------------------
+template <typename PT>
+__global__ void k_log_table(const PT* __restrict__ P, int64_t n, int D, int Dp, double* __restrict__ L,
+                            int32_t* __restrict__ bad) {
+  const int64_t total = n * Dp;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / Dp;
+    const int i = (int)(t - j * Dp);
+    double out = 0.0;
+    if (i < D) {
+      const double v = (double)P[j * D + i];
+      if (!(v > 0.0) || isinf(v)) {
+        atomicOr(bad, 1);
+      } else {
+        out = crlog(v);
+      }
+    }
+    L[t] = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a0: random K-out start, one wave per point (Section 3.2).  Draw a of x is
+// y = r + (r >= x), r = bound(H(seed,1,x,a), n-1); the first K distinct draws
+// are kept, 64 draws at a time (one per lane), then sorted by (key, index).
+// ---------------------------------------------------------------------------
+template <typename PT>
+__global__ __launch_bounds__(256) void k_init_graph(const PT* __restrict__ P, const double* __restrict__ L,
+                                                    int64_t n, int D, int Dp, int K, uint64_t seed,
+                                                    uint32_t* __restrict__ F, double* __restrict__ keys) {
+  __shared__ uint32_t slot[4][WAVE];
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int64_t x = (int64_t)blockIdx.x * 4 + wave;
+  if (x >= n) return;  // whole wave; no block-level barrier follows
+  uint32_t mine = IDMASK;
+  int count = 0;
+  for (uint64_t a0 = 0; count < K; a0 += WAVE) {
+    const uint64_t r = bound(hash4(seed, 1, (uint64_t)x, a0 + lane), (uint64_t)(n - 1));
+    const uint32_t y = (uint32_t)(r + (r >= (uint64_t)x ? 1 : 0));
+    bool dup = false;
+    for (int j = 0; j < count; ++j) dup |= (shfl_u32(mine, j) == y);
+    for (int l = 0; l < WAVE - 1; ++l) {
+      const uint32_t yl = shfl_u32(y, l);
+      dup |= (l < lane) && (yl == y);
+    }
+    const uint64_t ok = __ballot(!dup);
+    const int pos = count + (int)rank_in(ok);
+    if (!dup && pos < K) slot[wave][pos] = y;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nc = min(K, count + (int)__popcll(ok));
+    if (lane >= count && lane < nc) mine = slot[wave][lane];
+    count = nc;
+  }
+  uint64_t kb = KEY_SENTINEL;
+  uint32_t id = IDMASK;
+  if (lane < K) {
+    kb = key_bits(canonical_key(P + x * D, L + x * Dp, L + (int64_t)mine * Dp, D));
+    id = mine;
+  }
+  wave_sort(kb, id);
+  if (lane < K) {
+    F[x * K + lane] = id | NEWBIT;
+    keys[x * K + lane] = bits_key(kb);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a6: friend clustering rate sample (Section 3.3), one thread per sample.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fcr(const uint32_t* __restrict__ F, int64_t n, int K, uint64_t seed,
+                                             int64_t round, int64_t M, int64_t* __restrict__ hits) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  bool hit = false;
+  if (s < M) {
+    const int64_t x = (int64_t)bound(hash4(seed, 2, (uint64_t)round, (uint64_t)s), (uint64_t)n);
+    const int av = (int)bound(hash4(seed, 3, (uint64_t)round, (uint64_t)s), (uint64_t)K);
+    const int bp = (int)bound(hash4(seed, 4, (uint64_t)round, (uint64_t)s), (uint64_t)(K - 1));
+    const int bv = bp + (bp >= av ? 1 : 0);
+    const uint32_t y = F[x * K + av] & IDMASK;
+    const uint32_t z = F[x * K + bv] & IDMASK;
+    for (int j = 0; j < K; ++j)
+      hit |= ((F[(int64_t)z * K + j] & IDMASK) == y) || ((F[(int64_t)y * K + j] & IDMASK) == z);
+  }
+  const uint64_t m = __ballot(hit);
+  if (lane_id() == 0 && m) atomicAdd((unsigned long long*)hits, (unsigned long long)__popcll(m));
+}
+
+// ---------------------------------------------------------------------------
+// a1: reverse neighbors by counting sort: in-degree histogram, exclusive scan,
+// scatter.  The order inside a co-friend list is arbitrary (the round's result
+// does not depend on it).
+// ---------------------------------------------------------------------------
+__global__ void k_degree(const uint32_t* __restrict__ F, int64_t nK, int32_t* __restrict__ deg) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&deg[F[e] & IDMASK], 1);
+}
+
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = 256 * SCAN_ITEMS;
+
+// Block-wide exclusive scan of one int64 per thread (256 threads).
+__device__ __forceinline__ int64_t block_exscan(int64_t v, int64_t* sh /*[4]*/, int64_t& total) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int64_t incl = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int64_t t = (int64_t)shfl_u64((uint64_t)incl, max(lane - o, 0));
+    if (lane >= o) incl += t;
+  }
+  if (lane == WAVE - 1) sh[wave] = incl;
+  __syncthreads();
+  int64_t off = 0;
+  for (int w = 0; w < wave; ++w) off += sh[w];
+  total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return off + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t* __restrict__ deg, int64_t n,
+                                                    int64_t* __restrict__ rowptr, int64_t* __restrict__ tilesum) {
+  __shared__ int64_t sh[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  int32_t v[SCAN_ITEMS];
+  int64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = (base + k < n) ? deg[base + k] : 0;
+    sum += v[k];
+  }
+  int64_t total;
+  int64_t run = block_exscan(sum, sh, total);
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < n) rowptr[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) tilesum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the tile sums in place (one block), total into rowptr[n].
+__global__ __launch_bounds__(256) void k_scan_top(int64_t* __restrict__ tilesum, int64_t ntiles,
+                                                  int64_t* __restrict__ rowptr, int64_t n) {
+  __shared__ int64_t sh[4];
+  int64_t carry = 0;
+  for (int64_t b = 0; b < ntiles; b += 256) {
+    const int64_t i = b + threadIdx.x;
+    const int64_t v = i < ntiles ? tilesum[i] : 0;
+    int64_t total;
+    const int64_t ex = block_exscan(v, sh, total);
+    if (i < ntiles) tilesum[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) rowptr[n] = carry;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ rowptr, int64_t n, const int64_t* __restrict__ tilesum) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    rowptr[i] += tilesum[i / SCAN_TILE];
+}
+
+__global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, const int64_t* __restrict__ rowptr,
+                          int32_t* __restrict__ fill, uint32_t* __restrict__ col) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t raw = F[e];
+    const uint32_t v = raw & IDMASK;
+    const int64_t pos = rowptr[v] + atomicAdd(&fill[v], 1);
+    col[pos] = (uint32_t)(e / K) | (raw & NEWBIT);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Receiver binning by hash-table size.  A receiver with c co-friends has at
+// most T = c + K*K + c*K candidate occurrences; its table must hold the
+// distinct candidates plus x and its K friends at load <= 1/2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t table_need(int64_t c, int K, int64_t n) {
+  const int64_t T = c + (int64_t)K * K + c * K;
+  return min(T, n - 1 - K) + K + 1;
+}
+
+__global__ void k_bin(const int64_t* __restrict__ rowptr, int64_t n, int K, int32_t* __restrict__ counts,
+                      int32_t* __restrict__ lists) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t need2 = 2 * table_need(rowptr[x + 1] - rowptr[x], K, n);
+    int cls = NCLASS - 1;
+    for (int k = 0; k < NCLASS - 1; ++k)
+      if (need2 <= (int64_t)(CLASS_CAP_MIN << k)) {
+        cls = k;
+        break;
+      }
+    const int pos = atomicAdd(&counts[cls], 1);
+    lists[(int64_t)cls * n + pos] = (int32_t)x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2..a5: the local join, pull form, one 256-thread block per receiver x.
+//  B  insert x and F(x) into the block's hash set, marked excluded
+//  C  enumerate every candidate occurrence (co-friends, friends of friends,
+//     friends of co-friends) and insert it; a first insertion is one
+//     algorithmic evaluation; an occurrence through a new edge marks NEW
+//  D1 compact the non-excluded entries marked NEW
+//  D2 each wave computes canonical keys for 64 candidates at a time, drops
+//     those that cannot beat the current K-th (the paper's compare-to-last,
+//     Section 4.2) and merges the rest into its sorted list in registers
+//  E  wave 0 merges the four lists and writes the first K
+// A candidate reached only through edges already present one round earlier
+// cannot enter (it was considered then and lost to K entries that are still
+// at least as good), so it is counted but not evaluated.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int tab_insert(uint32_t* tab, uint32_t mask, uint32_t z, uint32_t flag) {
+  uint32_t h = z * 0x9E3779B1u;
+  h = (h ^ (h >> 15)) & mask;
+  for (;;) {
+    const uint32_t old = atomicCAS(&tab[h], EMPTY, z | flag);
+    if (old == EMPTY) return 1;
+    if ((old & IDMASK) == z) {
+      if ((flag & NEWBIT) && !(old & NEWBIT)) atomicOr(&tab[h], NEWBIT);
+      return 0;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* sh /*[4]*/) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += (int64_t)shfl_xor_u64((uint64_t)v, o);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const int64_t t = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return t;
+}
+
+template <int CAP, typename PT>
+__global__ __launch_bounds__(256) void k_join(JoinArgs a, const int32_t* __restrict__ list,
+                                              const int32_t* __restrict__ count) {
+  constexpr bool GLOB = (CAP == 0);
+  __shared__ uint32_t s_tab[GLOB ? 1 : CAP];
+  __shared__ uint32_t s_cand[GLOB ? 1 : CAP / 2];
+  __shared__ uint32_t s_fx[WAVE];
+  __shared__ uint64_t s_lk[3][WAVE];
+  __shared__ uint32_t s_li[3][WAVE];
+  __shared__ uint64_t s_tau;
+  __shared__ int s_ncand;
+  __shared__ int64_t s_red[4];
+
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = tid >> 6;
+  const int K = a.K;
+  const int D = a.D, Dp = a.Dp;
+  const int64_t n = a.n;
+  uint32_t* tab = GLOB ? a.gtab + (int64_t)blockIdx.x * a.gstride : s_tab;
+  uint32_t* cand = GLOB ? a.gcand + (int64_t)blockIdx.x * (a.gstride / 2) : s_cand;
+  const PT* P = reinterpret_cast<const PT*>(a.P);
+  const int nitems = *count;
+  int64_t my_evals = 0, my_perf = 0, my_upd = 0;
+
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int64_t x = list[item];
+    const int64_t rp = a.rowptr[x];
+    const int64_t c = a.rowptr[x + 1] - rp;
+    const int64_t KK = (int64_t)K * K;
+    const int64_t T = c + KK + c * K;
+    uint32_t cap = (uint32_t)CAP;
+    if (GLOB) {
+      const int64_t need2 = 2 * table_need(c, K, n);
+      cap = CLASS_CAP_MIN;
+      while ((int64_t)cap < need2) cap <<= 1;
+    }
+    const uint32_t mask = cap - 1;
+
+    // A: clear
+    for (uint32_t s = tid; s < cap; s += 256) tab[s] = EMPTY;
+    if (tid == 0) {
+      s_ncand = 0;
+      s_tau = key_bits(a.keys[x * K + K - 1]);
+    }
+    __syncthreads();
+    // B: excluded entries
+    if (tid < K) {
+      const uint32_t raw = a.F[x * K + tid];
+      s_fx[tid] = raw;
+      tab_insert(tab, mask, raw & IDMASK, EXCLBIT);
+    } else if (tid == K) {
+      tab_insert(tab, mask, (uint32_t)x, EXCLBIT);
+    }
+    __syncthreads();
+    // C: enumerate candidate occurrences
+    for (int64_t t = tid; t < T; t += 256) {
+      uint32_t z, nw;
+      if (t < c) {
+        const uint32_t w = a.col[rp + t];
+        z = w & IDMASK;
+        nw = w & NEWBIT;
+      } else if (t < c + KK) {
+        const int u = (int)(t - c);
+        const int j = u / K;
+        const int s = u - j * K;
+        const uint32_t v = s_fx[j];
+        const uint32_t zr = a.F[(int64_t)(v & IDMASK) * K + s];
+        z = zr & IDMASK;
+        nw = (v | zr) & NEWBIT;
+      } else {
+        const int64_t u = t - c - KK;
+        const int64_t q = u / K;
+        const int s = (int)(u - q * K);
+        const uint32_t w = a.col[rp + q];
+        const uint32_t zr = a.F[(int64_t)(w & IDMASK) * K + s];
+        z = zr & IDMASK;
+        nw = (w | zr) & NEWBIT;
+      }
+      if (!a.skip) nw = NEWBIT;
+      my_evals += tab_insert(tab, mask, z, nw);
+    }
+    __syncthreads();
+    // D1: compact candidates to evaluate
+    for (uint32_t s = tid; s < cap; s += 256) {
+      const uint32_t e = tab[s];
+      const bool el = (e != EMPTY) && !(e & EXCLBIT) && (e & NEWBIT);
+      const uint64_t m = __ballot(el);
+      int base = 0;
+      if (lane == 0 && m) base = atomicAdd(&s_ncand, (int)__popcll(m));
+      base = __shfl(base, 0, WAVE);
+      if (el) cand[base + (int)rank_in(m)] = e & IDMASK;
+    }
+    __syncthreads();
+    // D2: keys, compare-to-last filter, wave merges
+    const int ncand = s_ncand;
+    uint64_t lk = KEY_SENTINEL;
+    uint32_t li = IDMASK;
+    if (wave == 0 && lane < K) {
+      lk = key_bits(a.keys[x * K + lane]);
+      li = s_fx[lane] & IDMASK;
+    }
+    const PT* px = P + x * D;
+    const double* lx = a.L + x * Dp;
+    for (int i0 = wave * WAVE; i0 < ncand; i0 += 256) {
+      const int i = i0 + lane;
+      const bool valid = i < ncand;
+      uint64_t kb = KEY_SENTINEL;
+      uint32_t z = IDMASK;
+      if (valid) {
+        z = cand[i];
+        kb = key_bits(canonical_key(px, lx, a.L + (int64_t)z * Dp, D));
+      }
+      my_perf += valid ? 1 : 0;
+      const uint64_t kk = shfl_u64(lk, K - 1);
+      const uint32_t ki = shfl_u32(li, K - 1);
+      const uint64_t tau = *(volatile uint64_t*)&s_tau;
+      const bool surv = valid && kb <= tau && ke_less(kb, z, kk, ki);
+      if (__ballot(surv)) {
+        uint64_t bk = surv ? kb : KEY_SENTINEL;
+        uint32_t bi = surv ? (z | NEWBIT) : IDMASK;
+        wave_sort(bk, bi);
+        wave_merge(lk, li, bk, bi);
+        const uint64_t nk = shfl_u64(lk, K - 1);
+        if (lane == 0 && nk < tau) atomicMin((unsigned long long*)&s_tau, (unsigned long long)nk);
+      }
+    }
+    // E: combine the four wave lists
+    if (wave > 0) {
+      s_lk[wave - 1][lane] = lk;
+      s_li[wave - 1][lane] = li;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int w = 0; w < 3; ++w) wave_merge(lk, li, s_lk[w][lane], s_li[w][lane]);
+      if (lane < K) {
+        a.Fn[x * K + lane] = li;
+        a.keysn[x * K + lane] = bits_key(lk);
+      }
+      const uint64_t um = __ballot(lane < K && (li & NEWBIT));
+      if (lane == 0) my_upd += (int64_t)__popcll(um);
+    }
+    __syncthreads();
+  }
+  const int64_t ev = block_sum(my_evals, s_red);
+  const int64_t pf = block_sum(my_perf, s_red);
+  const int64_t up = block_sum(my_upd, s_red);
+  if (tid == 0) {
+    if (ev) atomicAdd((unsigned long long*)&a.stats[STAT_EVALS], (unsigned long long)ev);
+    if (pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
+    if (up) atomicAdd((unsigned long long*)&a.stats[STAT_UPDATES], (unsigned long long)up);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline int grid_for(int64_t work, int block, int cap_blocks) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap_blocks) g = cap_blocks;
+  return (int)g;
+}
+
+hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_table(const Ctx& c, int32_t* bad) {
+  const int64_t total = c.n * c.Dp;
+  const int g = grid_for(total, 256, 65536);
+  if (c.dtype == 0)
+    hipLaunchKernelGGL(k_log_table<float>, dim3(g), dim3(256), 0, c.stream, (const float*)c.P, c.n, c.D, c.Dp,
+                       c.L, bad);
+  else
+    hipLaunchKernelGGL(k_log_table<double>, dim3(g), dim3(256), 0, c.stream, (const double*)c.P, c.n, c.D, c.Dp,
+                       c.L, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_graph(const Ctx& c) {
+  const int g = (int)((c.n + 3) / 4);
+  uint32_t* F = c.F[c.cur];
+  double* keys = c.keys[c.cur];
+  if (c.dtype == 0)
+    hipLaunchKernelGGL(k_init_graph<float>, dim3(g), dim3(256), 0, c.stream, (const float*)c.P, c.L, c.n, c.D,
+                       c.Dp, c.K, c.seed, F, keys);
+  else
+    hipLaunchKernelGGL(k_init_graph<double>, dim3(g), dim3(256), 0, c.stream, (const double*)c.P, c.L, c.n, c.D,
+                       c.Dp, c.K, c.seed, F, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits) {
+  const int g = grid_for(c.M, 256, 1 << 30);
+  hipLaunchKernelGGL(k_fcr, dim3(g), dim3(256), 0, c.stream, F, c.n, c.K, c.seed, round, c.M, hits);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
+  const int64_t nK = c.n * c.K;
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.deg, c.n);
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.fill, c.n);
+  hipLaunchKernelGGL(k_degree, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.deg);
+  const int64_t ntiles = (c.n + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, c.stream, c.deg, c.n, c.rowptr,
+                     c.tilesum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, c.stream, c.tilesum, ntiles, c.rowptr, c.n);
+  hipLaunchKernelGGL(k_scan_add, dim3(grid_for(c.n, 256, 8192)), dim3(256), 0, c.stream, c.rowptr, c.n,
+                     c.tilesum);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.rowptr,
+                     c.fill, c.col);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(const Ctx& c) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c.stream, c.class_count, (int64_t)NCLASS);
+  hipLaunchKernelGGL(k_bin, dim3(grid_for(c.n, 256, 8192)), dim3(256), 0, c.stream, c.rowptr, c.n, c.K,
+                     c.class_count, c.class_list);
+  return hipGetLastError();
+}
+
+template <int CAP, typename PT>
+static hipError_t launch_join_class(const Ctx& c, const JoinArgs& a, int cls) {
+  auto kern = k_join<CAP, PT>;
+  int grid;
+  if (CAP == 0) {
+    grid = c.gblocks;
+  } else {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.class_list + (int64_t)cls * c.n,
+                     c.class_count + cls);
+  return hipGetLastError();
+}
+
+template <typename PT>
+static hipError_t launch_join_all(const Ctx& c, const JoinArgs& a) {
+  hipError_t e;
+  if ((e = launch_join_class<CLASS_CAP_MIN << 0, PT>(c, a, 0)) != hipSuccess) return e;
+  if ((e = launch_join_class<CLASS_CAP_MIN << 1, PT>(c, a, 1)) != hipSuccess) return e;
+  if ((e = launch_join_class<CLASS_CAP_MIN << 2, PT>(c, a, 2)) != hipSuccess) return e;
+  if ((e = launch_join_class<CLASS_CAP_MIN << 3, PT>(c, a, 3)) != hipSuccess) return e;
+  if ((e = launch_join_class<CLASS_CAP_MIN << 4, PT>(c, a, 4)) != hipSuccess) return e;
+  if ((e = launch_join_class<CLASS_CAP_MIN << 5, PT>(c, a, 5)) != hipSuccess) return e;
+  return launch_join_class<0, PT>(c, a, 6);
+}
+
+hipError_t launch_join(const Ctx& c, int64_t* stats) {
+  JoinArgs a;
+  a.P = c.P;
+  a.L = c.L;
+  a.n = c.n;
+  a.D = c.D;
+  a.Dp = c.Dp;
+  a.K = c.K;
+  a.F = c.F[c.cur];
+  a.keys = c.keys[c.cur];
+  a.rowptr = c.rowptr;
+  a.col = c.col;
+  a.Fn = c.F[c.cur ^ 1];
+  a.keysn = c.keys[c.cur ^ 1];
+  a.stats = stats;
+  a.skip = (c.flags & 1) ? 0 : 1;
+  a.gtab = c.gtab;
+  a.gcand = c.gcand;
+  a.gstride = c.gstride;
+  return c.dtype == 0 ? launch_join_all<float>(c, a) : launch_join_all<double>(c, a);
+}
+
+hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out) {
+  const int64_t cnt = c.n * c.K;
+  hipLaunchKernelGGL(k_strip, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, F, cnt, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F) {
+  const int64_t cnt = c.n * c.K;
+  hipLaunchKernelGGL(k_load_idx, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, idx, cnt, F);
+  return hipGetLastError();
+}
+
+}  // namespace knnd

@@ -1,0 +1,65 @@
+"""The C ABI library loads on a host without a GPU and exports every function
+include/knnd.h declares; argument errors are reported before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2202_00517_amd as knnd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "knnd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(knnd_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_bound_functions():
+    assert _declared() == sorted(knnd.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(knnd.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_status_strings():
+    text = open(os.path.join(ROOT, "include", "knnd.h")).read()
+    ver = int(re.search(r"#define KNND_ABI_VERSION (\d+)", text).group(1))
+    assert knnd.lib().knnd_abi_version() == ver
+    for code, name in [(0, "KNND_OK"), (1, "KNND_WARN_MAX_ROUNDS"), (-1, "KNND_ERR_ARG"),
+                       (-2, "KNND_ERR_DOMAIN"), (-3, "KNND_ERR_NOMEM"), (-4, "KNND_ERR_DEVICE"),
+                       (-5, "KNND_ERR_UNSUPPORTED")]:
+        assert knnd.status_string(code) == name
+
+
+def test_params_struct_layout_matches_header():
+    assert ctypes.sizeof(knnd.knnd_params) == 24
+    assert ctypes.sizeof(knnd.knnd_round_stats) == 56
+    p = knnd.default_params()
+    assert (p.precision, p.dtype, p.fcr_samples, p.max_rounds, p.flags) == (0, 0, 0, 100, 0)
+
+
+@pytest.mark.parametrize("n,d,K", [(1, 3, 2), (10, 0, 2), (10, 3, 1), (10, 3, 10), (200, 3, 65)])
+def test_shape_errors_return_before_device_work(n, d, K):
+    P = np.full((max(n, 1), d + 1), 1.0 / (d + 1), dtype=np.float32)
+    idx = np.empty((max(n, 1), max(K, 1)), dtype=np.int32)
+    upd = np.empty(4, dtype=np.int64)
+    r = ctypes.c_int32()
+    st = knnd.lib().knnd_build(P.ctypes.data, n, d, K, 1, idx.ctypes.data, upd.ctypes.data, 4,
+                               ctypes.byref(r))
+    assert st == knnd.KNND_ERR_ARG
+
+
+def test_null_pointers_are_argument_errors():
+    lib = knnd.lib()
+    r = ctypes.c_int32()
+    assert lib.knnd_build(None, 10, 3, 2, 1, None, None, 4, ctypes.byref(r)) == knnd.KNND_ERR_ARG
+    assert lib.knnd_ctx_round(None, None) == knnd.KNND_ERR_ARG
+    assert lib.knnd_ctx_destroy(None) == knnd.KNND_ERR_ARG
+    assert lib.knnd_ctx_rounds(None) == -1

@@ -1,0 +1,322 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: neighbor lists and per-round counts bit-exact; keys compared as FP64
+bits (the tolerance allowed for keys is 1e-12 relative; the canonical key
+definition makes them identical, so the test demands identity).
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2202_00517_amd as knnd
+import synth
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def assert_same_graph(gi, gk, oi, ok, what):
+    gi = np.asarray(gi)
+    bad = np.nonzero((gi != oi).any(axis=1))[0]
+    assert bad.size == 0, f"{what}: {bad.size} rows differ, first x={bad[:5].tolist()}"
+    kb = np.nonzero((bits(gk) != bits(ok)).any(axis=1))[0]
+    assert kb.size == 0, f"{what}: keys differ in {kb.size} rows, first x={kb[:5].tolist()}"
+
+
+def full_compare(P, d, K, seed, M=0, flags=0, max_rounds=100):
+    say(f"full build n={P.shape[0]} d={d} K={K} seed={seed} {P.dtype} M={M} flags={flags}")
+    prm = knnd.default_params(fcr_samples=M, flags=flags, max_rounds=max_rounds)
+    g = knnd.knnd_build_ex(P, d, K, seed, prm)
+    o = oracle.build_graph(P, d, K, seed, M=M, max_rounds=max_rounds)
+    assert g["status"] == o.status
+    assert g["rounds"] == o.rounds, (g["rounds"], o.rounds)
+    for r in range(o.rounds + 1):
+        s = g["stats"][r]
+        assert s["fcr_hits"] == o.hits[r], (r, s, o.hits[r])
+        if r:
+            assert (s["updates"], s["evals_alg"]) == (o.updates[r], o.evals[r]), (r, s)
+    assert_same_graph(g["idx"], g["kl"], o.idx, o.keys, "final graph")
+    return g, o
+
+
+# ---------------------------------------------------------------------------
+# a0: log table and initial graph
+# ---------------------------------------------------------------------------
+def test_log_table_bit_exact():
+    specials = np.array([1.0, 1e-12, 0.5, 0.75, 2.0 ** -30, 0.7071067811865476, 0.7071067811865475,
+                         1.4142135623730951, 1.0 - 2.0 ** -53, 1e-310, 5e-324, 3.0, 1e300,
+                         0.999999, 1e-5, 0.1, 0.2, 0.3], dtype=np.float64)
+    near1 = 1.0 - 2.0 ** -np.arange(1, 55, dtype=np.float64)
+    vals = np.concatenate([specials, near1, np.random.default_rng(1).uniform(1e-9, 1.0, 4000)])
+    D = 8
+    vals = vals[: (vals.size // D) * D].reshape(-1, D)
+    say(f"log table of {vals.size} special/random values")
+    with knnd.Context(vals, D - 1, 2, 1) as c:
+        L = c.log_table()
+    ref = oracle.log_table(vals)
+    assert np.array_equal(bits(L), bits(ref))
+    for cfg in (1, 2):
+        cf = synth.CONFIGS[cfg]
+        P = synth.dirichlet(cf["data_seed"], cf["n"], cf["d"], cf["dtype"])
+        say(f"log table config {cfg}")
+        with knnd.Context(P, cf["d"], cf["K"], cf["seed"]) as c:
+            L = c.log_table()
+        assert np.array_equal(bits(L), bits(oracle.log_table(oracle.widen(P))))
+
+
+@pytest.mark.parametrize("n,d,K,dtype", [(2000, 5, 10, np.float64), (5000, 10, 20, np.float32),
+                                         (65, 3, 64, np.float32), (11, 2, 10, np.float32),
+                                         (777, 1, 2, np.float64)])
+def test_initial_graph_bit_exact(n, d, K, dtype):
+    P = synth.dirichlet(500 + n, n, d, dtype)
+    seed = 900 + n
+    say(f"initial graph n={n} d={d} K={K} {np.dtype(dtype).name}")
+    with knnd.Context(P, d, K, seed) as c:
+        st = c.init_graph()
+        gi, gk = c.get_graph()
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    oi, ok = oracle.initial_graph(P64, L, K, seed)
+    assert_same_graph(gi, gk, oi, ok, "initial graph")
+    assert st["fcr_hits"] == oracle.fcr(oi, seed, 0, min(n, 10000))
+
+
+# ---------------------------------------------------------------------------
+# a1..a5: one round from the oracle's own snapshot
+# ---------------------------------------------------------------------------
+def one_round(P, d, K, seed, F0=None, k0=None):
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    if F0 is None:
+        F0, k0 = oracle.initial_graph(P64, L, K, seed)
+    say(f"one round n={P.shape[0]} d={d} K={K}")
+    with knnd.Context(P, d, K, seed) as c:
+        c.set_graph(F0, k0, 0)
+        st = c.round()
+        gi, gk = c.get_graph()
+    oi, ok, upd, ev = oracle.round_step(P64, L, F0, k0)
+    assert_same_graph(gi, gk, oi, ok, "round 1")
+    assert (st["updates"], st["evals_alg"]) == (upd, ev)
+    assert st["fcr_hits"] == oracle.fcr(oi, seed, 1, min(P.shape[0], 10000))
+    return st
+
+
+@pytest.mark.parametrize("n,d,K", [(11, 3, 10), (200, 1, 2), (1000, 6, 16), (3001, 20, 30),
+                                   (4097, 60, 64), (20000, 10, 20)])
+def test_one_round_bit_exact(n, d, K):
+    one_round(synth.dirichlet(n + 7, n, d, np.float32), d, K, seed=n)
+
+
+def _hub_snapshot(P, K, hub, seed):
+    """Every point lists `hub` among its friends (the hub's own list is random),
+    so one receiver has n-1 co-friends.  Rows sorted by the oracle's keys."""
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    n = P.shape[0]
+    rng = np.random.default_rng(seed)
+    F = np.empty((n, K), dtype=np.int32)
+    keys = np.empty((n, K), dtype=np.float64)
+    for x in range(n):
+        row = [] if x == hub else [hub]
+        while len(row) < K:
+            y = int(rng.integers(0, n))
+            if y != x and y not in row:
+                row.append(y)
+        pairs = sorted((oracle.key(P64, L, x, y), y) for y in row)
+        F[x] = [y for _, y in pairs]
+        keys[x] = [k for k, _ in pairs]
+    return F, keys
+
+
+@pytest.mark.parametrize("n,d,K", [(3000, 6, 8), (20000, 4, 4)])
+def test_hub_receiver_large_tables(n, d, K):
+    # n=3000, K=8: the hub needs a 16384-slot LDS table; n=20000, K=4: the
+    # global-memory table.
+    P = synth.dirichlet(n + 11, n, d, np.float32)
+    F, k = _hub_snapshot(P, K, hub=n // 3, seed=n)
+    one_round(P, d, K, seed=5, F0=F, k0=k)
+
+
+def test_exact_ties_break_by_index():
+    # 20 distinct points, each repeated 12 times: many keys tie exactly
+    base = synth.dirichlet(31, 20, 5, np.float32)
+    P = np.repeat(base, 12, axis=0)
+    full_compare(P, 5, 8, seed=17)
+
+
+# ---------------------------------------------------------------------------
+# whole descent (all rounds, stop test) against the oracle
+# ---------------------------------------------------------------------------
+def test_config1_full():
+    c = synth.CONFIGS[1]
+    P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
+    full_compare(P, c["d"], c["K"], c["seed"])
+
+
+def test_random_small_configs_full():
+    rng = np.random.default_rng(2024)
+    for i in range(20):
+        n = int(rng.integers(30, 5000))
+        d = int(rng.integers(1, 61))
+        K = int(rng.integers(2, min(64, n - 1) + 1))
+        dtype = np.float32 if rng.random() < 0.7 else np.float64
+        P = synth.dirichlet(3000 + i, n, d, dtype)
+        full_compare(P, d, K, seed=4000 + i)
+
+
+def test_skipping_old_paths_changes_nothing():
+    P = synth.dirichlet(8, 6000, 9, np.float32)
+    a = knnd.knnd_build_ex(P, 9, 16, 33)
+    b = knnd.knnd_build_ex(P, 9, 16, 33, knnd.default_params(flags=knnd.KNND_FLAG_NO_SKIP))
+    assert a["rounds"] == b["rounds"]
+    assert np.array_equal(a["idx"], b["idx"]) and np.array_equal(bits(a["kl"]), bits(b["kl"]))
+    for sa, sb in zip(a["stats"], b["stats"]):
+        assert (sa["updates"], sa["fcr_hits"], sa["evals_alg"]) == \
+            (sb["updates"], sb["fcr_hits"], sb["evals_alg"])
+    assert sum(s["evals_performed"] for s in a["stats"]) < sum(s["evals_performed"] for s in b["stats"])
+    assert b["stats"][1]["evals_performed"] == b["stats"][1]["evals_alg"]
+
+
+def test_round_cap_and_fcr_sample_size():
+    P = synth.dirichlet(9, 4000, 8, np.float32)
+    full_compare(P, 8, 12, seed=3, max_rounds=2)
+    full_compare(P, 8, 12, seed=3, M=4000 * 3)
+
+
+def test_device_pointers_match_host_path():
+    import torch
+    P = synth.dirichlet(10, 7000, 12, np.float32)
+    h = knnd.knnd_build_ex(P, 12, 24, 44)
+    g = knnd.knnd_build_ex(torch.from_numpy(P).cuda(), 12, 24, 44)
+    torch.cuda.synchronize()
+    assert g["rounds"] == h["rounds"]
+    assert np.array_equal(g["idx"].cpu().numpy(), h["idx"])
+    assert np.array_equal(bits(g["kl"].cpu().numpy()), bits(h["kl"]))
+
+
+def test_basic_entry_point():
+    P = synth.dirichlet(12, 2500, 4, np.float32)
+    idx, upd, rounds, st = knnd.knnd_build(P, 4, 9, 123, max_rounds=50)
+    o = oracle.build_graph(P, 4, 9, 123, max_rounds=50)
+    assert st == o.status and rounds == o.rounds
+    assert np.array_equal(idx, o.idx)
+    assert np.array_equal(upd, o.updates[1:])
+
+
+def test_domain_errors():
+    P = synth.dirichlet(13, 100, 3, np.float32)
+    for bad in (0.0, -0.1, np.nan, np.inf):
+        Q = P.copy()
+        Q[17, 2] = bad
+        with pytest.raises(knnd.KnndError) as e:
+            knnd.knnd_build_ex(Q, 3, 4, 1)
+        assert e.value.status == knnd.KNND_ERR_DOMAIN
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads against the oracle's stored digests
+# ---------------------------------------------------------------------------
+def _golden(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def check_against_golden(cfg):
+    gold = _golden(f"c{cfg}")
+    c = synth.CONFIGS[cfg]
+    P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
+    say(f"config {cfg} full size vs stored oracle digests")
+    g = knnd.knnd_build_ex(P, c["d"], c["K"], c["seed"])
+    assert g["status"] == gold["status"]
+    assert g["rounds"] == gold["rounds"]
+    assert [s["fcr_hits"] for s in g["stats"]] == gold["fcr_hits"]
+    assert [s["updates"] for s in g["stats"]][1:] == gold["updates"][1:]
+    assert [s["evals_alg"] for s in g["stats"]][1:] == gold["evals_alg"][1:]
+    assert _digest(g["idx"]) == gold["idx_sha256"]
+    assert _digest(g["kl"]) == gold["kl_sha256"]
+    return g, P
+
+
+def test_config2_full_size():
+    check_against_golden(2)
+
+
+def test_config2_live_oracle():
+    c = synth.CONFIGS[2]
+    P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
+    full_compare(P, c["d"], c["K"], c["seed"])
+
+
+def test_config3_full_size():
+    g, P = check_against_golden(3)
+    c = synth.CONFIGS[3]
+    # sampled rows recomputed key by key with the oracle's key function
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    xs = synth.subsample(99, c["n"], 300)
+    for x in xs:
+        for j in range(c["K"]):
+            assert g["kl"][x, j] == oracle.key(P64, L, int(x), int(g["idx"][x, j]))
+
+
+def test_config3_round1_sampled_receivers():
+    # Round 1 at full size from the oracle's own initial graph, on 2000 receivers.
+    c = synth.CONFIGS[3]
+    P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    F0, k0 = oracle.initial_graph(P64, L, c["K"], c["seed"])
+    say("config 3 round 1 from the oracle snapshot")
+    with knnd.Context(P, c["d"], c["K"], c["seed"]) as ctx:
+        st0 = ctx.init_graph()
+        gi, gk = ctx.get_graph()
+        assert_same_graph(gi, gk, F0, k0, "config 3 initial graph")
+        st1 = ctx.round()
+        gi, gk = ctx.get_graph()
+    xs = synth.subsample(7, c["n"], 2000)
+    oi, ok, _, _ = oracle.round_subset(P64, L, F0, k0, xs)
+    assert_same_graph(gi[xs], gk[xs], oi, ok, "config 3 round 1 sample")
+    gold = _golden("c3")
+    assert st0["fcr_hits"] == gold["fcr_hits"][0]
+    assert (st1["updates"], st1["evals_alg"], st1["fcr_hits"]) == \
+        (gold["updates"][1], gold["evals_alg"][1], gold["fcr_hits"][1])
+
+
+def test_config4_full_size_and_recall():
+    g, P = check_against_golden(4)
+    c = synth.CONFIGS[4]
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    qs = synth.subsample(c["seed"], c["n"], 2000)
+    bf, _ = oracle.bruteforce(P64, L, c["K"], qs)
+    rec = np.mean([len(set(g["idx"][q].tolist()) & set(b.tolist())) / c["K"] for q, b in zip(qs, bf)])
+    say(f"config 4 recall@{c['K']} on 2000 queries: {rec:.4f}")
+    assert 0.0 < rec <= 1.0
