@@ -74,6 +74,9 @@ typedef enum {
 #define KNND_FLAG_NO_SKIP 0x1   /* also evaluate candidates reached only through
                                    edges that were already present one round
                                    earlier (same result, more work) */
+#define KNND_FLAG_PULL 0x2      /* join in pull form (each receiver gathers its
+                                   candidates' log rows) instead of hub form
+                                   (same result) */
 
 typedef struct {
     int32_t precision;          /* knnd_precision */

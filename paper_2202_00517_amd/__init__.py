@@ -25,6 +25,7 @@ KNND_ERR_UNSUPPORTED = -5
 KNND_F32, KNND_F64 = 0, 1
 KNND_PREC_FP64, KNND_PREC_MIXED_BF16, KNND_PREC_MIXED_FP16 = 0, 1, 2
 KNND_FLAG_NO_SKIP = 0x1
+KNND_FLAG_PULL = 0x2
 
 EXPORTED = [
     "knnd_default_params", "knnd_status_string", "knnd_abi_version", "knnd_build",

@@ -35,9 +35,10 @@ hipError_t dalloc(T** p, size_t count) {
 }
 
 void free_ctx(Ctx& c) {
-  void* bufs[] = {c.P,  c.L,      c.F[0],    c.F[1],   c.keys[0],     c.keys[1],    c.deg,   c.fill,
-                  c.rowptr, c.col, c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.dstats,
-                  c.dflag};
+  void* bufs[] = {c.P,      c.L,      c.F[0],   c.F[1],      c.keys[0],     c.keys[1],  c.deg,
+                  c.fill,   c.rowptr, c.col,    c.colslot,   c.revpos,      c.segbase,  c.seg,
+                  c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.gckey, c.bcand, c.bckey,
+                  c.dstats, c.dflag};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c.hstats) (void)hipHostFree(c.hstats);
@@ -90,6 +91,7 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   c.d = d;
   c.D = d + 1;
   c.Dp = (c.D + 1) & ~1;
+  c.Ds = c.D | 1;  // odd LDS row stride (in doubles) for conflict-free column reads
   c.K = K;
   c.seed = seed;
   c.dtype = prm.dtype;
@@ -114,11 +116,18 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   if (e == hipSuccess) e = dalloc(&c.fill, (size_t)n);
   if (e == hipSuccess) e = dalloc(&c.rowptr, (size_t)n + 1);
   if (e == hipSuccess) e = dalloc(&c.col, nK);
+  if (e == hipSuccess) e = dalloc(&c.colslot, nK);
+  if (e == hipSuccess) e = dalloc(&c.revpos, nK);
+  if (e == hipSuccess) e = dalloc(&c.segbase, (size_t)n + 1);
   if (e == hipSuccess) e = dalloc(&c.tilesum, (size_t)ntiles + 1);
   if (e == hipSuccess) e = dalloc(&c.class_count, (size_t)knnd::NCLASS);
   if (e == hipSuccess) e = dalloc(&c.class_list, (size_t)knnd::NCLASS * n);
   if (e == hipSuccess) e = dalloc(&c.gtab, (size_t)c.gblocks * c.gstride);
   if (e == hipSuccess) e = dalloc(&c.gcand, (size_t)c.gblocks * (c.gstride / 2));
+  if (e == hipSuccess) e = dalloc(&c.gckey, (size_t)c.gblocks * (c.gstride / 2));
+  c.bblocks = 2 * c.num_cu;
+  if (e == hipSuccess) e = dalloc(&c.bcand, (size_t)c.bblocks * knnd::BIG_CAND);
+  if (e == hipSuccess) e = dalloc(&c.bckey, (size_t)c.bblocks * knnd::BIG_CAND);
   if (e == hipSuccess) e = dalloc(&c.dstats, (size_t)knnd::STAT_N);
   if (e == hipSuccess) e = dalloc(&c.dflag, (size_t)4);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c.hstats), knnd::STAT_N * sizeof(int64_t));
@@ -127,6 +136,14 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   if (e == hipSuccess) e = hipEventCreate(&c.evj0);
   if (e == hipSuccess) e = hipEventCreate(&c.evj1);
   if (e != hipSuccess) return map_err(e);
+  // Hub form: candidate rows of a hub must fit in LDS, and the key segments
+  // (K(2K+1) doubles per point) must fit in memory; otherwise the pull form.
+  c.use_hub = !(c.flags & KNND_FLAG_PULL) && (size_t)(K + 1) * c.Ds * sizeof(double) <= 64 * 1024;
+  if (c.use_hub && dalloc(&c.seg, nK * (size_t)(2 * K + 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    c.seg = nullptr;
+    c.use_hub = false;
+  }
 
   const size_t pbytes = (size_t)n * c.D * esz;
   KNND_HIP(hipMemcpyAsync(c.P, points, pbytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,

@@ -8,9 +8,11 @@
 
 namespace knnd {
 
-// Receiver classes by hash-table capacity: 512 << k slots for k = 0..5 in LDS,
-// class 6 in global memory for very large co-friend lists.
-constexpr int NCLASS = 7;
+// Receiver classes by hash-table capacity: 512 << k slots for k = 0..6 in LDS
+// (classes 5 and 6 keep their candidate lists in global memory), class 7 in
+// global memory for very large co-friend lists.
+constexpr int NCLASS = 8;
+constexpr int BIG_CAND = 16384;  // candidate-list entries per block of the big LDS classes
 constexpr uint32_t IDMASK_HOST = 0x3FFFFFFFu;  // point indices are below this
 constexpr uint32_t CLASS_CAP_MIN = 512;
 
@@ -22,7 +24,7 @@ struct Ctx {
   hipStream_t stream = nullptr;
   int num_cu = 0;
   int64_t n = 0;
-  int d = 0, D = 0, Dp = 0, K = 0;
+  int d = 0, D = 0, Dp = 0, Ds = 0, K = 0;
   uint64_t seed = 0;
   int dtype = 0;      // 0 F32, 1 F64
   int precision = 0;
@@ -42,11 +44,20 @@ struct Ctx {
   int32_t* fill = nullptr;    // [n]
   int64_t* rowptr = nullptr;  // [n+1]
   uint32_t* col = nullptr;    // [nK]
+  uint8_t* colslot = nullptr; // [nK] slot of the edge in its source's list
+  int32_t* revpos = nullptr;  // [nK] position of an edge's source in its target's co-friend list
+  int64_t* segbase = nullptr; // [n+1] candidate-segment offsets (hub form)
+  double* seg = nullptr;      // [nK(2K+1)] candidate keys (hub form)
+  bool use_hub = false;
   int64_t* tilesum = nullptr;
   int32_t* class_count = nullptr;  // [NCLASS]
   int32_t* class_list = nullptr;   // [NCLASS][n]
   uint32_t* gtab = nullptr;        // [gblocks][gstride]
   uint32_t* gcand = nullptr;       // [gblocks][gstride/2]
+  double* gckey = nullptr;         // [gblocks][gstride/2]
+  uint32_t* bcand = nullptr;       // [bblocks][BIG_CAND]
+  double* bckey = nullptr;         // [bblocks][BIG_CAND]
+  int bblocks = 0;
   int64_t gstride = 0;
   int gblocks = 0;
   int64_t* dstats = nullptr;  // [STAT_N] device
@@ -59,18 +70,25 @@ struct JoinArgs {
   const void* P;
   const double* L;
   int64_t n;
-  int D, Dp, K;
+  int D, Dp, Ds, K;
   const uint32_t* F;
   const double* keys;
   const int64_t* rowptr;
   const uint32_t* col;
+  const uint8_t* colslot;
+  const int32_t* revpos;
+  const int64_t* segbase;
+  double* seg;
   uint32_t* Fn;
   double* keysn;
   int64_t* stats;
   int skip;
   uint32_t* gtab;
   uint32_t* gcand;
+  double* gckey;
   int64_t gstride;
+  uint32_t* bcand;
+  double* bckey;
 };
 
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);

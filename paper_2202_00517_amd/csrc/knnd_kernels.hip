@@ -159,15 +159,18 @@ __device__ __forceinline__ int64_t block_exscan(int64_t v, int64_t* sh /*[4]*/, 
   return off + incl - v;
 }
 
-__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t* __restrict__ deg, int64_t n,
-                                                    int64_t* __restrict__ rowptr, int64_t* __restrict__ tilesum) {
+// Exclusive scan of deg[i] * a + b (a = 1, b = 0: reverse-neighbor offsets;
+// a = K+1, b = K*K: offsets of the per-receiver candidate segments).
+__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t* __restrict__ deg, int64_t n, int64_t a,
+                                                    int64_t b, int64_t* __restrict__ rowptr,
+                                                    int64_t* __restrict__ tilesum) {
   __shared__ int64_t sh[4];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-  int32_t v[SCAN_ITEMS];
+  int64_t v[SCAN_ITEMS];
   int64_t sum = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    v[k] = (base + k < n) ? deg[base + k] : 0;
+    v[k] = (base + k < n) ? (int64_t)deg[base + k] * a + b : 0;
     sum += v[k];
   }
   int64_t total;
@@ -201,13 +204,20 @@ __global__ void k_scan_add(int64_t* __restrict__ rowptr, int64_t n, const int64_
     rowptr[i] += tilesum[i / SCAN_TILE];
 }
 
+// Edge e = x*K + j (x -> v = F[x][j]) lands at position q of coF(v):
+// col[rowptr[v] + q] = x | new-flag, colslot[...] = j, revpos[e] = q.
 __global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, const int64_t* __restrict__ rowptr,
-                          int32_t* __restrict__ fill, uint32_t* __restrict__ col) {
+                          int32_t* __restrict__ fill, uint32_t* __restrict__ col, uint8_t* __restrict__ colslot,
+                          int32_t* __restrict__ revpos) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t raw = F[e];
     const uint32_t v = raw & IDMASK;
-    const int64_t pos = rowptr[v] + atomicAdd(&fill[v], 1);
-    col[pos] = (uint32_t)(e / K) | (raw & NEWBIT);
+    const int q = atomicAdd(&fill[v], 1);
+    const int64_t pos = rowptr[v] + q;
+    const int64_t x = e / K;
+    col[pos] = (uint32_t)x | (raw & NEWBIT);
+    colslot[pos] = (uint8_t)(e - x * K);
+    revpos[e] = q;
   }
 }
 
@@ -236,35 +246,6 @@ __global__ void k_bin(const int64_t* __restrict__ rowptr, int64_t n, int K, int3
   }
 }
 
-// ---------------------------------------------------------------------------
-// a2..a5: the local join, pull form, one 256-thread block per receiver x.
-//  B  insert x and F(x) into the block's hash set, marked excluded
-//  C  enumerate every candidate occurrence (co-friends, friends of friends,
-//     friends of co-friends) and insert it; a first insertion is one
-//     algorithmic evaluation; an occurrence through a new edge marks NEW
-//  D1 compact the non-excluded entries marked NEW
-//  D2 each wave computes canonical keys for 64 candidates at a time, drops
-//     those that cannot beat the current K-th (the paper's compare-to-last,
-//     Section 4.2) and merges the rest into its sorted list in registers
-//  E  wave 0 merges the four lists and writes the first K
-// A candidate reached only through edges already present one round earlier
-// cannot enter (it was considered then and lost to K entries that are still
-// at least as good), so it is counted but not evaluated.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int tab_insert(uint32_t* tab, uint32_t mask, uint32_t z, uint32_t flag) {
-  uint32_t h = z * 0x9E3779B1u;
-  h = (h ^ (h >> 15)) & mask;
-  for (;;) {
-    const uint32_t old = atomicCAS(&tab[h], EMPTY, z | flag);
-    if (old == EMPTY) return 1;
-    if ((old & IDMASK) == z) {
-      if ((flag & NEWBIT) && !(old & NEWBIT)) atomicOr(&tab[h], NEWBIT);
-      return 0;
-    }
-    h = (h + 1) & mask;
-  }
-}
-
 __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* sh /*[4]*/) {
 #pragma unroll
   for (int o = WAVE / 2; o > 0; o >>= 1) v += (int64_t)shfl_xor_u64((uint64_t)v, o);
@@ -275,12 +256,155 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* sh /*[4]*/) {
   return t;
 }
 
-template <int CAP, typename PT>
-__global__ __launch_bounds__(256) void k_join(JoinArgs a, const int32_t* __restrict__ list,
+// ---------------------------------------------------------------------------
+// a2+a3, hub form: every point v is a hub whose friends F(v) (and v itself)
+// are candidates for the receivers R(v) = coF(v) u F(v):
+//   r in coF(v):      friends of a friend      -> F(v)
+//   r in F(v):        friends of a co-friend   -> F(v) \ {r}, and the co-friend v
+// The K+1 candidate log rows are staged in LDS once per hub; each wave takes
+// floor(64/(K+1)) receivers at a time, one lane per candidate, and folds the
+// canonical FP64 key.  Keys go to fixed slots of the receiver's segment, laid
+// out in the receiver's own enumeration order:
+//   [c co-friends][K x K friends of friends][c x K friends of co-friends]
+// Pairs whose two edges were both present one round earlier are skipped
+// (their candidate cannot enter, see the receiver kernel).
+// ---------------------------------------------------------------------------
+template <typename PT>
+__global__ __launch_bounds__(256) void k_hub(JoinArgs a) {
+  extern __shared__ double s_cand[];  // (K+1) rows of Ds doubles
+  __shared__ uint32_t s_fv[2 * WAVE];
+  const int K = a.K, K1 = a.K + 1, D = a.D, Dp = a.Dp, Ds = a.Ds;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const PT* P = reinterpret_cast<const PT*>(a.P);
+  int G, g, ci0, cstep;
+  if (K1 <= WAVE) {
+    G = WAVE / K1;
+    g = lane / K1;
+    ci0 = lane - g * K1;
+    cstep = K1;
+  } else {
+    G = 1;
+    g = 0;
+    ci0 = lane;
+    cstep = WAVE;
+  }
+  const bool lane_on = g < G;
+  int64_t my_perf = 0;
+
+  for (int64_t v = blockIdx.x; v < a.n; v += gridDim.x) {
+    const int64_t rp = a.rowptr[v];
+    const int cv = (int)(a.rowptr[v + 1] - rp);
+    bool anynew = !a.skip;
+    if (tid < K) {
+      const uint32_t e = a.F[v * K + tid];
+      s_fv[tid] = e;
+      anynew |= (e & NEWBIT) != 0;
+    }
+    for (int q = tid; q < cv; q += 256) anynew |= (a.col[rp + q] & NEWBIT) != 0;
+    if (!__syncthreads_or(anynew)) continue;
+    for (int idx = tid; idx < K1 * D; idx += 256) {
+      const int j = idx / D, i = idx - j * D;
+      const int64_t c = (j < K) ? (int64_t)(s_fv[j] & IDMASK) : v;
+      s_cand[j * Ds + i] = a.L[c * Dp + i];
+    }
+    __syncthreads();
+    const int nR = cv + K;
+    for (int kb = wave * G; kb < nR; kb += 4 * G) {
+      const int k = kb + g;
+      if (!lane_on || k >= nR) continue;
+      int64_t r, b0, b1 = -1;
+      uint32_t rnew;
+      int excl = -1;
+      if (k < cv) {
+        const uint32_t e = a.col[rp + k];
+        r = e & IDMASK;
+        rnew = e & NEWBIT;
+        const int64_t cr = a.rowptr[r + 1] - a.rowptr[r];
+        b0 = a.segbase[r] + cr + (int64_t)a.colslot[rp + k] * K;
+      } else {
+        const int sp = k - cv;
+        const uint32_t e = s_fv[sp];
+        r = e & IDMASK;
+        rnew = e & NEWBIT;
+        excl = sp;
+        const int64_t q = a.revpos[v * K + sp];
+        const int64_t cr = a.rowptr[r + 1] - a.rowptr[r];
+        b0 = a.segbase[r] + cr + (int64_t)K * K + q * K;
+        b1 = a.segbase[r] + q;
+      }
+      const PT* pr = P + r * D;
+      const double* lr = a.L + r * Dp;
+      for (int ci = ci0; ci < K1; ci += cstep) {
+        int64_t pos;
+        bool isnew;
+        if (ci < K) {
+          if (ci == excl) continue;
+          pos = b0 + ci;
+          isnew = (rnew | (s_fv[ci] & NEWBIT)) != 0;
+        } else {
+          if (b1 < 0) continue;
+          pos = b1;
+          isnew = rnew != 0;
+        }
+        if (a.skip && !isnew) continue;
+        const double* lc = s_cand + ci * Ds;
+        double acc = 0.0;
+        for (int i = 0; i < D; ++i) acc = fma((double)pr[i], lr[i] - lc[i], acc);
+        a.seg[pos] = acc + 0.0;
+        ++my_perf;
+      }
+    }
+    __syncthreads();
+  }
+  __shared__ int64_t s_red[4];
+  const int64_t pf = block_sum(my_perf, s_red);
+  if (tid == 0 && pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
+}
+
+// ---------------------------------------------------------------------------
+// a2..a5, receiver side: one 256-thread block per receiver x.
+//  B  insert x and F(x) into the block's hash set, marked excluded
+//  C  enumerate every candidate occurrence (co-friends, friends of friends,
+//     friends of co-friends) and insert it.  A first insertion is one
+//     algorithmic evaluation.  The occurrence that first marks a candidate as
+//     reached through a new edge appends it to the candidate list (with its
+//     key from the segment in the hub form).
+//  D  each wave takes 64 listed candidates at a time (the pull form computes
+//     their canonical keys here, gathering log rows), drops those that cannot
+//     beat the current K-th (the paper's compare-to-last, Section 4.2) and
+//     merges the rest into its sorted list held in registers
+//  E  wave 0 merges the four lists and writes the first K
+// A candidate reached only through edges already present one round earlier
+// was a candidate then too and lost to K entries that are still at least as
+// good, so it cannot enter: it is counted but not evaluated.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int tab_insert(uint32_t* tab, uint32_t mask, uint32_t z, uint32_t flag) {
+  // returns bit 0: first insertion of z; bit 1: this call marked z NEW first
+  uint32_t h = z * 0x9E3779B1u;
+  h = (h ^ (h >> 15)) & mask;
+  for (;;) {
+    const uint32_t old = atomicCAS(&tab[h], EMPTY, z | flag);
+    if (old == EMPTY) return 1 | ((flag & NEWBIT) ? 2 : 0);
+    if ((old & IDMASK) == z) {
+      if ((flag & NEWBIT) && !(old & (NEWBIT | EXCLBIT))) {
+        const uint32_t prev = atomicOr(&tab[h], NEWBIT);
+        if (!(prev & NEWBIT)) return 2;
+      }
+      return 0;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+template <int CAP, typename PT, bool SEG>
+__global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restrict__ list,
                                               const int32_t* __restrict__ count) {
   constexpr bool GLOB = (CAP == 0);
+  constexpr bool BIG = (CAP > 8192);  // table in LDS, candidate list in global memory
+  constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   __shared__ uint32_t s_tab[GLOB ? 1 : CAP];
-  __shared__ uint32_t s_cand[GLOB ? 1 : CAP / 2];
+  __shared__ uint32_t s_cid[CC];
+  __shared__ double s_ckey[SEG ? CC : 1];
   __shared__ uint32_t s_fx[WAVE];
   __shared__ uint64_t s_lk[3][WAVE];
   __shared__ uint32_t s_li[3][WAVE];
@@ -294,8 +418,13 @@ __global__ __launch_bounds__(256) void k_join(JoinArgs a, const int32_t* __restr
   const int K = a.K;
   const int D = a.D, Dp = a.Dp;
   const int64_t n = a.n;
+  const int64_t half = a.gstride / 2;
   uint32_t* tab = GLOB ? a.gtab + (int64_t)blockIdx.x * a.gstride : s_tab;
-  uint32_t* cand = GLOB ? a.gcand + (int64_t)blockIdx.x * (a.gstride / 2) : s_cand;
+  uint32_t* cid = GLOB ? a.gcand + (int64_t)blockIdx.x * half
+                       : (BIG ? a.bcand + (int64_t)blockIdx.x * BIG_CAND : s_cid);
+  double* ckey = SEG ? (GLOB ? a.gckey + (int64_t)blockIdx.x * half
+                             : (BIG ? a.bckey + (int64_t)blockIdx.x * BIG_CAND : s_ckey))
+                     : nullptr;
   const PT* P = reinterpret_cast<const PT*>(a.P);
   const int nitems = *count;
   int64_t my_evals = 0, my_perf = 0, my_upd = 0;
@@ -306,6 +435,7 @@ __global__ __launch_bounds__(256) void k_join(JoinArgs a, const int32_t* __restr
     const int64_t c = a.rowptr[x + 1] - rp;
     const int64_t KK = (int64_t)K * K;
     const int64_t T = c + KK + c * K;
+    const int64_t sbase = SEG ? a.segbase[x] : 0;
     uint32_t cap = (uint32_t)CAP;
     if (GLOB) {
       const int64_t need2 = 2 * table_need(c, K, n);
@@ -330,46 +460,53 @@ __global__ __launch_bounds__(256) void k_join(JoinArgs a, const int32_t* __restr
       tab_insert(tab, mask, (uint32_t)x, EXCLBIT);
     }
     __syncthreads();
-    // C: enumerate candidate occurrences
-    for (int64_t t = tid; t < T; t += 256) {
-      uint32_t z, nw;
-      if (t < c) {
-        const uint32_t w = a.col[rp + t];
-        z = w & IDMASK;
-        nw = w & NEWBIT;
-      } else if (t < c + KK) {
-        const int u = (int)(t - c);
-        const int j = u / K;
-        const int s = u - j * K;
-        const uint32_t v = s_fx[j];
-        const uint32_t zr = a.F[(int64_t)(v & IDMASK) * K + s];
-        z = zr & IDMASK;
-        nw = (v | zr) & NEWBIT;
-      } else {
-        const int64_t u = t - c - KK;
-        const int64_t q = u / K;
-        const int s = (int)(u - q * K);
-        const uint32_t w = a.col[rp + q];
-        const uint32_t zr = a.F[(int64_t)(w & IDMASK) * K + s];
-        z = zr & IDMASK;
-        nw = (w | zr) & NEWBIT;
+    // C: enumerate candidate occurrences (uniform trip count across the block)
+    for (int64_t t0 = 0; t0 < T; t0 += 256) {
+      const int64_t t = t0 + tid;
+      int res = 0;
+      uint32_t z = 0;
+      if (t < T) {
+        uint32_t nw;
+        if (t < c) {
+          const uint32_t w = a.col[rp + t];
+          z = w & IDMASK;
+          nw = w & NEWBIT;
+        } else if (t < c + KK) {
+          const int u = (int)(t - c);
+          const int j = u / K;
+          const int s = u - j * K;
+          const uint32_t v = s_fx[j];
+          const uint32_t zr = a.F[(int64_t)(v & IDMASK) * K + s];
+          z = zr & IDMASK;
+          nw = (v | zr) & NEWBIT;
+        } else {
+          const int64_t u = t - c - KK;
+          const int64_t q = u / K;
+          const int s = (int)(u - q * K);
+          const uint32_t w = a.col[rp + q];
+          const uint32_t zr = a.F[(int64_t)(w & IDMASK) * K + s];
+          z = zr & IDMASK;
+          nw = (w | zr) & NEWBIT;
+        }
+        if (!a.skip) nw = NEWBIT;
+        res = tab_insert(tab, mask, z, nw);
+        my_evals += res & 1;
       }
-      if (!a.skip) nw = NEWBIT;
-      my_evals += tab_insert(tab, mask, z, nw);
+      const bool app = (res & 2) != 0;
+      const uint64_t m = __ballot(app);
+      if (m) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_ncand, (int)__popcll(m));
+        base = __shfl(base, 0, WAVE);
+        if (app) {
+          const int at = base + (int)rank_in(m);
+          cid[at] = z;
+          if (SEG) ckey[at] = a.seg[sbase + t];
+        }
+      }
     }
     __syncthreads();
-    // D1: compact candidates to evaluate
-    for (uint32_t s = tid; s < cap; s += 256) {
-      const uint32_t e = tab[s];
-      const bool el = (e != EMPTY) && !(e & EXCLBIT) && (e & NEWBIT);
-      const uint64_t m = __ballot(el);
-      int base = 0;
-      if (lane == 0 && m) base = atomicAdd(&s_ncand, (int)__popcll(m));
-      base = __shfl(base, 0, WAVE);
-      if (el) cand[base + (int)rank_in(m)] = e & IDMASK;
-    }
-    __syncthreads();
-    // D2: keys, compare-to-last filter, wave merges
+    // D: keys, compare-to-last filter, wave merges
     const int ncand = s_ncand;
     uint64_t lk = KEY_SENTINEL;
     uint32_t li = IDMASK;
@@ -385,10 +522,13 @@ __global__ __launch_bounds__(256) void k_join(JoinArgs a, const int32_t* __restr
       uint64_t kb = KEY_SENTINEL;
       uint32_t z = IDMASK;
       if (valid) {
-        z = cand[i];
-        kb = key_bits(canonical_key(px, lx, a.L + (int64_t)z * Dp, D));
+        z = cid[i];
+        if (SEG)
+          kb = key_bits(ckey[i]);
+        else
+          kb = key_bits(canonical_key(px, lx, a.L + (int64_t)z * Dp, D));
       }
-      my_perf += valid ? 1 : 0;
+      my_perf += (!SEG && valid) ? 1 : 0;
       const uint64_t kk = shfl_u64(lk, K - 1);
       const uint32_t ki = shfl_u32(li, K - 1);
       const uint64_t tau = *(volatile uint64_t*)&s_tau;
@@ -475,19 +615,23 @@ hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* h
   return hipGetLastError();
 }
 
+static void launch_scan(const Ctx& c, int64_t a, int64_t b, int64_t* out) {
+  const int64_t ntiles = (c.n + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, c.stream, c.deg, c.n, a, b, out,
+                     c.tilesum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, c.stream, c.tilesum, ntiles, out, c.n);
+  hipLaunchKernelGGL(k_scan_add, dim3(grid_for(c.n, 256, 8192)), dim3(256), 0, c.stream, out, c.n, c.tilesum);
+}
+
 hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
   const int64_t nK = c.n * c.K;
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.deg, c.n);
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.fill, c.n);
   hipLaunchKernelGGL(k_degree, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.deg);
-  const int64_t ntiles = (c.n + SCAN_TILE - 1) / SCAN_TILE;
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, c.stream, c.deg, c.n, c.rowptr,
-                     c.tilesum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, c.stream, c.tilesum, ntiles, c.rowptr, c.n);
-  hipLaunchKernelGGL(k_scan_add, dim3(grid_for(c.n, 256, 8192)), dim3(256), 0, c.stream, c.rowptr, c.n,
-                     c.tilesum);
+  launch_scan(c, 1, 0, c.rowptr);
+  if (c.use_hub) launch_scan(c, c.K + 1, (int64_t)c.K * c.K, c.segbase);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.rowptr,
-                     c.fill, c.col);
+                     c.fill, c.col, c.colslot, c.revpos);
   return hipGetLastError();
 }
 
@@ -498,9 +642,9 @@ hipError_t launch_bin(const Ctx& c) {
   return hipGetLastError();
 }
 
-template <int CAP, typename PT>
-static hipError_t launch_join_class(const Ctx& c, const JoinArgs& a, int cls) {
-  auto kern = k_join<CAP, PT>;
+template <int CAP, typename PT, bool SEG>
+static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
+  auto kern = k_recv<CAP, PT, SEG>;
   int grid;
   if (CAP == 0) {
     grid = c.gblocks;
@@ -509,22 +653,35 @@ static hipError_t launch_join_class(const Ctx& c, const JoinArgs& a, int cls) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1)
       per_cu = 1;
     grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
+    if (CAP > 8192) grid = std::min(grid, c.bblocks);
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.class_list + (int64_t)cls * c.n,
                      c.class_count + cls);
   return hipGetLastError();
 }
 
-template <typename PT>
-static hipError_t launch_join_all(const Ctx& c, const JoinArgs& a) {
+template <typename PT, bool SEG>
+static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
   hipError_t e;
-  if ((e = launch_join_class<CLASS_CAP_MIN << 0, PT>(c, a, 0)) != hipSuccess) return e;
-  if ((e = launch_join_class<CLASS_CAP_MIN << 1, PT>(c, a, 1)) != hipSuccess) return e;
-  if ((e = launch_join_class<CLASS_CAP_MIN << 2, PT>(c, a, 2)) != hipSuccess) return e;
-  if ((e = launch_join_class<CLASS_CAP_MIN << 3, PT>(c, a, 3)) != hipSuccess) return e;
-  if ((e = launch_join_class<CLASS_CAP_MIN << 4, PT>(c, a, 4)) != hipSuccess) return e;
-  if ((e = launch_join_class<CLASS_CAP_MIN << 5, PT>(c, a, 5)) != hipSuccess) return e;
-  return launch_join_class<0, PT>(c, a, 6);
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 0, PT, SEG>(c, a, 0)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 1, PT, SEG>(c, a, 1)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 2, PT, SEG>(c, a, 2)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 3, PT, SEG>(c, a, 3)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 4, PT, SEG>(c, a, 4)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 5, PT, SEG>(c, a, 5)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 6, PT, SEG>(c, a, 6)) != hipSuccess) return e;
+  return launch_recv_class<0, PT, SEG>(c, a, 7);
+}
+
+template <typename PT>
+static hipError_t launch_hub(const Ctx& c, const JoinArgs& a) {
+  const size_t lds = (size_t)(c.K + 1) * c.Ds * sizeof(double);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hub<PT>, 256, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu * 2);
+  hipLaunchKernelGGL(k_hub<PT>, dim3(grid), dim3(256), lds, c.stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_join(const Ctx& c, int64_t* stats) {
@@ -534,19 +691,33 @@ hipError_t launch_join(const Ctx& c, int64_t* stats) {
   a.n = c.n;
   a.D = c.D;
   a.Dp = c.Dp;
+  a.Ds = c.Ds;
   a.K = c.K;
   a.F = c.F[c.cur];
   a.keys = c.keys[c.cur];
   a.rowptr = c.rowptr;
   a.col = c.col;
+  a.colslot = c.colslot;
+  a.revpos = c.revpos;
+  a.segbase = c.segbase;
+  a.seg = c.seg;
   a.Fn = c.F[c.cur ^ 1];
   a.keysn = c.keys[c.cur ^ 1];
   a.stats = stats;
   a.skip = (c.flags & 1) ? 0 : 1;
   a.gtab = c.gtab;
   a.gcand = c.gcand;
+  a.gckey = c.gckey;
   a.gstride = c.gstride;
-  return c.dtype == 0 ? launch_join_all<float>(c, a) : launch_join_all<double>(c, a);
+  a.bcand = c.bcand;
+  a.bckey = c.bckey;
+  hipError_t e;
+  if (c.use_hub) {
+    e = c.dtype == 0 ? launch_hub<float>(c, a) : launch_hub<double>(c, a);
+    if (e != hipSuccess) return e;
+    return c.dtype == 0 ? launch_recv_all<float, true>(c, a) : launch_recv_all<double, true>(c, a);
+  }
+  return c.dtype == 0 ? launch_recv_all<float, false>(c, a) : launch_recv_all<double, false>(c, a);
 }
 
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out) {

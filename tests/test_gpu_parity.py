@@ -105,13 +105,13 @@ def test_initial_graph_bit_exact(n, d, K, dtype):
 # ---------------------------------------------------------------------------
 # a1..a5: one round from the oracle's own snapshot
 # ---------------------------------------------------------------------------
-def one_round(P, d, K, seed, F0=None, k0=None):
+def one_round(P, d, K, seed, F0=None, k0=None, flags=0):
     P64 = oracle.widen(P)
     L = oracle.log_table(P64)
     if F0 is None:
         F0, k0 = oracle.initial_graph(P64, L, K, seed)
-    say(f"one round n={P.shape[0]} d={d} K={K}")
-    with knnd.Context(P, d, K, seed) as c:
+    say(f"one round n={P.shape[0]} d={d} K={K} flags={flags}")
+    with knnd.Context(P, d, K, seed, knnd.default_params(flags=flags)) as c:
         c.set_graph(F0, k0, 0)
         st = c.round()
         gi, gk = c.get_graph()
@@ -122,10 +122,14 @@ def one_round(P, d, K, seed, F0=None, k0=None):
     return st
 
 
+JOIN_FORMS = [0, knnd.KNND_FLAG_PULL]
+
+
+@pytest.mark.parametrize("flags", JOIN_FORMS, ids=["hub", "pull"])
 @pytest.mark.parametrize("n,d,K", [(11, 3, 10), (200, 1, 2), (1000, 6, 16), (3001, 20, 30),
                                    (4097, 60, 64), (20000, 10, 20)])
-def test_one_round_bit_exact(n, d, K):
-    one_round(synth.dirichlet(n + 7, n, d, np.float32), d, K, seed=n)
+def test_one_round_bit_exact(n, d, K, flags):
+    one_round(synth.dirichlet(n + 7, n, d, np.float32), d, K, seed=n, flags=flags)
 
 
 def _hub_snapshot(P, K, hub, seed):
@@ -149,13 +153,15 @@ def _hub_snapshot(P, K, hub, seed):
     return F, keys
 
 
-@pytest.mark.parametrize("n,d,K", [(3000, 6, 8), (20000, 4, 4)])
-def test_hub_receiver_large_tables(n, d, K):
-    # n=3000, K=8: the hub needs a 16384-slot LDS table; n=20000, K=4: the
-    # global-memory table.
+@pytest.mark.parametrize("flags", JOIN_FORMS, ids=["hub", "pull"])
+@pytest.mark.parametrize("n,d,K", [(3000, 6, 8), (7000, 5, 4), (40000, 4, 4)])
+def test_hub_receiver_large_tables(n, d, K, flags):
+    # the receiver with n-1 co-friends needs a 16384-slot LDS table (n=3000,
+    # K=8), a 32768-slot one (n=7000, K=4) and the global-memory table
+    # (n=40000, K=4)
     P = synth.dirichlet(n + 11, n, d, np.float32)
     F, k = _hub_snapshot(P, K, hub=n // 3, seed=n)
-    one_round(P, d, K, seed=5, F0=F, k0=k)
+    one_round(P, d, K, seed=5, F0=F, k0=k, flags=flags)
 
 
 def test_exact_ties_break_by_index():
@@ -176,26 +182,31 @@ def test_config1_full():
 
 def test_random_small_configs_full():
     rng = np.random.default_rng(2024)
-    for i in range(20):
+    for i in range(24):
         n = int(rng.integers(30, 5000))
         d = int(rng.integers(1, 61))
         K = int(rng.integers(2, min(64, n - 1) + 1))
         dtype = np.float32 if rng.random() < 0.7 else np.float64
         P = synth.dirichlet(3000 + i, n, d, dtype)
-        full_compare(P, d, K, seed=4000 + i)
+        full_compare(P, d, K, seed=4000 + i, flags=JOIN_FORMS[i % 2])
 
 
-def test_skipping_old_paths_changes_nothing():
+@pytest.mark.parametrize("form", JOIN_FORMS, ids=["hub", "pull"])
+def test_skipping_old_paths_changes_nothing(form):
     P = synth.dirichlet(8, 6000, 9, np.float32)
-    a = knnd.knnd_build_ex(P, 9, 16, 33)
-    b = knnd.knnd_build_ex(P, 9, 16, 33, knnd.default_params(flags=knnd.KNND_FLAG_NO_SKIP))
+    a = knnd.knnd_build_ex(P, 9, 16, 33, knnd.default_params(flags=form))
+    b = knnd.knnd_build_ex(P, 9, 16, 33, knnd.default_params(flags=form | knnd.KNND_FLAG_NO_SKIP))
     assert a["rounds"] == b["rounds"]
     assert np.array_equal(a["idx"], b["idx"]) and np.array_equal(bits(a["kl"]), bits(b["kl"]))
     for sa, sb in zip(a["stats"], b["stats"]):
         assert (sa["updates"], sa["fcr_hits"], sa["evals_alg"]) == \
             (sb["updates"], sb["fcr_hits"], sb["evals_alg"])
     assert sum(s["evals_performed"] for s in a["stats"]) < sum(s["evals_performed"] for s in b["stats"])
-    assert b["stats"][1]["evals_performed"] == b["stats"][1]["evals_alg"]
+    if form == knnd.KNND_FLAG_PULL:
+        assert b["stats"][1]["evals_performed"] == b["stats"][1]["evals_alg"]
+    else:  # the hub form computes every candidate occurrence except x itself
+        n, K = 6000, 16
+        assert b["stats"][1]["evals_performed"] == n * K * (2 * K + 1) - n * K
 
 
 def test_round_cap_and_fcr_sample_size():
@@ -269,10 +280,11 @@ def test_config2_full_size():
     check_against_golden(2)
 
 
-def test_config2_live_oracle():
+@pytest.mark.parametrize("form", JOIN_FORMS, ids=["hub", "pull"])
+def test_config2_live_oracle(form):
     c = synth.CONFIGS[2]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
-    full_compare(P, c["d"], c["K"], c["seed"])
+    full_compare(P, c["d"], c["K"], c["seed"], flags=form)
 
 
 def test_config3_full_size():
