@@ -106,8 +106,8 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   c.gblocks = 32;
   c.gstride = next_pow2(2 * n) < 1024 ? 1024 : next_pow2(2 * n);
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = hipMalloc(&c.P, (size_t)n * c.D * esz + 16);
-  if (e == hipSuccess) e = dalloc(&c.L, (size_t)n * c.Dp);
+  if (e == hipSuccess) e = hipMalloc(&c.P, ((size_t)n * c.D + knnd::HUB_MAXD) * esz);
+  if (e == hipSuccess) e = dalloc(&c.L, (size_t)n * c.Dp + knnd::HUB_MAXD);
   for (int b = 0; b < 2; ++b) {
     if (e == hipSuccess) e = dalloc(&c.F[b], nK);
     if (e == hipSuccess) e = dalloc(&c.keys[b], nK);
@@ -148,6 +148,8 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   const size_t pbytes = (size_t)n * c.D * esz;
   KNND_HIP(hipMemcpyAsync(c.P, points, pbytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                           c.stream));
+  KNND_HIP(hipMemsetAsync(static_cast<char*>(c.P) + pbytes, 0, knnd::HUB_MAXD * esz, c.stream));
+  KNND_HIP(hipMemsetAsync(c.L + (size_t)n * c.Dp, 0, knnd::HUB_MAXD * sizeof(double), c.stream));
   KNND_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int32_t), c.stream));
   KNND_HIP(knnd::launch_log_table(c, c.dflag));
   int32_t bad = 0;

@@ -225,4 +225,23 @@ __device__ __forceinline__ void wave_merge(uint64_t& ak, uint32_t& aid, uint64_t
   for (int stride = WAVE / 2; stride > 0; stride >>= 1) cx_step(ak, aid, stride, (lane & stride) == 0);
 }
 
+// Insert one wave-uniform entry (ck, ci) into the ascending list held one
+// entry per lane; the last lane's entry drops out.
+__device__ __forceinline__ void wave_insert(uint64_t& lk, uint32_t& li, uint64_t ck, uint32_t ci) {
+  const int lane = lane_id();
+  const bool move = ke_less(ck, ci, lk, li);  // the new entry goes before mine
+  const uint64_t pk = shfl_u64(lk, lane > 0 ? lane - 1 : 0);
+  const uint32_t pi = shfl_u32(li, lane > 0 ? lane - 1 : 0);
+  const int pos = (int)__popcll(__ballot(!move));
+  if (move) {
+    if (lane == pos) {
+      lk = ck;
+      li = ci;
+    } else {
+      lk = pk;
+      li = pi;
+    }
+  }
+}
+
 }  // namespace knnd

@@ -12,7 +12,9 @@ namespace knnd {
 // (classes 5 and 6 keep their candidate lists in global memory), class 7 in
 // global memory for very large co-friend lists.
 constexpr int NCLASS = 8;
-constexpr int BIG_CAND = 16384;  // candidate-list entries per block of the big LDS classes
+constexpr int BIG_CAND = 16384;
+constexpr int HUB_MAXD = 64;     // register hub kernel up to this many coordinates;
+                                 // P and L carry HUB_MAXD zeroed elements of tail padding  // candidate-list entries per block of the big LDS classes
 constexpr uint32_t IDMASK_HOST = 0x3FFFFFFFu;  // point indices are below this
 constexpr uint32_t CLASS_CAP_MIN = 512;
 

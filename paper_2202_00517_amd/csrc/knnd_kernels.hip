@@ -231,18 +231,30 @@ __device__ __forceinline__ int64_t table_need(int64_t c, int K, int64_t n) {
   return min(T, n - 1 - K) + K + 1;
 }
 
-__global__ void k_bin(const int64_t* __restrict__ rowptr, int64_t n, int K, int32_t* __restrict__ counts,
-                      int32_t* __restrict__ lists) {
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t need2 = 2 * table_need(rowptr[x + 1] - rowptr[x], K, n);
-    int cls = NCLASS - 1;
-    for (int k = 0; k < NCLASS - 1; ++k)
-      if (need2 <= (int64_t)(CLASS_CAP_MIN << k)) {
-        cls = k;
-        break;
-      }
-    const int pos = atomicAdd(&counts[cls], 1);
-    lists[(int64_t)cls * n + pos] = (int32_t)x;
+__global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr, int64_t n, int K,
+                                             int32_t* __restrict__ counts, int32_t* __restrict__ lists) {
+  const int lane = lane_id();
+  // uniform trip count so that every lane takes part in the ballots
+  for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = x0 + threadIdx.x;
+    int cls = -1;
+    if (x < n) {
+      const int64_t need2 = 2 * table_need(rowptr[x + 1] - rowptr[x], K, n);
+      cls = NCLASS - 1;
+      for (int k = 0; k < NCLASS - 1; ++k)
+        if (need2 <= (int64_t)(CLASS_CAP_MIN << k)) {
+          cls = k;
+          break;
+        }
+    }
+    for (int k = 0; k < NCLASS; ++k) {
+      const uint64_t m = __ballot(cls == k);
+      if (!m) continue;
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&counts[k], (int)__popcll(m));
+      base = __shfl(base, 0, WAVE);
+      if (cls == k) lists[(int64_t)k * n + base + (int)rank_in(m)] = (int32_t)x;
+    }
   }
 }
 
@@ -270,7 +282,7 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* sh /*[4]*/) {
 // (their candidate cannot enter, see the receiver kernel).
 // ---------------------------------------------------------------------------
 template <typename PT>
-__global__ __launch_bounds__(256) void k_hub(JoinArgs a) {
+__global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
   extern __shared__ double s_cand[];  // (K+1) rows of Ds doubles
   __shared__ uint32_t s_fv[2 * WAVE];
   const int K = a.K, K1 = a.K + 1, D = a.D, Dp = a.Dp, Ds = a.Ds;
@@ -359,6 +371,103 @@ __global__ __launch_bounds__(256) void k_hub(JoinArgs a) {
   __shared__ int64_t s_red[4];
   const int64_t pf = block_sum(my_perf, s_red);
   if (tid == 0 && pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
+}
+
+// Register form of the hub kernel for D <= MAXD (the common case): one wave
+// per hub, one lane per receiver.  The receiver's coordinates and logs live in
+// VGPRs; each candidate's log row is wave-uniform and is read with scalar
+// loads, so the fold is two FP64 VALU operations per coordinate with no
+// vector memory traffic.  Same output as k_hub_lds.
+template <int MAXD, typename PT>
+__global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __restrict__ L,
+                                                 const PT* __restrict__ P) {
+  const int K = a.K, K1 = a.K + 1, D = a.D, Dp = a.Dp;
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  int64_t my_perf = 0;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < a.n; v += nwaves) {
+    const int64_t rp = a.rowptr[v];
+    const int cv = (int)(a.rowptr[v + 1] - rp);
+    const uint32_t fv = lane < K ? a.F[v * K + lane] : 0u;  // lane j holds F(v)[j]
+    const uint64_t cand_new = __ballot((fv & NEWBIT) != 0);
+    const int nR = cv + K;
+    for (int k0 = 0; k0 < nR; k0 += WAVE) {
+      const int k = k0 + lane;
+      const bool on = k < nR;
+      // all lanes take part in the shuffle (a disabled source lane reads as 0)
+      const uint32_t fsp = (uint32_t)__shfl((int)fv, (k >= cv && k < nR) ? k - cv : 0, WAVE);
+      int64_t r = 0, b0 = 0, b1 = -1;
+      uint32_t rnew = 0;
+      int excl = -1;
+      if (on) {
+        if (k < cv) {
+          const uint32_t e = a.col[rp + k];
+          r = e & IDMASK;
+          rnew = e & NEWBIT;
+          const int64_t cr = a.rowptr[r + 1] - a.rowptr[r];
+          b0 = a.segbase[r] + cr + (int64_t)a.colslot[rp + k] * K;
+        } else {
+          const int sp = k - cv;
+          r = fsp & IDMASK;
+          rnew = fsp & NEWBIT;
+          excl = sp;
+          const int64_t q = a.revpos[v * K + sp];
+          const int64_t cr = a.rowptr[r + 1] - a.rowptr[r];
+          b0 = a.segbase[r] + cr + (int64_t)K * K + q * K;
+          b1 = a.segbase[r] + q;
+        }
+      }
+      const bool want_any = on && (!a.skip || rnew != 0);
+      if (a.skip && cand_new == 0 && __ballot(want_any) == 0) continue;
+      // Receiver row in registers; coordinates beyond D are zero, so the
+      // extra terms fma(0, y, acc) (y finite) leave acc unchanged.  Rows are
+      // read past their end into the zeroed tail padding of P and L.
+      double pr[MAXD], lr[MAXD];
+      const PT* prow = P + (on ? r : 0) * D;
+      const double* lrow = L + (on ? r : 0) * Dp;
+#pragma unroll
+      for (int i = 0; i < MAXD; ++i) {
+        const double pv = (double)prow[i];
+        const double lv = lrow[i];
+        pr[i] = i < D ? pv : 0.0;
+        lr[i] = i < D ? lv : 0.0;
+      }
+      for (int ci = 0; ci < K1; ++ci) {
+        const bool cnew = ci < K && ((cand_new >> ci) & 1);
+        bool need;
+        int64_t pos;
+        if (ci < K) {
+          need = on && ci != excl && (!a.skip || rnew || cnew);
+          pos = b0 + ci;
+        } else {
+          need = on && b1 >= 0 && (!a.skip || rnew);
+          pos = b1;
+        }
+        if (__ballot(need) == 0) continue;
+        const uint32_t craw = ci < K ? (uint32_t)__shfl((int)fv, ci, WAVE) : (uint32_t)v;
+        const int64_t cidx = (int64_t)__builtin_amdgcn_readfirstlane(craw & IDMASK);
+        const double* lc = L + cidx * Dp;  // wave-uniform: scalar loads
+        double acc = 0.0;
+#pragma unroll
+        for (int i0 = 0; i0 < MAXD; i0 += 16) {
+          double cv16[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (i0 + i < MAXD) cv16[i] = lc[i0 + i];
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (i0 + i < MAXD) acc = fma(pr[i0 + i], lr[i0 + i] - cv16[i], acc);
+        }
+        if (need) {
+          a.seg[pos] = acc + 0.0;
+          ++my_perf;
+        }
+      }
+    }
+  }
+  __shared__ int64_t s_red[4];
+  const int64_t pf = block_sum(my_perf, s_red);
+  if (threadIdx.x == 0 && pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,48 +569,62 @@ __global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restr
       tab_insert(tab, mask, (uint32_t)x, EXCLBIT);
     }
     __syncthreads();
-    // C: enumerate candidate occurrences (uniform trip count across the block)
-    for (int64_t t0 = 0; t0 < T; t0 += 256) {
-      const int64_t t = t0 + tid;
-      int res = 0;
-      uint32_t z = 0;
-      if (t < T) {
-        uint32_t nw;
+    // C: enumerate candidate occurrences, four per thread in flight (uniform
+    // trip count across the block)
+    for (int64_t t0 = 0; t0 < T; t0 += 4 * 256) {
+      uint32_t z[4], nw[4];
+      int res[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t t = t0 + tid + 256 * u;
+        z[u] = 0;
+        nw[u] = 0;
         if (t < c) {
           const uint32_t w = a.col[rp + t];
-          z = w & IDMASK;
-          nw = w & NEWBIT;
+          z[u] = w & IDMASK;
+          nw[u] = w & NEWBIT;
         } else if (t < c + KK) {
-          const int u = (int)(t - c);
-          const int j = u / K;
-          const int s = u - j * K;
+          const int uu = (int)(t - c);
+          const int j = uu / K;
+          const int s = uu - j * K;
           const uint32_t v = s_fx[j];
           const uint32_t zr = a.F[(int64_t)(v & IDMASK) * K + s];
-          z = zr & IDMASK;
-          nw = (v | zr) & NEWBIT;
-        } else {
-          const int64_t u = t - c - KK;
-          const int64_t q = u / K;
-          const int s = (int)(u - q * K);
+          z[u] = zr & IDMASK;
+          nw[u] = (v | zr) & NEWBIT;
+        } else if (t < T) {
+          const int64_t uu = t - c - KK;
+          const int64_t q = uu / K;
+          const int s = (int)(uu - q * K);
           const uint32_t w = a.col[rp + q];
           const uint32_t zr = a.F[(int64_t)(w & IDMASK) * K + s];
-          z = zr & IDMASK;
-          nw = (w | zr) & NEWBIT;
+          z[u] = zr & IDMASK;
+          nw[u] = (w | zr) & NEWBIT;
         }
-        if (!a.skip) nw = NEWBIT;
-        res = tab_insert(tab, mask, z, nw);
-        my_evals += res & 1;
       }
-      const bool app = (res & 2) != 0;
-      const uint64_t m = __ballot(app);
-      if (m) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&s_ncand, (int)__popcll(m));
-        base = __shfl(base, 0, WAVE);
-        if (app) {
-          const int at = base + (int)rank_in(m);
-          cid[at] = z;
-          if (SEG) ckey[at] = a.seg[sbase + t];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        res[u] = 0;
+        if (t0 + tid + 256 * u < T) {
+          res[u] = tab_insert(tab, mask, z[u], a.skip ? nw[u] : NEWBIT);
+          my_evals += res[u] & 1;
+        }
+      }
+      double kv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) kv[u] = (SEG && (res[u] & 2)) ? a.seg[sbase + t0 + tid + 256 * u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool app = (res[u] & 2) != 0;
+        const uint64_t m = __ballot(app);
+        if (m) {
+          int base = 0;
+          if (lane == 0) base = atomicAdd(&s_ncand, (int)__popcll(m));
+          base = __shfl(base, 0, WAVE);
+          if (app) {
+            const int at = base + (int)rank_in(m);
+            cid[at] = z[u];
+            if (SEG) ckey[at] = kv[u];
+          }
         }
       }
     }
@@ -533,11 +656,24 @@ __global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restr
       const uint32_t ki = shfl_u32(li, K - 1);
       const uint64_t tau = *(volatile uint64_t*)&s_tau;
       const bool surv = valid && kb <= tau && ke_less(kb, z, kk, ki);
-      if (__ballot(surv)) {
-        uint64_t bk = surv ? kb : KEY_SENTINEL;
-        uint32_t bi = surv ? (z | NEWBIT) : IDMASK;
-        wave_sort(bk, bi);
-        wave_merge(lk, li, bk, bi);
+      const uint64_t sm = __ballot(surv);
+      if (sm) {
+        if (__popcll(sm) <= 8) {
+          // few survivors: insert them one by one
+          uint64_t mm = sm;
+          while (mm) {
+            const int src = __ffsll((unsigned long long)mm) - 1;
+            mm &= mm - 1;
+            const uint64_t ck = shfl_u64(kb, src);
+            const uint32_t cz = shfl_u32(z, src) | NEWBIT;
+            if (ke_less(ck, cz, shfl_u64(lk, K - 1), shfl_u32(li, K - 1))) wave_insert(lk, li, ck, cz);
+          }
+        } else {
+          uint64_t bk = surv ? kb : KEY_SENTINEL;
+          uint32_t bi = surv ? (z | NEWBIT) : IDMASK;
+          wave_sort(bk, bi);
+          wave_merge(lk, li, bk, bi);
+        }
         const uint64_t nk = shfl_u64(lk, K - 1);
         if (lane == 0 && nk < tau) atomicMin((unsigned long long*)&s_tau, (unsigned long long)nk);
       }
@@ -673,14 +809,32 @@ static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
   return launch_recv_class<0, PT, SEG>(c, a, 7);
 }
 
+template <int MAXD, typename PT>
+static hipError_t launch_hub_reg(const Ctx& c, const JoinArgs& a) {
+  auto kern = k_hub_reg<MAXD, PT>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu * 4);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.L, (const PT*)c.P);
+  return hipGetLastError();
+}
+
 template <typename PT>
 static hipError_t launch_hub(const Ctx& c, const JoinArgs& a) {
+  if (c.D <= 8) return launch_hub_reg<8, PT>(c, a);
+  if (c.D <= 12) return launch_hub_reg<12, PT>(c, a);
+  if (c.D <= 16) return launch_hub_reg<16, PT>(c, a);
+  if (c.D <= 24) return launch_hub_reg<24, PT>(c, a);
+  if (c.D <= 32) return launch_hub_reg<32, PT>(c, a);
+  if (c.D <= 40) return launch_hub_reg<40, PT>(c, a);
+  if (c.D <= 52) return launch_hub_reg<52, PT>(c, a);
+  if (c.D <= HUB_MAXD) return launch_hub_reg<HUB_MAXD, PT>(c, a);
   const size_t lds = (size_t)(c.K + 1) * c.Ds * sizeof(double);
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hub<PT>, 256, lds) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hub_lds<PT>, 256, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
   const int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu * 2);
-  hipLaunchKernelGGL(k_hub<PT>, dim3(grid), dim3(256), lds, c.stream, a);
+  hipLaunchKernelGGL(k_hub_lds<PT>, dim3(grid), dim3(256), lds, c.stream, a);
   return hipGetLastError();
 }
 
