@@ -174,6 +174,8 @@ int read_stats(Ctx& c, knnd_round_stats* st, bool joined) {
     st->ms = ms;
     st->ms_join = msj;
   }
+  // an internal consistency check failed on the device (results are unusable)
+  if (c.hstats[knnd::STAT_ERR] != 0) return KNND_ERR_DEVICE;
   return KNND_OK;
 }
 
@@ -280,9 +282,16 @@ int knnd_ctx_set_graph(knnd_ctx* h, const int32_t* idx, const double* kl, int32_
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   int32_t* staging = reinterpret_cast<int32_t*>(c.F[c.cur ^ 1]);
   KNND_HIP(hipMemcpyAsync(staging, idx, nK * 4, kind, c.stream));
-  KNND_HIP(knnd::launch_load_idx(c, staging, c.F[c.cur]));
+  KNND_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int32_t), c.stream));
+  KNND_HIP(knnd::launch_load_idx(c, staging, c.F[c.cur], c.dflag));
   KNND_HIP(hipMemcpyAsync(c.keys[c.cur], kl, nK * 8, kind, c.stream));
+  int32_t bad = 0;
+  KNND_HIP(hipMemcpyAsync(&bad, c.dflag, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
   KNND_HIP(hipStreamSynchronize(c.stream));
+  if (bad) {
+    c.have_graph = false;
+    return KNND_ERR_ARG;
+  }
   c.round = round;
   c.have_graph = true;
   return KNND_OK;

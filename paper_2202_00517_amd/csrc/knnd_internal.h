@@ -12,14 +12,14 @@ namespace knnd {
 // (classes 5 and 6 keep their candidate lists in global memory), class 7 in
 // global memory for very large co-friend lists.
 constexpr int NCLASS = 8;
-constexpr int BIG_CAND = 16384;
+constexpr int BIG_CAND = 24576;  // candidate-list entries per block of the big LDS classes
 constexpr int HUB_MAXD = 64;     // register hub kernel up to this many coordinates;
-                                 // P and L carry HUB_MAXD zeroed elements of tail padding  // candidate-list entries per block of the big LDS classes
+                                 // P and L carry HUB_MAXD zeroed elements of tail padding
 constexpr uint32_t IDMASK_HOST = 0x3FFFFFFFu;  // point indices are below this
 constexpr uint32_t CLASS_CAP_MIN = 512;
 
 // Per-round device counters
-enum { STAT_UPDATES = 0, STAT_HITS = 1, STAT_EVALS = 2, STAT_PERF = 3, STAT_RESCUES = 4, STAT_N = 8 };
+enum { STAT_UPDATES = 0, STAT_HITS = 1, STAT_EVALS = 2, STAT_PERF = 3, STAT_RESCUES = 4, STAT_ERR = 5, STAT_N = 8 };
 
 struct Ctx {
   int device = 0;
@@ -101,6 +101,6 @@ hipError_t launch_csr(const Ctx& c, const uint32_t* F);
 hipError_t launch_bin(const Ctx& c);
 hipError_t launch_join(const Ctx& c, int64_t* stats);
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out);
-hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F);
+hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad);
 
 }  // namespace knnd

@@ -30,10 +30,16 @@ __global__ void k_strip(const uint32_t* __restrict__ F, int64_t cnt, int32_t* __
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (int32_t)(F[i] & IDMASK);
 }
-// F = idx | NEWBIT (an externally supplied snapshot: every edge counts as new)
-__global__ void k_load_idx(const int32_t* __restrict__ idx, int64_t cnt, uint32_t* __restrict__ F) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
-    F[i] = ((uint32_t)idx[i] & IDMASK) | NEWBIT;
+// F = idx | NEWBIT (an externally supplied snapshot: every edge counts as
+// new).  An index outside [0, n) is replaced by 0 and counted in *bad.
+__global__ void k_load_idx(const int32_t* __restrict__ idx, int64_t cnt, int64_t n, uint32_t* __restrict__ F,
+                           int32_t* __restrict__ bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = idx[i];
+    const bool ok = v >= 0 && (int64_t)v < n;
+    if (!ok) atomicOr(bad, 1);
+    F[i] = ((uint32_t)(ok ? v : 0)) | NEWBIT;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -239,13 +245,24 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
     const int64_t x = x0 + threadIdx.x;
     int cls = -1;
     if (x < n) {
-      const int64_t need2 = 2 * table_need(rowptr[x + 1] - rowptr[x], K, n);
-      cls = NCLASS - 1;
-      for (int k = 0; k < NCLASS - 1; ++k)
-        if (need2 <= (int64_t)(CLASS_CAP_MIN << k)) {
-          cls = k;
-          break;
-        }
+      const int64_t c = rowptr[x + 1] - rowptr[x];
+      const int64_t need2 = 2 * table_need(c, K, n);
+      if (need2 <= (int64_t)(CLASS_CAP_MIN << 4)) {  // exact bound fits a small table
+        cls = 0;
+        while (need2 > (int64_t)(CLASS_CAP_MIN << cls)) ++cls;
+      } else {
+        // Large receivers: distinct candidates are typically 30-60% of the
+        // occurrences, so size optimistically; the two guarded classes hand
+        // a receiver that overflows to the global-memory class.
+        const int64_t T = c + (int64_t)K * K + c * K;
+        const int64_t est = (min(T, n - 1 - K) * 5) / 8 + K + 1;
+        if (est <= (int64_t)(CLASS_CAP_MIN << 5) * 5 / 8)
+          cls = 5;
+        else if (est <= (int64_t)(CLASS_CAP_MIN << 6) * 5 / 8)
+          cls = 6;
+        else
+          cls = NCLASS - 1;
+      }
     }
     for (int k = 0; k < NCLASS; ++k) {
       const uint64_t m = __ballot(cls == k);
@@ -378,14 +395,38 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
 // VGPRs; each candidate's log row is wave-uniform and is read with scalar
 // loads, so the fold is two FP64 VALU operations per coordinate with no
 // vector memory traffic.  Same output as k_hub_lds.
+// Canonical fold of one receiver (registers, zero beyond D) against one
+// wave-uniform candidate log row read with scalar loads.
+template <int MAXD>
+__device__ __forceinline__ double hub_fold(const double (&pr)[MAXD], const double (&lr)[MAXD],
+                                           const double* __restrict__ lc) {
+  double acc = 0.0;
+#pragma unroll
+  for (int i0 = 0; i0 < MAXD; i0 += 16) {
+    double cv16[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i0 + i < MAXD) cv16[i] = lc[i0 + i];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i0 + i < MAXD) acc = fma(pr[i0 + i], lr[i0 + i] - cv16[i], acc);
+  }
+  return acc + 0.0;
+}
+
 template <int MAXD, typename PT>
 __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __restrict__ L,
                                                  const PT* __restrict__ P) {
+  constexpr int CH = 16;  // candidates per LDS tile
+  __shared__ double s_keys[4][WAVE][CH + 1];
+  __shared__ int64_t s_b0[4][WAVE];
+  __shared__ uint64_t s_need[4][WAVE];
   const int K = a.K, K1 = a.K + 1, D = a.D, Dp = a.Dp;
   const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   int64_t my_perf = 0;
-  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < a.n; v += nwaves) {
+  for (int64_t v = (int64_t)blockIdx.x * 4 + wv; v < a.n; v += nwaves) {
     const int64_t rp = a.rowptr[v];
     const int cv = (int)(a.rowptr[v + 1] - rp);
     const uint32_t fv = lane < K ? a.F[v * K + lane] : 0u;  // lane j holds F(v)[j]
@@ -417,8 +458,17 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
           b1 = a.segbase[r] + q;
         }
       }
-      const bool want_any = on && (!a.skip || rnew != 0);
-      if (a.skip && cand_new == 0 && __ballot(want_any) == 0) continue;
+      // which of this receiver's K+1 candidate slots need a key (bit ci)
+      uint64_t need = 0;
+      if (on) {
+        const uint64_t all = K >= 64 ? ~0ull : ((1ull << K) - 1);
+        need = (!a.skip || rnew) ? all : (cand_new & all);
+        if (excl >= 0) need &= ~(1ull << excl);
+      }
+      const bool need_v = on && b1 >= 0 && (!a.skip || rnew);  // slot K: the hub itself
+      if (__ballot(need != 0 || need_v) == 0) continue;
+      s_b0[wv][lane] = b0;
+      s_need[wv][lane] = need;
       // Receiver row in registers; coordinates beyond D are zero, so the
       // extra terms fma(0, y, acc) (y finite) leave acc unchanged.  Rows are
       // read past their end into the zeroed tail padding of P and L.
@@ -432,34 +482,37 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
         pr[i] = i < D ? pv : 0.0;
         lr[i] = i < D ? lv : 0.0;
       }
-      for (int ci = 0; ci < K1; ++ci) {
-        const bool cnew = ci < K && ((cand_new >> ci) & 1);
-        bool need;
-        int64_t pos;
-        if (ci < K) {
-          need = on && ci != excl && (!a.skip || rnew || cnew);
-          pos = b0 + ci;
-        } else {
-          need = on && b1 >= 0 && (!a.skip || rnew);
-          pos = b1;
+      // slots 0..K-1 (the hub's friends) go through an LDS tile so that the
+      // stores are contiguous runs of a receiver's segment
+      for (int c0 = 0; c0 < K; c0 += CH) {
+        for (int cj = 0; cj < CH && c0 + cj < K; ++cj) {
+          const int ci = c0 + cj;
+          const bool nd = ((need >> ci) & 1) != 0;
+          if (__ballot(nd) == 0) continue;
+          const uint32_t craw = (uint32_t)__shfl((int)fv, ci, WAVE);
+          const int64_t cidx = (int64_t)__builtin_amdgcn_readfirstlane(craw & IDMASK);
+          s_keys[wv][lane][cj] = hub_fold<MAXD>(pr, lr, L + cidx * Dp);  // scalar loads
+          my_perf += nd ? 1 : 0;
         }
-        if (__ballot(need) == 0) continue;
-        const uint32_t craw = ci < K ? (uint32_t)__shfl((int)fv, ci, WAVE) : (uint32_t)v;
-        const int64_t cidx = (int64_t)__builtin_amdgcn_readfirstlane(craw & IDMASK);
-        const double* lc = L + cidx * Dp;  // wave-uniform: scalar loads
-        double acc = 0.0;
-#pragma unroll
-        for (int i0 = 0; i0 < MAXD; i0 += 16) {
-          double cv16[16];
-#pragma unroll
-          for (int i = 0; i < 16; ++i)
-            if (i0 + i < MAXD) cv16[i] = lc[i0 + i];
-#pragma unroll
-          for (int i = 0; i < 16; ++i)
-            if (i0 + i < MAXD) acc = fma(pr[i0 + i], lr[i0 + i] - cv16[i], acc);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int g = 0; g < WAVE / 4; ++g) {  // 4 receivers x 16 consecutive slots per store
+          const int rl = 4 * g + (lane >> 4);
+          const int cj = lane & 15;
+          const int ci = c0 + cj;
+          if (k0 + rl < nR && ci < K && ((s_need[wv][rl] >> ci) & 1))
+            a.seg[s_b0[wv][rl] + ci] = s_keys[wv][rl][cj];
         }
-        if (need) {
-          a.seg[pos] = acc + 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      // slot K: the hub itself, a co-friend candidate of each of its friends
+      if (__ballot(need_v)) {
+        const double key = hub_fold<MAXD>(pr, lr, L + v * Dp);
+        if (need_v) {
+          a.seg[b1] = key;
           ++my_perf;
         }
       }
@@ -505,21 +558,115 @@ __device__ __forceinline__ int tab_insert(uint32_t* tab, uint32_t mask, uint32_t
   }
 }
 
-template <int CAP, typename PT, bool SEG>
-__global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restrict__ list,
-                                              const int32_t* __restrict__ count) {
+// Block-wide exclusive scan of one int64 per thread (NW waves).
+template <int NW>
+__device__ __forceinline__ int64_t block_exscan_nw(int64_t v, int64_t* sh /*[NW]*/) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  int64_t incl = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int64_t t = (int64_t)shfl_u64((uint64_t)incl, max(lane - o, 0));
+    if (lane >= o) incl += t;
+  }
+  if (lane == WAVE - 1) sh[wave] = incl;
+  __syncthreads();
+  int64_t off = 0;
+  for (int w = 0; w < wave; ++w) off += sh[w];
+  __syncthreads();
+  return off + incl - v;
+}
+
+// Block-wide minimum of one double per thread (NW waves).
+template <int NW>
+__device__ __forceinline__ double block_min(double v, double* sh /*[NW]*/) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const double t = __longlong_as_double((long long)shfl_xor_u64((uint64_t)__double_as_longlong(v), o));
+    v = fmin(v, t);
+  }
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = sh[0];
+  for (int w = 1; w < NW; ++w) m = fmin(m, sh[w]);
+  __syncthreads();
+  return m;
+}
+
+template <int NW>
+__device__ __forceinline__ int64_t block_sum_nw(int64_t v, int64_t* sh /*[NW]*/) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += (int64_t)shfl_xor_u64((uint64_t)v, o);
+  if (lane_id() == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int64_t t = 0;
+  for (int w = 0; w < NW; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// Lanes 0..K-1 of a wave write receiver x's new list.  An index outside
+// [0, n) (impossible for a correct list) is never written: the lane keeps the
+// old entry and the round reports an internal error.
+__device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, int lane, uint64_t lk, uint32_t li,
+                                          const uint32_t* s_fx, int64_t& my_upd, int64_t& my_err) {
+  bool bad = false;
+  if (lane < K) {
+    uint32_t id = li;
+    double key = bits_key(lk);
+    if ((int64_t)(id & IDMASK) >= a.n) {
+      bad = true;
+      id = s_fx[lane] & IDMASK;
+      key = a.keys[x * K + lane];
+    }
+    a.Fn[x * K + lane] = id;
+    a.keysn[x * K + lane] = key;
+  }
+  const uint64_t um = __ballot(lane < K && !bad && (li & NEWBIT));
+  const uint64_t bm = __ballot(bad);
+  if (lane == 0) {
+    my_upd += (int64_t)__popcll(um);
+    my_err += (int64_t)__popcll(bm);
+  }
+}
+
+// Receiver kernel.  CAP: hash-table slots in LDS (0: per-block region of
+// global memory sized per receiver); SEG: keys come from the hub kernel's
+// segments (hub form) instead of being computed here (pull form); NW: waves
+// per block.  Classes with CAP > 8192 size their tables optimistically and
+// hand a receiver that overflows to the global-memory class.
+constexpr int SEL_BINS = 1024;   // histogram bins of the threshold selection
+constexpr int SEL_SURV = 256;    // survivors handled by the fast selection path
+
+template <int CAP, typename PT, bool SEG, int NW>
+__global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restrict__ lists,
+                                                  int32_t* __restrict__ counts, int cls) {
+  constexpr int NT = NW * 64;
   constexpr bool GLOB = (CAP == 0);
   constexpr bool BIG = (CAP > 8192);  // table in LDS, candidate list in global memory
+  constexpr bool GUARD = BIG;
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
+  constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
+  // a guarded class overshoots LIMIT by at most one batch (4 per thread)
+  static_assert(!BIG || LIMIT + 4 * NT <= BIG_CAND, "candidate list of the big classes too small");
   __shared__ uint32_t s_tab[GLOB ? 1 : CAP];
   __shared__ uint32_t s_cid[CC];
   __shared__ double s_ckey[SEG ? CC : 1];
   __shared__ uint32_t s_fx[WAVE];
-  __shared__ uint64_t s_lk[3][WAVE];
-  __shared__ uint32_t s_li[3][WAVE];
+  __shared__ uint64_t s_lk[NW - 1][WAVE];
+  __shared__ uint32_t s_li[NW - 1][WAVE];
+  // selection scratch: reuses the hash table's LDS (dead after phase C) when
+  // it is large enough
+  constexpr bool ALIAS = !GLOB && CAP >= 2048;
+  __shared__ int32_t s_hist_d[(SEG && !ALIAS) ? SEL_BINS : 1];
+  __shared__ uint64_t s_sk_d[(SEG && !ALIAS) ? SEL_SURV : 1];
+  __shared__ uint32_t s_si_d[(SEG && !ALIAS) ? SEL_SURV : 1];
+  int32_t* s_hist = ALIAS ? reinterpret_cast<int32_t*>(s_tab) : s_hist_d;
+  uint64_t* s_sk = ALIAS ? reinterpret_cast<uint64_t*>(s_tab + SEL_BINS) : s_sk_d;
+  uint32_t* s_si = ALIAS ? reinterpret_cast<uint32_t*>(s_tab + SEL_BINS + 2 * SEL_SURV) : s_si_d;
   __shared__ uint64_t s_tau;
-  __shared__ int s_ncand;
-  __shared__ int64_t s_red[4];
+  __shared__ int s_ncand, s_nuniq, s_over, s_ns, s_bstar;
+  __shared__ int64_t s_red[NW];
+  __shared__ double s_dred[NW];
 
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -528,15 +675,17 @@ __global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restr
   const int D = a.D, Dp = a.Dp;
   const int64_t n = a.n;
   const int64_t half = a.gstride / 2;
+  const int32_t* list = lists + (int64_t)cls * n;
   uint32_t* tab = GLOB ? a.gtab + (int64_t)blockIdx.x * a.gstride : s_tab;
   uint32_t* cid = GLOB ? a.gcand + (int64_t)blockIdx.x * half
                        : (BIG ? a.bcand + (int64_t)blockIdx.x * BIG_CAND : s_cid);
   double* ckey = SEG ? (GLOB ? a.gckey + (int64_t)blockIdx.x * half
                              : (BIG ? a.bckey + (int64_t)blockIdx.x * BIG_CAND : s_ckey))
                      : nullptr;
+  const int64_t ccap = GLOB ? half : (BIG ? (int64_t)BIG_CAND : (int64_t)CC);  // candidate-list capacity
   const PT* P = reinterpret_cast<const PT*>(a.P);
-  const int nitems = *count;
-  int64_t my_evals = 0, my_perf = 0, my_upd = 0;
+  const int nitems = counts[cls];
+  int64_t my_evals = 0, my_perf = 0, my_upd = 0, my_err = 0;
 
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int64_t x = list[item];
@@ -552,11 +701,14 @@ __global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restr
       while ((int64_t)cap < need2) cap <<= 1;
     }
     const uint32_t mask = cap - 1;
+    int64_t item_evals = 0;
 
     // A: clear
-    for (uint32_t s = tid; s < cap; s += 256) tab[s] = EMPTY;
+    for (uint32_t s = tid; s < cap; s += NT) tab[s] = EMPTY;
     if (tid == 0) {
       s_ncand = 0;
+      s_nuniq = 0;
+      s_over = 0;
       s_tau = key_bits(a.keys[x * K + K - 1]);
     }
     __syncthreads();
@@ -569,14 +721,13 @@ __global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restr
       tab_insert(tab, mask, (uint32_t)x, EXCLBIT);
     }
     __syncthreads();
-    // C: enumerate candidate occurrences, four per thread in flight (uniform
-    // trip count across the block)
-    for (int64_t t0 = 0; t0 < T; t0 += 4 * 256) {
+    // C: enumerate candidate occurrences, four per thread in flight
+    for (int64_t t0 = 0; t0 < T; t0 += 4 * NT) {
       uint32_t z[4], nw[4];
       int res[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int64_t t = t0 + tid + 256 * u;
+        const int64_t t = t0 + tid + NT * u;
         z[u] = 0;
         nw[u] = 0;
         if (t < c) {
@@ -601,17 +752,19 @@ __global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restr
           nw[u] = (w | zr) & NEWBIT;
         }
       }
+      int fresh = 0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         res[u] = 0;
-        if (t0 + tid + 256 * u < T) {
+        if (t0 + tid + NT * u < T) {
           res[u] = tab_insert(tab, mask, z[u], a.skip ? nw[u] : NEWBIT);
-          my_evals += res[u] & 1;
+          fresh += res[u] & 1;
         }
       }
+      item_evals += fresh;
       double kv[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) kv[u] = (SEG && (res[u] & 2)) ? a.seg[sbase + t0 + tid + 256 * u] : 0.0;
+      for (int u = 0; u < 4; ++u) kv[u] = (SEG && (res[u] & 2)) ? a.seg[sbase + t0 + tid + NT * u] : 0.0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const bool app = (res[u] & 2) != 0;
@@ -622,83 +775,186 @@ __global__ __launch_bounds__(256) void k_recv(JoinArgs a, const int32_t* __restr
           base = __shfl(base, 0, WAVE);
           if (app) {
             const int at = base + (int)rank_in(m);
-            cid[at] = z[u];
-            if (SEG) ckey[at] = kv[u];
+            if (at < ccap) {
+              cid[at] = z[u];
+              if (SEG) ckey[at] = kv[u];
+            } else if (GUARD) {
+              s_over = 1;  // list full: the global-memory class redoes this receiver
+            } else {
+              ++my_err;  // cannot happen with exact sizing
+            }
           }
         }
       }
+      if (GUARD) {
+        if (fresh && atomicAdd(&s_nuniq, fresh) + fresh > LIMIT) s_over = 1;
+        __syncthreads();
+        const bool over = s_over != 0;
+        __syncthreads();
+        if (over) break;
+      }
     }
     __syncthreads();
-    // D: keys, compare-to-last filter, wave merges
-    const int ncand = s_ncand;
-    uint64_t lk = KEY_SENTINEL;
-    uint32_t li = IDMASK;
-    if (wave == 0 && lane < K) {
-      lk = key_bits(a.keys[x * K + lane]);
-      li = s_fx[lane] & IDMASK;
-    }
-    const PT* px = P + x * D;
-    const double* lx = a.L + x * Dp;
-    for (int i0 = wave * WAVE; i0 < ncand; i0 += 256) {
-      const int i = i0 + lane;
-      const bool valid = i < ncand;
-      uint64_t kb = KEY_SENTINEL;
-      uint32_t z = IDMASK;
-      if (valid) {
-        z = cid[i];
-        if (SEG)
-          kb = key_bits(ckey[i]);
-        else
-          kb = key_bits(canonical_key(px, lx, a.L + (int64_t)z * Dp, D));
+    if (GUARD && s_over) {  // table too small: the global-memory class redoes this receiver
+      if (tid == 0) {
+        const int pos = atomicAdd(&counts[NCLASS - 1], 1);
+        lists[(int64_t)(NCLASS - 1) * n + pos] = (int32_t)x;
       }
-      my_perf += (!SEG && valid) ? 1 : 0;
-      const uint64_t kk = shfl_u64(lk, K - 1);
-      const uint32_t ki = shfl_u32(li, K - 1);
-      const uint64_t tau = *(volatile uint64_t*)&s_tau;
-      const bool surv = valid && kb <= tau && ke_less(kb, z, kk, ki);
-      const uint64_t sm = __ballot(surv);
-      if (sm) {
-        if (__popcll(sm) <= 8) {
-          // few survivors: insert them one by one
-          uint64_t mm = sm;
-          while (mm) {
-            const int src = __ffsll((unsigned long long)mm) - 1;
-            mm &= mm - 1;
-            const uint64_t ck = shfl_u64(kb, src);
-            const uint32_t cz = shfl_u32(z, src) | NEWBIT;
-            if (ke_less(ck, cz, shfl_u64(lk, K - 1), shfl_u32(li, K - 1))) wave_insert(lk, li, ck, cz);
-          }
-        } else {
-          uint64_t bk = surv ? kb : KEY_SENTINEL;
-          uint32_t bi = surv ? (z | NEWBIT) : IDMASK;
-          wave_sort(bk, bi);
-          wave_merge(lk, li, bk, bi);
+      __syncthreads();
+      continue;
+    }
+    my_evals += item_evals;
+    // (s_ncand exceeds the list capacity only after a reported internal error)
+    const int ncand = (int)min((int64_t)s_ncand, ccap);
+    const double* kx = a.keys + x * K;
+
+    bool done = false;
+    if (SEG) {
+      // D (hub form): every key is known.  Only entries with key <= tau0 (the
+      // current K-th) can be in the result.  Histogram them over [kmin, tau0]
+      // with a monotone binning, find the first bin b* where the count
+      // reaches K: every entry in a later bin has K strictly better ones.
+      const double tau0 = kx[K - 1];
+      double kmin = kx[0];
+      for (int i = tid; i < ncand; i += NT) kmin = fmin(kmin, ckey[i]);
+      kmin = block_min<NW>(kmin, s_dred);
+      const double scale = tau0 > kmin ? (double)SEL_BINS / (tau0 - kmin) : 0.0;
+      auto bin_of = [&](double k) {
+        const int b = (int)((k - kmin) * scale);
+        return b < 0 ? 0 : (b >= SEL_BINS ? SEL_BINS - 1 : b);
+      };
+      for (int b = tid; b < SEL_BINS; b += NT) s_hist[b] = 0;
+      if (tid == 0) s_ns = 0;
+      __syncthreads();
+      for (int i = tid; i < ncand; i += NT) {
+        const double k = ckey[i];
+        if (k <= tau0) atomicAdd(&s_hist[bin_of(k)], 1);
+      }
+      if (tid < K) atomicAdd(&s_hist[bin_of(kx[tid])], 1);
+      __syncthreads();
+      {  // b*: first bin whose inclusive prefix count reaches K
+        constexpr int PER = SEL_BINS / NT > 0 ? SEL_BINS / NT : 1;
+        int loc[PER];
+        int64_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int b = tid * PER + q;
+          loc[q] = b < SEL_BINS ? s_hist[b] : 0;
+          sum += loc[q];
         }
-        const uint64_t nk = shfl_u64(lk, K - 1);
-        if (lane == 0 && nk < tau) atomicMin((unsigned long long*)&s_tau, (unsigned long long)nk);
+        int64_t run = block_exscan_nw<NW>(sum, s_red);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int b = tid * PER + q;
+          if (b < SEL_BINS && run < K && run + loc[q] >= K) s_bstar = b;
+          run += loc[q];
+        }
+      }
+      __syncthreads();
+      const int bstar = s_bstar;
+      for (int i = tid; i < ncand; i += NT) {
+        const double k = ckey[i];
+        if (k <= tau0 && bin_of(k) <= bstar) {
+          const int pos = atomicAdd(&s_ns, 1);
+          if (pos < SEL_SURV) {
+            s_sk[pos] = key_bits(k);
+            s_si[pos] = cid[i] | NEWBIT;
+          }
+        }
+      }
+      if (tid < K && bin_of(kx[tid]) <= bstar) {
+        const int pos = atomicAdd(&s_ns, 1);
+        if (pos < SEL_SURV) {
+          s_sk[pos] = key_bits(kx[tid]);
+          s_si[pos] = s_fx[tid] & IDMASK;
+        }
+      }
+      __syncthreads();
+      const int ns = s_ns;
+      if (ns <= SEL_SURV) {
+        done = true;
+        if (wave == 0) {
+          uint64_t lk = KEY_SENTINEL;
+          uint32_t li = IDMASK;
+          for (int b0 = 0; b0 < ns; b0 += WAVE) {
+            const bool ok = b0 + lane < ns;
+            uint64_t bk = ok ? s_sk[b0 + lane] : KEY_SENTINEL;
+            uint32_t bi = ok ? s_si[b0 + lane] : IDMASK;
+            wave_sort(bk, bi);
+            wave_merge(lk, li, bk, bi);
+          }
+          write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
+        }
       }
     }
-    // E: combine the four wave lists
-    if (wave > 0) {
-      s_lk[wave - 1][lane] = lk;
-      s_li[wave - 1][lane] = li;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      for (int w = 0; w < 3; ++w) wave_merge(lk, li, s_lk[w][lane], s_li[w][lane]);
-      if (lane < K) {
-        a.Fn[x * K + lane] = li;
-        a.keysn[x * K + lane] = bits_key(lk);
+    if (!done) {  // block-uniform
+      // D: per-wave running top-K: compare-to-last filter (the paper's
+      // NavigableSet insertion, Section 4.2) and merges in registers
+      uint64_t lk = KEY_SENTINEL;
+      uint32_t li = IDMASK;
+      if (wave == 0 && lane < K) {
+        lk = key_bits(kx[lane]);
+        li = s_fx[lane] & IDMASK;
       }
-      const uint64_t um = __ballot(lane < K && (li & NEWBIT));
-      if (lane == 0) my_upd += (int64_t)__popcll(um);
+      const PT* px = P + x * D;
+      const double* lx = a.L + x * Dp;
+      for (int i0 = wave * WAVE; i0 < ncand; i0 += NT) {
+        const int i = i0 + lane;
+        const bool valid = i < ncand;
+        uint64_t kb = KEY_SENTINEL;
+        uint32_t z = IDMASK;
+        if (valid) {
+          z = cid[i];
+          if (SEG)
+            kb = key_bits(ckey[i]);
+          else
+            kb = key_bits(canonical_key(px, lx, a.L + (int64_t)z * Dp, D));
+        }
+        my_perf += (!SEG && valid) ? 1 : 0;
+        const uint64_t kk = shfl_u64(lk, K - 1);
+        const uint32_t ki = shfl_u32(li, K - 1);
+        const uint64_t tau = *(volatile uint64_t*)&s_tau;
+        const bool surv = valid && kb <= tau && ke_less(kb, z, kk, ki);
+        const uint64_t sm = __ballot(surv);
+        if (sm) {
+          if (__popcll(sm) <= 8) {
+            uint64_t mm = sm;
+            while (mm) {
+              const int src = __ffsll((unsigned long long)mm) - 1;
+              mm &= mm - 1;
+              const uint64_t ck = shfl_u64(kb, src);
+              const uint32_t cz = shfl_u32(z, src) | NEWBIT;
+              if (ke_less(ck, cz, shfl_u64(lk, K - 1), shfl_u32(li, K - 1))) wave_insert(lk, li, ck, cz);
+            }
+          } else {
+            uint64_t bk = surv ? kb : KEY_SENTINEL;
+            uint32_t bi = surv ? (z | NEWBIT) : IDMASK;
+            wave_sort(bk, bi);
+            wave_merge(lk, li, bk, bi);
+          }
+          const uint64_t nk = shfl_u64(lk, K - 1);
+          if (lane == 0 && nk < tau) atomicMin((unsigned long long*)&s_tau, (unsigned long long)nk);
+        }
+      }
+      // E: combine the wave lists
+      if (wave > 0) {
+        s_lk[wave - 1][lane] = lk;
+        s_li[wave - 1][lane] = li;
+      }
+      __syncthreads();
+      if (wave == 0) {
+        for (int w = 0; w < NW - 1; ++w) wave_merge(lk, li, s_lk[w][lane], s_li[w][lane]);
+        write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
+      }
     }
     __syncthreads();
   }
-  const int64_t ev = block_sum(my_evals, s_red);
-  const int64_t pf = block_sum(my_perf, s_red);
-  const int64_t up = block_sum(my_upd, s_red);
+  const int64_t ev = block_sum_nw<NW>(my_evals, s_red);
+  const int64_t pf = block_sum_nw<NW>(my_perf, s_red);
+  const int64_t up = block_sum_nw<NW>(my_upd, s_red);
+  const int64_t er = block_sum_nw<NW>(my_err, s_red);
   if (tid == 0) {
+    if (er) atomicAdd((unsigned long long*)&a.stats[STAT_ERR], (unsigned long long)er);
     if (ev) atomicAdd((unsigned long long*)&a.stats[STAT_EVALS], (unsigned long long)ev);
     if (pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
     if (up) atomicAdd((unsigned long long*)&a.stats[STAT_UPDATES], (unsigned long long)up);
@@ -780,20 +1036,23 @@ hipError_t launch_bin(const Ctx& c) {
 
 template <int CAP, typename PT, bool SEG>
 static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
-  auto kern = k_recv<CAP, PT, SEG>;
-  int grid;
-  if (CAP == 0) {
-    grid = c.gblocks;
+  if constexpr (CAP == 0) {
+    // few, very large receivers: 1024 threads each, global-memory tables
+    hipLaunchKernelGGL((k_recv<CAP, PT, SEG, 16>), dim3(c.gblocks), dim3(1024), 0, c.stream, a, c.class_list,
+                       c.class_count, cls);
+    return hipGetLastError();
   } else {
+    auto kern = k_recv<CAP, PT, SEG, 4>;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) {
+      (void)hipGetLastError();
       per_cu = 1;
-    grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
-    if (CAP > 8192) grid = std::min(grid, c.bblocks);
+    }
+    int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
+    if (CAP > 8192) grid = std::min(grid, c.bblocks);  // one global candidate region per block
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.class_list, c.class_count, cls);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.class_list + (int64_t)cls * c.n,
-                     c.class_count + cls);
-  return hipGetLastError();
 }
 
 template <typename PT, bool SEG>
@@ -880,9 +1139,9 @@ hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out) {
   return hipGetLastError();
 }
 
-hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F) {
+hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad) {
   const int64_t cnt = c.n * c.K;
-  hipLaunchKernelGGL(k_load_idx, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, idx, cnt, F);
+  hipLaunchKernelGGL(k_load_idx, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, idx, cnt, c.n, F, bad);
   return hipGetLastError();
 }
 

@@ -154,11 +154,14 @@ def _hub_snapshot(P, K, hub, seed):
 
 
 @pytest.mark.parametrize("flags", JOIN_FORMS, ids=["hub", "pull"])
-@pytest.mark.parametrize("n,d,K", [(3000, 6, 8), (7000, 5, 4), (40000, 4, 4)])
+@pytest.mark.parametrize("n,d,K", [(3000, 6, 8), (7000, 5, 4), (18005, 4, 4), (30000, 4, 4),
+                                   (40000, 4, 4)])
 def test_hub_receiver_large_tables(n, d, K, flags):
-    # the receiver with n-1 co-friends needs a 16384-slot LDS table (n=3000,
-    # K=8), a 32768-slot one (n=7000, K=4) and the global-memory table
-    # (n=40000, K=4)
+    # The receiver with n-1 co-friends lands in the 16384-slot LDS class
+    # (n=3000 and 7000), in the 32768-slot class with about 18000 distinct
+    # candidates, more than 16384 (n=18005), in the 32768-slot class whose
+    # guard hands it to the global-memory class (n=30000), and directly in the
+    # global-memory class (n=40000).
     P = synth.dirichlet(n + 11, n, d, np.float32)
     F, k = _hub_snapshot(P, K, hub=n // 3, seed=n)
     one_round(P, d, K, seed=5, F0=F, k0=k, flags=flags)
