@@ -36,7 +36,7 @@ hipError_t dalloc(T** p, size_t count) {
 
 void free_ctx(Ctx& c) {
   void* bufs[] = {c.P,      c.L,      c.F[0],   c.F[1],      c.keys[0],     c.keys[1],  c.deg,
-                  c.fill,   c.rowptr, c.col,    c.colslot,   c.revpos,      c.segbase,  c.seg,
+                  c.fill,   c.rowptr, c.col,    c.colslot,   c.seg,
                   c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.gckey, c.bcand, c.bckey,
                   c.dstats, c.dflag};
   for (void* b : bufs)
@@ -117,8 +117,6 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   if (e == hipSuccess) e = dalloc(&c.rowptr, (size_t)n + 1);
   if (e == hipSuccess) e = dalloc(&c.col, nK);
   if (e == hipSuccess) e = dalloc(&c.colslot, nK);
-  if (e == hipSuccess) e = dalloc(&c.revpos, nK);
-  if (e == hipSuccess) e = dalloc(&c.segbase, (size_t)n + 1);
   if (e == hipSuccess) e = dalloc(&c.tilesum, (size_t)ntiles + 1);
   if (e == hipSuccess) e = dalloc(&c.class_count, (size_t)knnd::NCLASS);
   if (e == hipSuccess) e = dalloc(&c.class_list, (size_t)knnd::NCLASS * n);

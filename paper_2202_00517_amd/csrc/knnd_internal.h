@@ -47,9 +47,7 @@ struct Ctx {
   int64_t* rowptr = nullptr;  // [n+1]
   uint32_t* col = nullptr;    // [nK]
   uint8_t* colslot = nullptr; // [nK] slot of the edge in its source's list
-  int32_t* revpos = nullptr;  // [nK] position of an edge's source in its target's co-friend list
-  int64_t* segbase = nullptr; // [n+1] candidate-segment offsets (hub form)
-  double* seg = nullptr;      // [nK(2K+1)] candidate keys (hub form)
+  double* seg = nullptr;      // [nK(2K+1)] candidate keys by snapshot edge (hub form)
   bool use_hub = false;
   int64_t* tilesum = nullptr;
   int32_t* class_count = nullptr;  // [NCLASS]
@@ -78,8 +76,7 @@ struct JoinArgs {
   const int64_t* rowptr;
   const uint32_t* col;
   const uint8_t* colslot;
-  const int32_t* revpos;
-  const int64_t* segbase;
+  int64_t nKK;  // n*K*K: offset of the FC part of seg (DI part at 2nKK)
   double* seg;
   uint32_t* Fn;
   double* keysn;

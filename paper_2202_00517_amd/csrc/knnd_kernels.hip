@@ -211,10 +211,9 @@ __global__ void k_scan_add(int64_t* __restrict__ rowptr, int64_t n, const int64_
 }
 
 // Edge e = x*K + j (x -> v = F[x][j]) lands at position q of coF(v):
-// col[rowptr[v] + q] = x | new-flag, colslot[...] = j, revpos[e] = q.
+// col[rowptr[v] + q] = x | new-flag, colslot[...] = j.
 __global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, const int64_t* __restrict__ rowptr,
-                          int32_t* __restrict__ fill, uint32_t* __restrict__ col, uint8_t* __restrict__ colslot,
-                          int32_t* __restrict__ revpos) {
+                          int32_t* __restrict__ fill, uint32_t* __restrict__ col, uint8_t* __restrict__ colslot) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t raw = F[e];
     const uint32_t v = raw & IDMASK;
@@ -223,7 +222,6 @@ __global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, con
     const int64_t x = e / K;
     col[pos] = (uint32_t)x | (raw & NEWBIT);
     colslot[pos] = (uint8_t)(e - x * K);
-    revpos[e] = q;
   }
 }
 
@@ -292,9 +290,14 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* sh /*[4]*/) {
 //   r in F(v):        friends of a co-friend   -> F(v) \ {r}, and the co-friend v
 // The K+1 candidate log rows are staged in LDS once per hub; each wave takes
 // floor(64/(K+1)) receivers at a time, one lane per candidate, and folds the
-// canonical FP64 key.  Keys go to fixed slots of the receiver's segment, laid
-// out in the receiver's own enumeration order:
-//   [c co-friends][K x K friends of friends][c x K friends of co-friends]
+// canonical FP64 key.  Keys go to fixed slots indexed by the edges of the
+// round-start snapshot (seg = [FF | FC | DI]):
+//   friends of friends    x -> v = F(x)[j] -> F(v)[s]:   FF + (x*K + j)*K + s
+//   friends of co-friends w -> x (slot sp), F(w)[s]:     FC + (w*K + sp)*K + s
+//   the co-friend itself  w -> x (slot sp):              DI + w*K + sp
+// with FF = 0, FC = nK^2 and DI = 2nK^2.  A hub v writes, for a co-friend r
+// (edge r -> v at slot j), the run FF + (r*K + j)*K + [0, K); for its friends
+// the contiguous block FC + v*K^2 + [0, K^2) and DI + v*K + [0, K).
 // Pairs whose two edges were both present one round earlier are skipped
 // (their candidate cannot enter, see the receiver kernel).
 // ---------------------------------------------------------------------------
@@ -348,18 +351,15 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
         const uint32_t e = a.col[rp + k];
         r = e & IDMASK;
         rnew = e & NEWBIT;
-        const int64_t cr = a.rowptr[r + 1] - a.rowptr[r];
-        b0 = a.segbase[r] + cr + (int64_t)a.colslot[rp + k] * K;
+        b0 = (r * K + a.colslot[rp + k]) * K;  // FF
       } else {
         const int sp = k - cv;
         const uint32_t e = s_fv[sp];
         r = e & IDMASK;
         rnew = e & NEWBIT;
         excl = sp;
-        const int64_t q = a.revpos[v * K + sp];
-        const int64_t cr = a.rowptr[r + 1] - a.rowptr[r];
-        b0 = a.segbase[r] + cr + (int64_t)K * K + q * K;
-        b1 = a.segbase[r] + q;
+        b0 = a.nKK + (v * K + sp) * K;  // FC
+        b1 = 2 * a.nKK + v * K + sp;    // DI
       }
       const PT* pr = P + r * D;
       const double* lr = a.L + r * Dp;
@@ -445,17 +445,14 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
           const uint32_t e = a.col[rp + k];
           r = e & IDMASK;
           rnew = e & NEWBIT;
-          const int64_t cr = a.rowptr[r + 1] - a.rowptr[r];
-          b0 = a.segbase[r] + cr + (int64_t)a.colslot[rp + k] * K;
+          b0 = (r * K + a.colslot[rp + k]) * K;  // FF
         } else {
           const int sp = k - cv;
           r = fsp & IDMASK;
           rnew = fsp & NEWBIT;
           excl = sp;
-          const int64_t q = a.revpos[v * K + sp];
-          const int64_t cr = a.rowptr[r + 1] - a.rowptr[r];
-          b0 = a.segbase[r] + cr + (int64_t)K * K + q * K;
-          b1 = a.segbase[r] + q;
+          b0 = a.nKK + (v * K + sp) * K;  // FC
+          b1 = 2 * a.nKK + v * K + sp;    // DI
         }
       }
       // which of this receiver's K+1 candidate slots need a key (bit ci)
@@ -693,7 +690,6 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
     const int64_t c = a.rowptr[x + 1] - rp;
     const int64_t KK = (int64_t)K * K;
     const int64_t T = c + KK + c * K;
-    const int64_t sbase = SEG ? a.segbase[x] : 0;
     uint32_t cap = (uint32_t)CAP;
     if (GLOB) {
       const int64_t need2 = 2 * table_need(c, K, n);
@@ -702,6 +698,9 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
     }
     const uint32_t mask = cap - 1;
     int64_t item_evals = 0;
+    // the round-start K-th key: a candidate with a larger key cannot enter
+    // (the paper's compare-to-last, Section 4.2)
+    const double tau0 = a.keys[x * K + K - 1];
 
     // A: clear
     for (uint32_t s = tid; s < cap; s += NT) tab[s] = EMPTY;
@@ -724,17 +723,20 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
     // C: enumerate candidate occurrences, four per thread in flight
     for (int64_t t0 = 0; t0 < T; t0 += 4 * NT) {
       uint32_t z[4], nw[4];
+      int64_t kp[4];  // key slot of the occurrence (hub form)
       int res[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int64_t t = t0 + tid + NT * u;
         z[u] = 0;
         nw[u] = 0;
-        if (t < c) {
+        kp[u] = 0;
+        if (t < c) {  // co-friend w (edge w -> x at slot sp)
           const uint32_t w = a.col[rp + t];
           z[u] = w & IDMASK;
           nw[u] = w & NEWBIT;
-        } else if (t < c + KK) {
+          if (SEG) kp[u] = 2 * a.nKK + (int64_t)(w & IDMASK) * K + a.colslot[rp + t];
+        } else if (t < c + KK) {  // friend of friend: row j of F(F(x))
           const int uu = (int)(t - c);
           const int j = uu / K;
           const int s = uu - j * K;
@@ -742,7 +744,8 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
           const uint32_t zr = a.F[(int64_t)(v & IDMASK) * K + s];
           z[u] = zr & IDMASK;
           nw[u] = (v | zr) & NEWBIT;
-        } else if (t < T) {
+          if (SEG) kp[u] = x * KK + uu;
+        } else if (t < T) {  // friend of co-friend w
           const int64_t uu = t - c - KK;
           const int64_t q = uu / K;
           const int s = (int)(uu - q * K);
@@ -750,6 +753,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
           const uint32_t zr = a.F[(int64_t)(w & IDMASK) * K + s];
           z[u] = zr & IDMASK;
           nw[u] = (w | zr) & NEWBIT;
+          if (SEG) kp[u] = a.nKK + ((int64_t)(w & IDMASK) * K + a.colslot[rp + q]) * K + s;
         }
       }
       int fresh = 0;
@@ -764,10 +768,10 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
       item_evals += fresh;
       double kv[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) kv[u] = (SEG && (res[u] & 2)) ? a.seg[sbase + t0 + tid + NT * u] : 0.0;
+      for (int u = 0; u < 4; ++u) kv[u] = (SEG && (res[u] & 2)) ? a.seg[kp[u]] : 0.0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const bool app = (res[u] & 2) != 0;
+        const bool app = (res[u] & 2) != 0 && (!SEG || kv[u] <= tau0);
         const uint64_t m = __ballot(app);
         if (m) {
           int base = 0;
@@ -809,12 +813,28 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
     const double* kx = a.keys + x * K;
 
     bool done = false;
-    if (SEG) {
-      // D (hub form): every key is known.  Only entries with key <= tau0 (the
-      // current K-th) can be in the result.  Histogram them over [kmin, tau0]
-      // with a monotone binning, find the first bin b* where the count
-      // reaches K: every entry in a later bin has K strictly better ones.
-      const double tau0 = kx[K - 1];
+    if (SEG && ncand <= 2 * WAVE) {
+      // D (hub form, short list): wave 0 sorts the listed candidates and
+      // merges them into the old list
+      done = true;
+      if (wave == 0) {
+        uint64_t lk = lane < K ? key_bits(kx[lane]) : KEY_SENTINEL;
+        uint32_t li = lane < K ? (s_fx[lane] & IDMASK) : IDMASK;
+        for (int b0 = 0; b0 < ncand; b0 += WAVE) {
+          const bool ok = b0 + lane < ncand;
+          uint64_t bk = ok ? key_bits(ckey[b0 + lane]) : KEY_SENTINEL;
+          uint32_t bi = ok ? (cid[b0 + lane] | NEWBIT) : IDMASK;
+          wave_sort(bk, bi);
+          wave_merge(lk, li, bk, bi);
+        }
+        write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
+      }
+    } else if (SEG) {
+      // D (hub form): every key is known and every listed candidate has key
+      // <= tau0.  Histogram the candidates and the old list over
+      // [kmin, tau0] with a monotone binning and find the first bin b* where
+      // the count reaches K: every entry in a later bin has K strictly better
+      // ones.
       double kmin = kx[0];
       for (int i = tid; i < ncand; i += NT) kmin = fmin(kmin, ckey[i]);
       kmin = block_min<NW>(kmin, s_dred);
@@ -1021,9 +1041,8 @@ hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.fill, c.n);
   hipLaunchKernelGGL(k_degree, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.deg);
   launch_scan(c, 1, 0, c.rowptr);
-  if (c.use_hub) launch_scan(c, c.K + 1, (int64_t)c.K * c.K, c.segbase);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.rowptr,
-                     c.fill, c.col, c.colslot, c.revpos);
+                     c.fill, c.col, c.colslot);
   return hipGetLastError();
 }
 
@@ -1111,8 +1130,7 @@ hipError_t launch_join(const Ctx& c, int64_t* stats) {
   a.rowptr = c.rowptr;
   a.col = c.col;
   a.colslot = c.colslot;
-  a.revpos = c.revpos;
-  a.segbase = c.segbase;
+  a.nKK = c.n * (int64_t)c.K * c.K;
   a.seg = c.seg;
   a.Fn = c.F[c.cur ^ 1];
   a.keysn = c.keys[c.cur ^ 1];
