@@ -10,7 +10,11 @@ the stop test fires, lists copied to the caller's device buffer.
 value = sum over rounds of evals_alg (one KL key per receiver and distinct
 non-friend candidate, the oracle's count) / time-to-graph.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision plain]
+The default precision is mixed (BF16 MFMA screen with FP64 rescue, bit-exact
+output); the plain FP64 descent of the same workload is timed beside it and
+reported under "plain" so the line carries both sides of the comparison.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision mixed|plain]
 """
 import argparse
 import json
@@ -59,7 +63,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="plain", choices=["plain"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "plain"])
+    ap.add_argument("--no-plain", action="store_true",
+                    help="with --precision mixed, skip timing the plain descent beside it")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=60_000)
@@ -84,31 +90,49 @@ def main():
     torch.cuda.set_device(dev)
     Pd = torch.from_numpy(P).to(dev)
     stream = torch.cuda.current_stream(dev)
-    prm = knnd.default_params(precision=knnd.KNND_PREC_FP64)
+    mixed = args.precision == "mixed"
+    prec = knnd.KNND_PREC_MIXED_BF16 if mixed else knnd.KNND_PREC_FP64
 
-    def step():
-        return knnd.knnd_build_ex(Pd, d, K, seed, prm, stream=stream.cuda_stream)
+    def timed(precision, tag):
+        prm = knnd.default_params(precision=precision)
 
-    for i in range(args.warmup):
-        out = step()
-        log(f"warmup {i}: rounds={out['rounds']}")
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        out = step()
+        def step():
+            return knnd.knnd_build_ex(Pd, d, K, seed, prm, stream=stream.cuda_stream)
+
+        for i in range(args.warmup):
+            out = step()
+            log(f"[{tag}] warmup {i}: rounds={out['rounds']}")
         torch.cuda.synchronize()
-        results.append((out, time.perf_counter() - ts))
-        log(f"step {i}: {1e3 * results[-1][1]:.1f} ms, rounds={out['rounds']}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        results = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            out = step()
+            torch.cuda.synchronize()
+            results.append((out, time.perf_counter() - ts))
+            log(f"[{tag}] step {i}: {1e3 * results[-1][1]:.1f} ms, rounds={out['rounds']}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        evals = [sum(s["evals_alg"] for s in o["stats"]) for o, _ in results]
+        assert len(set(evals)) == 1, "evaluation counts differ between identical runs"
+        return results, elapsed, evals[0]
 
-    evals = [sum(s["evals_alg"] for s in o["stats"]) for o, _ in results]
-    assert len(set(evals)) == 1, "evaluation counts differ between identical runs"
+    results, elapsed, ev = timed(prec, args.precision)
+    evals = [ev]
     ms_per_step = 1e3 * elapsed / args.steps
     value = evals[0] / (elapsed / args.steps)
     last = results[-1][0]
+    plain = None
+    if mixed and not args.no_plain:
+        pres, pel, pev = timed(knnd.KNND_PREC_FP64, "plain")
+        pl = pres[-1][0]
+        same = (np.array_equal(pl["idx"].cpu().numpy(), last["idx"].cpu().numpy())
+                and np.array_equal(pl["kl"].cpu().numpy(), last["kl"].cpu().numpy()))
+        assert pev == ev and same, "mixed and plain descents differ"
+        plain = {"value": pev / (pel / args.steps), "unit": "evals/s",
+                 "ms_per_step": 1e3 * pel / args.steps,
+                 "speedup_mixed_over_plain": pel / elapsed,
+                 "identical_graph": bool(same)}
 
     # roofline of the dominant kernel: the join (steps a2-a5), all launches of
     # one round; algorithmic bytes = keys computed x (8 D + 4) bytes
@@ -134,7 +158,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "bf16+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"Dirichlet(1^{D}) points on the {d}-simplex, FP32 storage, "
                                f"n={n}, K={K}, seed={seed}, whole descent to the stop test",
@@ -143,8 +167,11 @@ def main():
         "rounds": last["rounds"],
         "evals_alg": evals[0],
         "per_round_ms": [round(s["ms"], 3) for s in last["stats"]],
+        "rescues": sum(s["rescues"] for s in last["stats"]),
         "roofline": roofline,
     }
+    if plain is not None:
+        line["plain"] = plain
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle round 1 on {args.cpu_receivers} receivers, {threads} threads")

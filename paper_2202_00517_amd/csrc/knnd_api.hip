@@ -7,6 +7,7 @@
 // synchronises once, to read the counters the stop test needs (Section 3.3).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -38,7 +39,7 @@ void free_ctx(Ctx& c) {
   void* bufs[] = {c.P,      c.L,      c.F[0],   c.F[1],      c.keys[0],     c.keys[1],  c.deg,
                   c.fill,   c.rowptr, c.col,    c.colslot,   c.seg,
                   c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.gckey, c.bcand, c.bckey,
-                  c.dstats, c.dflag};
+                  c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c.hstats) (void)hipHostFree(c.hstats);
@@ -62,7 +63,6 @@ int resolve_params(const knnd_params* p, int64_t n, knnd_params* out) {
   if (out->max_rounds <= 0) out->max_rounds = 100;
   if (out->dtype != KNND_F32 && out->dtype != KNND_F64) return KNND_ERR_ARG;
   if (out->precision < KNND_PREC_FP64 || out->precision > KNND_PREC_MIXED_FP16) return KNND_ERR_ARG;
-  if (out->precision != KNND_PREC_FP64) return KNND_ERR_UNSUPPORTED;
   return KNND_OK;
 }
 
@@ -72,6 +72,8 @@ int check_shape(int64_t n, int32_t d, int32_t K) {
   if (d > 1 << 20) return KNND_ERR_ARG;
   return KNND_OK;
 }
+
+int prepare_mixed(Ctx& c, size_t nK);
 
 int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,
            int32_t on_device, void* stream, Ctx& c) {
@@ -134,10 +136,24 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   if (e == hipSuccess) e = hipEventCreate(&c.evj0);
   if (e == hipSuccess) e = hipEventCreate(&c.evj1);
   if (e != hipSuccess) return map_err(e);
-  // Hub form: candidate rows of a hub must fit in LDS, and the key segments
-  // (K(2K+1) doubles per point) must fit in memory; otherwise the pull form.
+  // Hub form: candidate rows of a hub must fit in LDS, and the key slots
+  // (K(2K+1) per point) must fit in memory; otherwise the pull form.  The
+  // mixed-precision form needs the hub form and D <= 64 (MFMA K dimension).
   c.use_hub = !(c.flags & KNND_FLAG_PULL) && (size_t)(K + 1) * c.Ds * sizeof(double) <= 64 * 1024;
-  if (c.use_hub && dalloc(&c.seg, nK * (size_t)(2 * K + 1)) != hipSuccess) {
+  c.mixed = c.use_hub && c.precision != KNND_PREC_FP64 && c.D <= 64;
+  if (c.mixed) {
+    c.dk = c.D <= 32 ? 32 : 64;
+    // rows of 2 dk 16-bit values: dk high parts, then dk low parts
+    if (e == hipSuccess) e = hipMalloc(&c.Ph, (size_t)n * c.dk * 4 + 64);
+    if (e == hipSuccess) e = hipMalloc(&c.Lh, (size_t)n * c.dk * 4 + 64);
+    if (e == hipSuccess) e = dalloc(&c.S, (size_t)n);
+    if (e == hipSuccess && dalloc(&c.seg32, nK * (size_t)(2 * K + 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      c.mixed = false;
+    }
+    if (e != hipSuccess) return map_err(e);
+  }
+  if (c.use_hub && !c.mixed && dalloc(&c.seg, nK * (size_t)(2 * K + 1)) != hipSuccess) {
     (void)hipGetLastError();
     c.seg = nullptr;
     c.use_hub = false;
@@ -154,6 +170,57 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   KNND_HIP(hipMemcpyAsync(&bad, c.dflag, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
   KNND_HIP(hipStreamSynchronize(c.stream));
   if (bad) return KNND_ERR_DOMAIN;
+  if (c.mixed) return prepare_mixed(c, nK);
+  return KNND_OK;
+}
+
+// Split 16-bit operand copies and the error-bound constants of the mixed
+// form.  Each operand v (x_i or log c_i) is v = hi + lo + r with
+// |r| <= u^2 |v| + 2s and |lo| <= u(1+u)|v| + 3s, where u bounds the relative
+// rounding error of one conversion to the 16-bit format (unit roundoff, plus
+// 2^-23 in case the conversion rounds through FP32 first) and s is half the
+// smallest 16-bit subnormal spacing, likewise inflated.  Dropping lo*lo and
+// the residuals costs at most (3u^2 + 3u^3)|x_i||log c_i| + 3s(|x_i| +
+// |log c_i|) + 21 s^2 per coordinate.  The products of 16-bit values are
+// exact in FP32; the sum of the 3D nonzero products and the accumulator
+// chain is charged (3D + 3) 2^-23 times the sum of their magnitudes
+// (directed rounding, any order), plus 2^-126 per term for FP32 underflow.
+// With every coordinate <= 1, every product x_i log c_i is <= 0, so the sum
+// of magnitudes is |C| itself.  Inputs with a coordinate above 1 or outside
+// the 16-bit range disable the mixed form (same results, plain speed).
+int prepare_mixed(Ctx& c, size_t nK) {
+  unsigned long long* dmax = reinterpret_cast<unsigned long long*>(c.dstats);
+  KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
+  KNND_HIP(knnd::launch_prep_mixed(c, dmax));
+  unsigned long long hmax[2] = {0, 0};
+  KNND_HIP(hipMemcpyAsync(hmax, dmax, sizeof hmax, hipMemcpyDeviceToHost, c.stream));
+  KNND_HIP(hipStreamSynchronize(c.stream));
+  double pmax, lmax;
+  std::memcpy(&pmax, &hmax[0], 8);
+  std::memcpy(&lmax, &hmax[1], 8);
+  const bool bf16 = c.precision == KNND_PREC_MIXED_BF16;
+  const double range = bf16 ? 1e38 : 6.0e4;
+  if (!(pmax <= 1.0) || !(lmax <= range)) {
+    // fall back to the exact hub form
+    c.mixed = false;
+    (void)hipFree(c.seg32);
+    c.seg32 = nullptr;
+    if (dalloc(&c.seg, nK * (size_t)(2 * c.K + 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      c.seg = nullptr;
+      c.use_hub = false;
+    }
+    return KNND_OK;
+  }
+  const double u = (bf16 ? 0x1p-8 : 0x1p-11) + 0x1p-23;
+  const double s = bf16 ? 0x1p-133 : 0x1p-24;
+  const double m = 3.0 * c.D + 3.0;         // FP32 rounding steps
+  const double g = m * 0x1p-23 * 1.0001;    // (1 + 2^-23)^m - 1
+  const double grow = std::pow(1 + u, 5);  // sum of |hi*hi|, |hi*lo|, |lo*hi| over |x log c|
+  const double opabs = c.D * (3 * s * (pmax + lmax) + 21 * s * s);
+  const double e_rel = 3 * u * u + 3 * u * u * u + g * grow;
+  c.eps_relq = e_rel / (1 - e_rel) * (1 + 0x1p-50);
+  c.eps_abs = opabs * (1 + g) + g * 6 * c.D * s * (pmax + lmax) + 3 * c.D * 0x1p-126;
   return KNND_OK;
 }
 

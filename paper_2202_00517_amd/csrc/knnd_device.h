@@ -127,20 +127,81 @@ __device__ inline double crlog(double x) {
 // Canonical key: acc = fma(x_i, Lx_i - Lz_i, acc), i ascending, from +0.0.
 // Adding +0.0 at the end turns a -0.0 into +0.0 so that the bit order below
 // agrees with FP64 comparison.
+// The rows are read in chunks of 8 coordinates, the next chunk requested
+// before the current one is used, every read unconditional (so that no read
+// waits for the one before it).  Reads reach element D + 22 of each row: the
+// arrays must stay readable that far past their last row (P and L carry 64
+// elements of tail padding).  lx and lz must be 16-byte aligned.
 // ---------------------------------------------------------------------------
+template <typename PT>
+struct KeyChunk {
+  double x[8], l[8], z[8];
+  __device__ __forceinline__ void load(const PT* __restrict__ px, const double* __restrict__ lx,
+                                       const double* __restrict__ lz, int c0) {
+    const double2* lx2 = reinterpret_cast<const double2*>(lx + c0);
+    const double2* lz2 = reinterpret_cast<const double2*>(lz + c0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double2 a = lx2[j], b = lz2[j];
+      l[2 * j] = a.x;
+      l[2 * j + 1] = a.y;
+      z[2 * j] = b.x;
+      z[2 * j + 1] = b.y;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = (double)px[c0 + j];
+  }
+  __device__ __forceinline__ double fold(double acc, int c0, int D) const {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (c0 + j < D) acc = fma(x[j], l[j] - z[j], acc);
+    return acc;
+  }
+};
+
 template <typename PT>
 __device__ __forceinline__ double canonical_key(const PT* __restrict__ px,
                                                 const double* __restrict__ lx,
                                                 const double* __restrict__ lz, int D) {
   double acc = 0.0;
-  int i = 0;
-  const double2* lz2 = reinterpret_cast<const double2*>(lz);
-  for (; i + 1 < D; i += 2) {
-    const double2 v = lz2[i >> 1];
-    acc = fma((double)px[i], lx[i] - v.x, acc);
-    acc = fma((double)px[i + 1], lx[i + 1] - v.y, acc);
+  KeyChunk<PT> a, b;
+  a.load(px, lx, lz, 0);
+  for (int c0 = 0; c0 < D; c0 += 16) {
+    b.load(px, lx, lz, c0 + 8);
+    acc = a.fold(acc, c0, D);
+    a.load(px, lx, lz, c0 + 16);
+    acc = b.fold(acc, c0 + 8, D);
   }
-  if (i < D) acc = fma((double)px[i], lx[i] - lz[i], acc);
+  return acc + 0.0;
+}
+
+// The same key with x's row (as FP64) and its logs staged in LDS: sx and sl
+// must hold at least D + 16 readable entries (those past D are never used).
+__device__ __forceinline__ double canonical_key_lds(const double* sx, const double* sl,
+                                                    const double* __restrict__ lz, int D) {
+  double acc = 0.0;
+  double za[8], zb[8];
+  auto load = [&](double* z, int c0) {
+    const double2* lz2 = reinterpret_cast<const double2*>(lz + c0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double2 v = lz2[j];
+      z[2 * j] = v.x;
+      z[2 * j + 1] = v.y;
+    }
+  };
+  auto fold = [&](const double* z, int c0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (c0 + j < D) acc = fma(sx[c0 + j], sl[c0 + j] - z[j], acc);
+  };
+  load(za, 0);
+  for (int c0 = 0; c0 < D; c0 += 16) {
+    load(zb, c0 + 8);
+    fold(za, c0);
+    load(za, c0 + 16);
+    fold(zb, c0 + 8);
+  }
   return acc + 0.0;
 }
 

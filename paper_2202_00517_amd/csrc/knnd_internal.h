@@ -48,6 +48,14 @@ struct Ctx {
   uint32_t* col = nullptr;    // [nK]
   uint8_t* colslot = nullptr; // [nK] slot of the edge in its source's list
   double* seg = nullptr;      // [nK(2K+1)] candidate keys by snapshot edge (hub form)
+  // mixed precision
+  bool mixed = false;
+  int dk = 0;                 // D padded to 32 or 64 (MFMA K dimension)
+  void* Ph = nullptr;         // [n][2 dk] x split in 16-bit high and low parts (rows: dk high, dk low)
+  void* Lh = nullptr;         // [n][2 dk] the same split of L
+  double* S = nullptr;        // [n] sum_i x_i log x_i
+  float* seg32 = nullptr;     // [nK(2K+1)] cross terms C~ by snapshot edge
+  double eps_relq = 0.0, eps_abs = 0.0;  // mixed-form error bound: e_rel / (1 - e_rel) and e_abs
   bool use_hub = false;
   int64_t* tilesum = nullptr;
   int32_t* class_count = nullptr;  // [NCLASS]
@@ -77,6 +85,9 @@ struct JoinArgs {
   const uint32_t* col;
   const uint8_t* colslot;
   int64_t nKK;  // n*K*K: offset of the FC part of seg (DI part at 2nKK)
+  const float* seg32;
+  const double* S;
+  double eps_relq, eps_abs;
   double* seg;
   uint32_t* Fn;
   double* keysn;
@@ -97,6 +108,7 @@ hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* h
 hipError_t launch_csr(const Ctx& c, const uint32_t* F);
 hipError_t launch_bin(const Ctx& c);
 hipError_t launch_join(const Ctx& c, int64_t* stats);
+hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits);
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out);
 hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad);
 

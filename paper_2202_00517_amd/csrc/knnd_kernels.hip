@@ -9,10 +9,15 @@
 //   keys  [n][K]   FP64 canonical keys of F, ascending per row
 //   rowptr[n+1]    int64, col[nK] uint32: co-friend (reverse) lists; col holds
 //                  the source index | NEWBIT of that edge
+#include <type_traits>
+
 #include "knnd_device.h"
 #include "knnd_internal.h"
 
 namespace knnd {
+
+constexpr int SEL_BINS = 1024;  // histogram bins of the threshold selection
+constexpr int SEL_SURV = 256;   // survivors handled by the fast selection path
 
 // ---------------------------------------------------------------------------
 // Small utility kernels
@@ -521,6 +526,189 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Mixed precision (a3 on MFMA).  The cross term C(x,c) = sum_i x_i log c_i of
+// a hub's receivers x against its candidates c is a small dense product
+// (receivers x DK) . (DK x candidates), DK = D padded to 32 or 64, computed
+// with 16-bit operands (BF16 or FP16) and FP32 accumulation.  The key is then
+// approximated as S(x) - C~ with S(x) = sum_i x_i log x_i in FP64, and the
+// receiver bounds the error from |C~| (every product x_i log c_i is <= 0, so
+// sum_i |x_i log c_i| = |C|).
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename H>
+struct Mfma;
+template <>
+struct Mfma<__bf16> {
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ f32x4 mma(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<_Float16> {
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ f32x4 mma(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// a0 (mixed): each of x_i and log x_i split into two 16-bit parts,
+// v = hi + lo + residual with hi = v rounded and lo = (v - hi) rounded (the
+// difference is exact in FP64), stored as one row [hi(0..DK) | lo(0..DK)]
+// with zeros beyond D; S(x); and the largest |x_i| and |log x_i| (for the
+// absolute part of the error bound and the range checks).
+template <typename PT, typename H>
+__global__ void k_prep_mixed(const PT* __restrict__ P, const double* __restrict__ L, int64_t n, int D, int Dp,
+                             int DK, H* __restrict__ Ph, H* __restrict__ Lh, double* __restrict__ S,
+                             unsigned long long* __restrict__ maxbits /*[2]: max |x|, max |log x|*/) {
+  double pm = 0.0, lm = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < DK; ++i) {
+      double p = 0.0, l = 0.0;
+      if (i < D) {
+        p = (double)P[x * D + i];
+        l = L[x * Dp + i];
+        s = fma(p, l, s);
+        pm = fmax(pm, fabs(p));
+        lm = fmax(lm, fabs(l));
+      }
+      const H ph = (H)p, lh = (H)l;
+      Ph[x * 2 * DK + i] = ph;
+      Ph[x * 2 * DK + DK + i] = (H)(p - (double)ph);
+      Lh[x * 2 * DK + i] = lh;
+      Lh[x * 2 * DK + DK + i] = (H)(l - (double)lh);
+    }
+    S[x] = s;
+  }
+  // non-negative doubles order like their bit patterns
+  atomicMax(&maxbits[0], (unsigned long long)__double_as_longlong(pm));
+  atomicMax(&maxbits[1], (unsigned long long)__double_as_longlong(lm));
+}
+
+// a2+a3, hub form with MFMA: one wave per hub.  Candidate columns (the K
+// friends of the hub, then the hub itself) in tiles of 16, receivers in tiles
+// of 16 rows; lane l holds A[l%16][8(l/16)..+8), B[8(l/16)..+8)[l%16] and
+// D[4(l/16)+i][l%16].  With both operands split in two 16-bit parts, the
+// cross term is accumulated as lo*hi + hi*lo + hi*hi (the lo*lo term is left
+// to the error bound).  C~ goes to the same edge-indexed slots as the FP64
+// keys of the exact hub form, as FP32.
+template <int DK, typename H>
+__global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restrict__ Ph, const H* __restrict__ Lh,
+                                                  float* __restrict__ seg32) {
+  using V8 = typename Mfma<H>::v8;
+  constexpr int KS = DK / 32;  // MFMA k-steps
+  constexpr int MAXCT = 5;     // candidate tiles: K+1 <= 80
+  const int K = a.K, K1 = a.K + 1;
+  const int nct = (K1 + 15) / 16;
+  const int lane = lane_id();
+  const int col = lane & 15, kb = lane >> 4;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  int64_t my_perf = 0;
+  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < a.n; v += nwaves) {
+    const int64_t rp = a.rowptr[v];
+    const int cv = (int)(a.rowptr[v + 1] - rp);
+    const uint32_t fv = lane < K ? a.F[v * K + lane] : 0u;
+    const uint64_t cand_new = __ballot((fv & NEWBIT) != 0);
+    const int nR = cv + K;
+    // candidate fragments, hi and lo parts (registers for the whole hub)
+    V8 bhi[MAXCT][KS], blo[MAXCT][KS];
+#pragma unroll
+    for (int ct = 0; ct < MAXCT; ++ct) {
+      const int ci = ct * 16 + col;
+      const uint32_t craw = (uint32_t)__shfl((int)fv, ci < K ? ci : 0, WAVE);
+      const int64_t c = ci < K ? (int64_t)(craw & IDMASK) : (ci == K ? v : -1);
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        V8 fh = {}, fl = {};
+        if (ct < nct && c >= 0) {
+          fh = *reinterpret_cast<const V8*>(Lh + c * 2 * DK + s * 32 + kb * 8);
+          fl = *reinterpret_cast<const V8*>(Lh + c * 2 * DK + DK + s * 32 + kb * 8);
+        }
+        bhi[ct][s] = fh;
+        blo[ct][s] = fl;
+      }
+    }
+    for (int k0 = 0; k0 < nR; k0 += 16) {
+      // metadata of row k0 + col (the four lanes sharing col compute the same)
+      const int row = k0 + col;
+      const bool on = row < nR;
+      const uint32_t fsp = (uint32_t)__shfl((int)fv, (row >= cv && row < nR) ? row - cv : 0, WAVE);
+      int64_t r = 0, b0 = 0, b1 = -1;
+      uint32_t rnew = 0;
+      int excl = -1;
+      if (on) {
+        if (row < cv) {
+          const uint32_t e = a.col[rp + row];
+          r = e & IDMASK;
+          rnew = e & NEWBIT;
+          b0 = (r * K + a.colslot[rp + row]) * K;  // FF
+        } else {
+          const int sp = row - cv;
+          r = fsp & IDMASK;
+          rnew = fsp & NEWBIT;
+          excl = sp;
+          b0 = a.nKK + (v * K + sp) * K;  // FC
+          b1 = 2 * a.nKK + v * K + sp;    // DI
+        }
+      }
+      const bool want = on && (!a.skip || rnew != 0 || cand_new != 0);
+      if (__ballot(want) == 0) continue;
+      V8 ahi[KS], alo[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        V8 fh = {}, fl = {};
+        if (on) {
+          fh = *reinterpret_cast<const V8*>(Ph + r * 2 * DK + s * 32 + kb * 8);
+          fl = *reinterpret_cast<const V8*>(Ph + r * 2 * DK + DK + s * 32 + kb * 8);
+        }
+        ahi[s] = fh;
+        alo[s] = fl;
+      }
+#pragma unroll
+      for (int ct = 0; ct < MAXCT; ++ct) {
+        if (ct >= nct) break;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          acc = Mfma<H>::mma(alo[s], bhi[ct][s], acc);
+          acc = Mfma<H>::mma(ahi[s], blo[ct][s], acc);
+          acc = Mfma<H>::mma(ahi[s], bhi[ct][s], acc);
+        }
+        const int ci = ct * 16 + col;
+        const bool cnew = ci < K && ((cand_new >> ci) & 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int src = 4 * kb + i;  // row k0 + src lives in lanes src, src+16, ...
+          const int64_t rb0 = (int64_t)shfl_u64((uint64_t)b0, src);
+          const int64_t rb1 = (int64_t)shfl_u64((uint64_t)b1, src);
+          const int rex = __shfl(excl, src, WAVE);
+          const uint32_t rnw = shfl_u32(rnew, src);
+          const bool ron = k0 + src < nR;
+          bool need;
+          int64_t pos;
+          if (ci < K) {
+            need = ron && ci != rex && (!a.skip || rnw || cnew);
+            pos = rb0 + ci;
+          } else {
+            need = ron && ci == K && rb1 >= 0 && (!a.skip || rnw);
+            pos = rb1;
+          }
+          if (need) {
+            seg32[pos] = acc[i];
+            ++my_perf;
+          }
+        }
+      }
+    }
+  }
+  __shared__ int64_t s_red[4];
+  const int64_t pf = block_sum(my_perf, s_red);
+  if (threadIdx.x == 0 && pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
+}
+
+// ---------------------------------------------------------------------------
 // a2..a5, receiver side: one 256-thread block per receiver x.
 //  B  insert x and F(x) into the block's hash set, marked excluded
 //  C  enumerate every candidate occurrence (co-friends, friends of friends,
@@ -601,6 +789,76 @@ __device__ __forceinline__ int64_t block_sum_nw(int64_t v, int64_t* sh /*[NW]*/)
   return t;
 }
 
+// Error bound of the mixed-precision key k~ = S(x) - C~ against the
+// canonical FP64 key, from |C~| = k~ - S(x) (both S and C are <= 0):
+//   |C~ - C| <= e_rel (|C~| + e_abs) / (1 - e_rel) + e_abs
+// with e_rel covering the rounding of both 16-bit operands and the FP32
+// accumulation, e_abs the 16-bit subnormal range, plus a small relative slack
+// for FP64 rounding (S(x), the subtraction, the canonical fold).
+// (eps_relq = e_rel / (1 - e_rel), rounded up on the host)
+__device__ __forceinline__ double mix_eps(const JoinArgs& a, double Sx, double kt) {
+  const double cabs = fmax(kt - Sx, 0.0);
+  return fma(a.eps_relq, cabs + a.eps_abs, a.eps_abs + 0x1p-44 * (fabs(Sx) + cabs + 1.0));
+}
+
+// An upper bound T on the K-th smallest of {old keys} u {k~_i + eps_i}: the
+// largest value in the first bins (of a monotone histogram over values <= hi)
+// that together hold at least K values.
+template <int NW>
+__device__ double kth_upper_bound(int K, int ncand, const double* kx, double hi, const double* ckey,
+                                  const JoinArgs& a, double Sx, int32_t* hist, int* s_bstar, int64_t* s_red,
+                                  double* s_dred) {
+  constexpr int NT = NW * 64;
+  const int tid = threadIdx.x;
+  auto ub = [&](int i) {
+    const double kt = ckey[i];
+    return kt + mix_eps(a, Sx, kt);
+  };
+  double lo = kx[0];
+  for (int i = tid; i < ncand; i += NT) lo = fmin(lo, ub(i));
+  lo = block_min<NW>(lo, s_dred);
+  const double scale = hi > lo ? (double)SEL_BINS / (hi - lo) : 0.0;
+  auto bin_of = [&](double k) {
+    const int b = (int)((k - lo) * scale);
+    return b < 0 ? 0 : (b >= SEL_BINS ? SEL_BINS - 1 : b);
+  };
+  for (int b = tid; b < SEL_BINS; b += NT) hist[b] = 0;
+  __syncthreads();
+  for (int i = tid; i < ncand; i += NT) {
+    const double u = ub(i);
+    if (u <= hi) atomicAdd(&hist[bin_of(u)], 1);
+  }
+  if (tid < K) atomicAdd(&hist[bin_of(kx[tid])], 1);
+  __syncthreads();
+  {
+    constexpr int PER = SEL_BINS / NT > 0 ? SEL_BINS / NT : 1;
+    int loc[PER];
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = tid * PER + q;
+      loc[q] = b < SEL_BINS ? hist[b] : 0;
+      sum += loc[q];
+    }
+    int64_t run = block_exscan_nw<NW>(sum, s_red);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = tid * PER + q;
+      if (b < SEL_BINS && run < K && run + loc[q] >= K) *s_bstar = b;
+      run += loc[q];
+    }
+  }
+  __syncthreads();
+  const int bstar = *s_bstar;
+  double m = -INFINITY;
+  for (int i = tid; i < ncand; i += NT) {
+    const double u = ub(i);
+    if (u <= hi && bin_of(u) <= bstar) m = fmax(m, u);
+  }
+  if (tid < K && bin_of(kx[tid]) <= bstar) m = fmax(m, kx[tid]);
+  return -block_min<NW>(-m, s_dred);
+}
+
 // Lanes 0..K-1 of a wave write receiver x's new list.  An index outside
 // [0, n) (impossible for a correct list) is never written: the lane keeps the
 // old entry and the round reports an internal error.
@@ -631,24 +889,33 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
 // segments (hub form) instead of being computed here (pull form); NW: waves
 // per block.  Classes with CAP > 8192 size their tables optimistically and
 // hand a receiver that overflows to the global-memory class.
-constexpr int SEL_BINS = 1024;   // histogram bins of the threshold selection
-constexpr int SEL_SURV = 256;    // survivors handled by the fast selection path
 
-template <int CAP, typename PT, bool SEG, int NW>
+template <int CAP, typename PT, int MODE, int NW>
 __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restrict__ lists,
                                                   int32_t* __restrict__ counts, int cls) {
+  constexpr bool SEG = MODE >= 1;  // keys (or cross terms) come from the hub kernel
+  constexpr bool MIX = MODE == 2;  // cross terms from MFMA, exact keys only where needed
   constexpr int NT = NW * 64;
   constexpr bool GLOB = (CAP == 0);
   constexpr bool BIG = (CAP > 8192);  // table in LDS, candidate list in global memory
   constexpr bool GUARD = BIG;
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
-  // a guarded class overshoots LIMIT by at most one batch (4 per thread)
-  static_assert(!BIG || LIMIT + 4 * NT <= BIG_CAND, "candidate list of the big classes too small");
+  constexpr int U = GLOB ? 4 : 8;            // occurrences per thread in flight
+  // a guarded class overshoots LIMIT by at most one batch (U per thread)
+  static_assert(!BIG || LIMIT + U * NT <= BIG_CAND, "candidate list of the big classes too small");
+  // occurrence counter: T < 2^32 in the LDS classes (their binning bounds
+  // min(T, n-1-K) by 32768, so T <= 32768, or c < n < 32768 + K + 1 and
+  // T = c (K+1) + K^2 < 2^22)
+  using IT = typename std::conditional<GLOB, int64_t, uint32_t>::type;
+  using KT = typename std::conditional<MIX, float, double>::type;  // what a key slot holds
   __shared__ uint32_t s_tab[GLOB ? 1 : CAP];
   __shared__ uint32_t s_cid[CC];
   __shared__ double s_ckey[SEG ? CC : 1];
   __shared__ uint32_t s_fx[WAVE];
+  __shared__ double s_kx[WAVE];
+  // mixed form: x's row and its logs for the rescue (D <= HUB_MAXD)
+  __shared__ double s_xr[MIX ? HUB_MAXD + 16 : 1], s_lr[MIX ? HUB_MAXD + 16 : 1];
   __shared__ uint64_t s_lk[NW - 1][WAVE];
   __shared__ uint32_t s_li[NW - 1][WAVE];
   // selection scratch: reuses the hash table's LDS (dead after phase C) when
@@ -661,6 +928,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
   uint64_t* s_sk = ALIAS ? reinterpret_cast<uint64_t*>(s_tab + SEL_BINS) : s_sk_d;
   uint32_t* s_si = ALIAS ? reinterpret_cast<uint32_t*>(s_tab + SEL_BINS + 2 * SEL_SURV) : s_si_d;
   __shared__ uint64_t s_tau;
+  __shared__ double s_theta;
   __shared__ int s_ncand, s_nuniq, s_over, s_ns, s_bstar;
   __shared__ int64_t s_red[NW];
   __shared__ double s_dred[NW];
@@ -682,7 +950,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
   const int64_t ccap = GLOB ? half : (BIG ? (int64_t)BIG_CAND : (int64_t)CC);  // candidate-list capacity
   const PT* P = reinterpret_cast<const PT*>(a.P);
   const int nitems = counts[cls];
-  int64_t my_evals = 0, my_perf = 0, my_upd = 0, my_err = 0;
+  int64_t my_evals = 0, my_perf = 0, my_upd = 0, my_err = 0, my_resc = 0;
 
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int64_t x = list[item];
@@ -701,6 +969,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
     // the round-start K-th key: a candidate with a larger key cannot enter
     // (the paper's compare-to-last, Section 4.2)
     const double tau0 = a.keys[x * K + K - 1];
+    const double Sx = MIX ? a.S[x] : 0.0;  // sum_i x_i log x_i
 
     // A: clear
     for (uint32_t s = tid; s < cap; s += NT) tab[s] = EMPTY;
@@ -711,67 +980,92 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
       s_tau = key_bits(a.keys[x * K + K - 1]);
     }
     __syncthreads();
+    if (MIX && tid < D) {  // (read only after the syncs of phases B and C)
+      s_xr[tid] = (double)P[x * D + tid];
+      s_lr[tid] = a.L[x * Dp + tid];
+    }
     // B: excluded entries
     if (tid < K) {
       const uint32_t raw = a.F[x * K + tid];
       s_fx[tid] = raw;
+      s_kx[tid] = a.keys[x * K + tid];
       tab_insert(tab, mask, raw & IDMASK, EXCLBIT);
     } else if (tid == K) {
       tab_insert(tab, mask, (uint32_t)x, EXCLBIT);
     }
     __syncthreads();
-    // C: enumerate candidate occurrences, four per thread in flight
-    for (int64_t t0 = 0; t0 < T; t0 += 4 * NT) {
-      uint32_t z[4], nw[4];
-      int64_t kp[4];  // key slot of the occurrence (hub form)
-      int res[4];
+    // C: enumerate candidate occurrences, U per thread in flight.  The key
+    // slot of an occurrence depends only on the edge it comes through, so the
+    // key is loaded together with the candidate id, before the table says
+    // whether this occurrence is the one that lists the candidate (slots of
+    // edges the hub kernel skipped hold stale values that are never used).
+    for (IT t0 = 0; t0 < (IT)T; t0 += U * NT) {
+      // Every load below is issued unconditionally (an occurrence that does
+      // not need it reads entry 0, which always exists) so that all U loads
+      // of a stage are in flight together; branches around the loads would
+      // make each occurrence wait for its own before the next is issued.
+      int rg[U];  // 1 co-friend, 2 friend of friend, 3 friend of co-friend, 0 none
+      int ss[U];
+      uint32_t cw[U], fw[U], sl[U];
+      // stage 1: the edge each occurrence comes through
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t t = t0 + tid + NT * u;
-        z[u] = 0;
-        nw[u] = 0;
-        kp[u] = 0;
-        if (t < c) {  // co-friend w (edge w -> x at slot sp)
-          const uint32_t w = a.col[rp + t];
-          z[u] = w & IDMASK;
-          nw[u] = w & NEWBIT;
-          if (SEG) kp[u] = 2 * a.nKK + (int64_t)(w & IDMASK) * K + a.colslot[rp + t];
-        } else if (t < c + KK) {  // friend of friend: row j of F(F(x))
-          const int uu = (int)(t - c);
-          const int j = uu / K;
-          const int s = uu - j * K;
-          const uint32_t v = s_fx[j];
-          const uint32_t zr = a.F[(int64_t)(v & IDMASK) * K + s];
-          z[u] = zr & IDMASK;
-          nw[u] = (v | zr) & NEWBIT;
-          if (SEG) kp[u] = x * KK + uu;
-        } else if (t < T) {  // friend of co-friend w
-          const int64_t uu = t - c - KK;
-          const int64_t q = uu / K;
-          const int s = (int)(uu - q * K);
-          const uint32_t w = a.col[rp + q];
-          const uint32_t zr = a.F[(int64_t)(w & IDMASK) * K + s];
-          z[u] = zr & IDMASK;
-          nw[u] = (w | zr) & NEWBIT;
-          if (SEG) kp[u] = a.nKK + ((int64_t)(w & IDMASK) * K + a.colslot[rp + q]) * K + s;
+      for (int u = 0; u < U; ++u) {
+        const IT t = t0 + tid + NT * u;
+        const bool inC = t < (IT)c;
+        const bool inFF = !inC && t < (IT)(c + KK);
+        const bool inFC = !inC && !inFF && t < (IT)T;
+        rg[u] = inC ? 1 : (inFF ? 2 : (inFC ? 3 : 0));
+        const IT uu = inFF ? t - (IT)c : t - (IT)(c + KK);  // meaningful in regions 2 and 3
+        const IT q = uu / (IT)K;                              // friend j or co-friend q
+        ss[u] = (int)(uu - q * (IT)K);                        // entry s of that row
+        const int64_t ci = inC ? rp + (int64_t)t : (inFC ? rp + (int64_t)q : 0);
+        cw[u] = a.col[ci];
+        sl[u] = SEG ? (uint32_t)a.colslot[ci] : 0u;
+        fw[u] = s_fx[inFF ? (int)q : 0];
+      }
+      // stage 2: candidate ids and their keys
+      uint32_t zr[U];
+      KT kr[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t srcw = rg[u] == 2 ? fw[u] : cw[u];
+        const int64_t v = srcw & IDMASK;
+        const IT t = t0 + tid + NT * u;
+        zr[u] = a.F[rg[u] >= 2 ? v * K + ss[u] : 0];
+        if (SEG) {
+          const int64_t kp = rg[u] == 1   ? 2 * a.nKK + v * K + sl[u]
+                             : rg[u] == 2 ? x * KK + (int64_t)(t - (IT)c)
+                             : rg[u] == 3 ? a.nKK + (v * K + sl[u]) * K + ss[u]
+                                          : 0;
+          kr[u] = MIX ? (KT)a.seg32[kp] : (KT)a.seg[kp];
         }
       }
+      uint32_t z[U], nw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t srcw = rg[u] == 2 ? fw[u] : cw[u];
+        z[u] = rg[u] == 1 ? (srcw & IDMASK) : (zr[u] & IDMASK);
+        nw[u] = (rg[u] == 1 ? srcw : (srcw | zr[u])) & NEWBIT;
+      }
+      int res[U];
       int fresh = 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         res[u] = 0;
-        if (t0 + tid + NT * u < T) {
+        if (t0 + tid + NT * u < (IT)T) {
           res[u] = tab_insert(tab, mask, z[u], a.skip ? nw[u] : NEWBIT);
           fresh += res[u] & 1;
         }
       }
       item_evals += fresh;
-      double kv[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) kv[u] = (SEG && (res[u] & 2)) ? a.seg[kp[u]] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const bool app = (res[u] & 2) != 0 && (!SEG || kv[u] <= tau0);
+      for (int u = 0; u < U; ++u) {
+        // list only candidates that can beat the round-start K-th (for the
+        // mixed form: whose lower bound can)
+        double kv = 0.0;
+        if (SEG) kv = MIX ? Sx - (double)kr[u] : (double)kr[u];
+        const bool app = (res[u] & 2) != 0 &&
+                         (!SEG || (MIX ? kv - mix_eps(a, Sx, kv) <= tau0 : kv <= tau0));
         const uint64_t m = __ballot(app);
         if (m) {
           int base = 0;
@@ -781,7 +1075,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
             const int at = base + (int)rank_in(m);
             if (at < ccap) {
               cid[at] = z[u];
-              if (SEG) ckey[at] = kv[u];
+              if (SEG) ckey[at] = kv;
             } else if (GUARD) {
               s_over = 1;  // list full: the global-memory class redoes this receiver
             } else {
@@ -810,10 +1104,70 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
     my_evals += item_evals;
     // (s_ncand exceeds the list capacity only after a reported internal error)
     const int ncand = (int)min((int64_t)s_ncand, ccap);
-    const double* kx = a.keys + x * K;
-
+    const double* kx = s_kx;  // the old list's keys
     bool done = false;
-    if (SEG && ncand <= 2 * WAVE) {
+
+    if (MIX) {
+      // Theta: an upper bound on the K-th smallest upper bound among the old
+      // list (exact keys) and the listed candidates (k~ + eps).  A candidate
+      // whose lower bound exceeds Theta has K entries strictly better than
+      // it.  Every other candidate gets its canonical FP64 key (the rescue)
+      // and only those are merged with the old list.
+      const bool all = ncand <= 2 * WAVE;  // short list: rescue every candidate
+      if (tid == 0) s_ns = all ? ncand : 0;
+      if (!all) {
+        const double theta =
+            kth_upper_bound<NW>(K, ncand, kx, tau0, ckey, a, Sx, s_hist, &s_bstar, s_red, s_dred);
+        if (tid == 0) s_theta = theta;
+        // compact the rescue set (its positions in the candidate list)
+        for (int i = tid; i < ncand; i += NT) {
+          const double kt = ckey[i];
+          if (kt - mix_eps(a, Sx, kt) <= theta) {
+            const int pos = atomicAdd(&s_ns, 1);
+            if (pos < SEL_SURV) s_si[pos] = (uint32_t)i;
+          }
+        }
+      }
+      __syncthreads();
+      const int ns = s_ns;
+      my_resc += tid == 0 ? ns : 0;
+      if (ns <= SEL_SURV) {
+        // canonical keys of the rescue set, then wave 0 merges them into the
+        // old list
+        for (int j = tid; j < ns; j += NT) {
+          const uint32_t z = cid[all ? j : s_si[j]];
+          s_sk[j] = key_bits(canonical_key_lds(s_xr, s_lr, a.L + (int64_t)z * Dp, D));
+          s_si[j] = z | NEWBIT;
+        }
+        __syncthreads();
+        done = true;
+        if (wave == 0) {
+          uint64_t lk = lane < K ? key_bits(kx[lane]) : KEY_SENTINEL;
+          uint32_t li = lane < K ? (s_fx[lane] & IDMASK) : IDMASK;
+          for (int b0 = 0; b0 < ns; b0 += WAVE) {
+            const bool ok = b0 + lane < ns;
+            uint64_t bk = ok ? s_sk[b0 + lane] : KEY_SENTINEL;
+            uint32_t bi = ok ? s_si[b0 + lane] : IDMASK;
+            wave_sort(bk, bi);
+            wave_merge(lk, li, bk, bi);
+          }
+          write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
+        }
+      } else {
+        // a large rescue set: canonical keys in place, +inf for the rest
+        // (bounds compared with the same Theta), then the exact selection
+        const double theta = s_theta;
+        for (int i = tid; i < ncand; i += NT) {
+          const double kt = ckey[i];
+          double exact = INFINITY;
+          if (kt - mix_eps(a, Sx, kt) <= theta) exact = canonical_key_lds(s_xr, s_lr, a.L + (int64_t)cid[i] * Dp, D);
+          ckey[i] = exact;
+        }
+        __syncthreads();
+      }
+    }
+
+    if (!done && SEG && ncand <= 2 * WAVE) {
       // D (hub form, short list): wave 0 sorts the listed candidates and
       // merges them into the old list
       done = true;
@@ -829,7 +1183,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
         }
         write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
       }
-    } else if (SEG) {
+    } else if (!done && SEG) {
       // D (hub form): every key is known and every listed candidate has key
       // <= tau0.  Histogram the candidates and the old list over
       // [kmin, tau0] with a monotone binning and find the first bin b* where
@@ -973,7 +1327,12 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
   const int64_t pf = block_sum_nw<NW>(my_perf, s_red);
   const int64_t up = block_sum_nw<NW>(my_upd, s_red);
   const int64_t er = block_sum_nw<NW>(my_err, s_red);
+  const int64_t rs = block_sum_nw<NW>(my_resc, s_red);
   if (tid == 0) {
+    if (rs) {
+      atomicAdd((unsigned long long*)&a.stats[STAT_RESCUES], (unsigned long long)rs);
+      atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)rs);
+    }
     if (er) atomicAdd((unsigned long long*)&a.stats[STAT_ERR], (unsigned long long)er);
     if (ev) atomicAdd((unsigned long long*)&a.stats[STAT_EVALS], (unsigned long long)ev);
     if (pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
@@ -1053,15 +1412,15 @@ hipError_t launch_bin(const Ctx& c) {
   return hipGetLastError();
 }
 
-template <int CAP, typename PT, bool SEG>
+template <int CAP, typename PT, int MODE>
 static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
   if constexpr (CAP == 0) {
     // few, very large receivers: 1024 threads each, global-memory tables
-    hipLaunchKernelGGL((k_recv<CAP, PT, SEG, 16>), dim3(c.gblocks), dim3(1024), 0, c.stream, a, c.class_list,
+    hipLaunchKernelGGL((k_recv<CAP, PT, MODE, 16>), dim3(c.gblocks), dim3(1024), 0, c.stream, a, c.class_list,
                        c.class_count, cls);
     return hipGetLastError();
   } else {
-    auto kern = k_recv<CAP, PT, SEG, 4>;
+    auto kern = k_recv<CAP, PT, MODE, 4>;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) {
       (void)hipGetLastError();
@@ -1074,17 +1433,17 @@ static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
   }
 }
 
-template <typename PT, bool SEG>
+template <typename PT, int MODE>
 static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
   hipError_t e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 0, PT, SEG>(c, a, 0)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 1, PT, SEG>(c, a, 1)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 2, PT, SEG>(c, a, 2)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 3, PT, SEG>(c, a, 3)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 4, PT, SEG>(c, a, 4)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 5, PT, SEG>(c, a, 5)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 6, PT, SEG>(c, a, 6)) != hipSuccess) return e;
-  return launch_recv_class<0, PT, SEG>(c, a, 7);
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 0, PT, MODE>(c, a, 0)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 1, PT, MODE>(c, a, 1)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 2, PT, MODE>(c, a, 2)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 3, PT, MODE>(c, a, 3)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 4, PT, MODE>(c, a, 4)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 5, PT, MODE>(c, a, 5)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 6, PT, MODE>(c, a, 6)) != hipSuccess) return e;
+  return launch_recv_class<0, PT, MODE>(c, a, 7);
 }
 
 template <int MAXD, typename PT>
@@ -1116,6 +1475,39 @@ static hipError_t launch_hub(const Ctx& c, const JoinArgs& a) {
   return hipGetLastError();
 }
 
+template <int DK, typename H>
+static hipError_t launch_hub_mfma_t(const Ctx& c, const JoinArgs& a) {
+  auto kern = k_hub_mfma<DK, H>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) {
+    (void)hipGetLastError();
+    per_cu = 1;
+  }
+  const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu * 4);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, (const H*)c.Ph, (const H*)c.Lh, c.seg32);
+  return hipGetLastError();
+}
+
+static hipError_t launch_hub_mfma(const Ctx& c, const JoinArgs& a) {
+  if (c.precision == 1) return c.dk == 32 ? launch_hub_mfma_t<32, __bf16>(c, a) : launch_hub_mfma_t<64, __bf16>(c, a);
+  return c.dk == 32 ? launch_hub_mfma_t<32, _Float16>(c, a) : launch_hub_mfma_t<64, _Float16>(c, a);
+}
+
+template <typename PT, typename H>
+static void launch_prep_t(const Ctx& c, unsigned long long* maxbits) {
+  hipLaunchKernelGGL((k_prep_mixed<PT, H>), dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream,
+                     (const PT*)c.P, c.L, c.n, c.D, c.Dp, c.dk, (H*)c.Ph, (H*)c.Lh, c.S, maxbits);
+}
+
+hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits) {
+  if (c.precision == 1) {
+    if (c.dtype == 0) launch_prep_t<float, __bf16>(c, maxbits); else launch_prep_t<double, __bf16>(c, maxbits);
+  } else {
+    if (c.dtype == 0) launch_prep_t<float, _Float16>(c, maxbits); else launch_prep_t<double, _Float16>(c, maxbits);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_join(const Ctx& c, int64_t* stats) {
   JoinArgs a;
   a.P = c.P;
@@ -1142,13 +1534,22 @@ hipError_t launch_join(const Ctx& c, int64_t* stats) {
   a.gstride = c.gstride;
   a.bcand = c.bcand;
   a.bckey = c.bckey;
+  a.seg32 = c.seg32;
+  a.S = c.S;
+  a.eps_relq = c.eps_relq;
+  a.eps_abs = c.eps_abs;
   hipError_t e;
+  if (c.mixed) {
+    e = launch_hub_mfma(c, a);
+    if (e != hipSuccess) return e;
+    return c.dtype == 0 ? launch_recv_all<float, 2>(c, a) : launch_recv_all<double, 2>(c, a);
+  }
   if (c.use_hub) {
     e = c.dtype == 0 ? launch_hub<float>(c, a) : launch_hub<double>(c, a);
     if (e != hipSuccess) return e;
-    return c.dtype == 0 ? launch_recv_all<float, true>(c, a) : launch_recv_all<double, true>(c, a);
+    return c.dtype == 0 ? launch_recv_all<float, 1>(c, a) : launch_recv_all<double, 1>(c, a);
   }
-  return c.dtype == 0 ? launch_recv_all<float, false>(c, a) : launch_recv_all<double, false>(c, a);
+  return c.dtype == 0 ? launch_recv_all<float, 0>(c, a) : launch_recv_all<double, 0>(c, a);
 }
 
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out) {

@@ -44,9 +44,11 @@ def assert_same_graph(gi, gk, oi, ok, what):
     assert kb.size == 0, f"{what}: keys differ in {kb.size} rows, first x={kb[:5].tolist()}"
 
 
-def full_compare(P, d, K, seed, M=0, flags=0, max_rounds=100):
-    say(f"full build n={P.shape[0]} d={d} K={K} seed={seed} {P.dtype} M={M} flags={flags}")
-    prm = knnd.default_params(fcr_samples=M, flags=flags, max_rounds=max_rounds)
+def full_compare(P, d, K, seed, M=0, flags=0, max_rounds=100, precision=0):
+    say(f"full build n={P.shape[0]} d={d} K={K} seed={seed} {P.dtype} M={M} flags={flags} "
+        f"precision={precision}")
+    prm = knnd.default_params(fcr_samples=M, flags=flags, max_rounds=max_rounds,
+                              precision=precision)
     g = knnd.knnd_build_ex(P, d, K, seed, prm)
     o = oracle.build_graph(P, d, K, seed, M=M, max_rounds=max_rounds)
     assert g["status"] == o.status
@@ -105,13 +107,14 @@ def test_initial_graph_bit_exact(n, d, K, dtype):
 # ---------------------------------------------------------------------------
 # a1..a5: one round from the oracle's own snapshot
 # ---------------------------------------------------------------------------
-def one_round(P, d, K, seed, F0=None, k0=None, flags=0):
+def one_round(P, d, K, seed, F0=None, k0=None, flags=0, precision=0):
     P64 = oracle.widen(P)
     L = oracle.log_table(P64)
     if F0 is None:
         F0, k0 = oracle.initial_graph(P64, L, K, seed)
-    say(f"one round n={P.shape[0]} d={d} K={K} flags={flags}")
-    with knnd.Context(P, d, K, seed, knnd.default_params(flags=flags)) as c:
+    say(f"one round n={P.shape[0]} d={d} K={K} flags={flags} precision={precision}")
+    prm = knnd.default_params(flags=flags, precision=precision)
+    with knnd.Context(P, d, K, seed, prm) as c:
         c.set_graph(F0, k0, 0)
         st = c.round()
         gi, gk = c.get_graph()
@@ -123,13 +126,18 @@ def one_round(P, d, K, seed, F0=None, k0=None, flags=0):
 
 
 JOIN_FORMS = [0, knnd.KNND_FLAG_PULL]
+# (flags, precision): exact hub form, pull form, BF16 and FP16 mixed forms
+FORMS = [(0, knnd.KNND_PREC_FP64), (knnd.KNND_FLAG_PULL, knnd.KNND_PREC_FP64),
+         (0, knnd.KNND_PREC_MIXED_BF16), (0, knnd.KNND_PREC_MIXED_FP16)]
+FORM_IDS = ["hub", "pull", "bf16", "fp16"]
 
 
-@pytest.mark.parametrize("flags", JOIN_FORMS, ids=["hub", "pull"])
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
 @pytest.mark.parametrize("n,d,K", [(11, 3, 10), (200, 1, 2), (1000, 6, 16), (3001, 20, 30),
                                    (4097, 60, 64), (20000, 10, 20)])
-def test_one_round_bit_exact(n, d, K, flags):
-    one_round(synth.dirichlet(n + 7, n, d, np.float32), d, K, seed=n, flags=flags)
+def test_one_round_bit_exact(n, d, K, form):
+    one_round(synth.dirichlet(n + 7, n, d, np.float32), d, K, seed=n, flags=form[0],
+              precision=form[1])
 
 
 def _hub_snapshot(P, K, hub, seed):
@@ -153,10 +161,10 @@ def _hub_snapshot(P, K, hub, seed):
     return F, keys
 
 
-@pytest.mark.parametrize("flags", JOIN_FORMS, ids=["hub", "pull"])
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
 @pytest.mark.parametrize("n,d,K", [(3000, 6, 8), (7000, 5, 4), (18005, 4, 4), (30000, 4, 4),
                                    (40000, 4, 4)])
-def test_hub_receiver_large_tables(n, d, K, flags):
+def test_hub_receiver_large_tables(n, d, K, form):
     # The receiver with n-1 co-friends lands in the 16384-slot LDS class
     # (n=3000 and 7000), in the 32768-slot class with about 18000 distinct
     # candidates, more than 16384 (n=18005), in the 32768-slot class whose
@@ -164,14 +172,15 @@ def test_hub_receiver_large_tables(n, d, K, flags):
     # global-memory class (n=40000).
     P = synth.dirichlet(n + 11, n, d, np.float32)
     F, k = _hub_snapshot(P, K, hub=n // 3, seed=n)
-    one_round(P, d, K, seed=5, F0=F, k0=k, flags=flags)
+    one_round(P, d, K, seed=5, F0=F, k0=k, flags=form[0], precision=form[1])
 
 
-def test_exact_ties_break_by_index():
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+def test_exact_ties_break_by_index(form):
     # 20 distinct points, each repeated 12 times: many keys tie exactly
     base = synth.dirichlet(31, 20, 5, np.float32)
     P = np.repeat(base, 12, axis=0)
-    full_compare(P, 5, 8, seed=17)
+    full_compare(P, 5, 8, seed=17, flags=form[0], precision=form[1])
 
 
 # ---------------------------------------------------------------------------
@@ -191,7 +200,8 @@ def test_random_small_configs_full():
         K = int(rng.integers(2, min(64, n - 1) + 1))
         dtype = np.float32 if rng.random() < 0.7 else np.float64
         P = synth.dirichlet(3000 + i, n, d, dtype)
-        full_compare(P, d, K, seed=4000 + i, flags=JOIN_FORMS[i % 2])
+        flags, prec = FORMS[i % len(FORMS)]
+        full_compare(P, d, K, seed=4000 + i, flags=flags, precision=prec)
 
 
 @pytest.mark.parametrize("form", JOIN_FORMS, ids=["hub", "pull"])
@@ -263,12 +273,12 @@ def _digest(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def check_against_golden(cfg):
+def check_against_golden(cfg, precision=0):
     gold = _golden(f"c{cfg}")
     c = synth.CONFIGS[cfg]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
-    say(f"config {cfg} full size vs stored oracle digests")
-    g = knnd.knnd_build_ex(P, c["d"], c["K"], c["seed"])
+    say(f"config {cfg} full size vs stored oracle digests, precision {precision}")
+    g = knnd.knnd_build_ex(P, c["d"], c["K"], c["seed"], knnd.default_params(precision=precision))
     assert g["status"] == gold["status"]
     assert g["rounds"] == gold["rounds"]
     assert [s["fcr_hits"] for s in g["stats"]] == gold["fcr_hits"]
@@ -283,11 +293,57 @@ def test_config2_full_size():
     check_against_golden(2)
 
 
-@pytest.mark.parametrize("form", JOIN_FORMS, ids=["hub", "pull"])
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
 def test_config2_live_oracle(form):
     c = synth.CONFIGS[2]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
-    full_compare(P, c["d"], c["K"], c["seed"], flags=form)
+    g, _ = full_compare(P, c["d"], c["K"], c["seed"], flags=form[0], precision=form[1])
+    resc = sum(s["rescues"] for s in g["stats"])
+    if form[1] != knnd.KNND_PREC_FP64:
+        alg = sum(s["evals_alg"] for s in g["stats"])
+        say(f"config 2 {FORM_IDS[FORMS.index(form)]}: rescued {resc} of {alg} evaluations "
+            f"({100.0 * resc / alg:.2f}%)")
+        assert 0 < resc < alg
+    else:
+        assert resc == 0
+
+
+MIXED = [knnd.KNND_PREC_MIXED_BF16, knnd.KNND_PREC_MIXED_FP16]
+
+
+@pytest.mark.parametrize("prec", MIXED, ids=["bf16", "fp16"])
+def test_mixed_off_the_simplex_runs_exact(prec):
+    # coordinates above 1 make some products x_i log c_i positive, where the
+    # mixed error bound does not hold: the library must run the exact form
+    P = synth.dirichlet(77, 3000, 6, np.float32) * np.float32(3.0)
+    g, _ = full_compare(P, 6, 8, seed=9, precision=prec)
+    assert all(s["rescues"] == 0 for s in g["stats"])
+
+
+@pytest.mark.parametrize("prec", MIXED, ids=["bf16", "fp16"])
+def test_mixed_tiny_coordinates(prec):
+    # most coordinates far below the FP16 normal range (down to the 1e-12
+    # clamp), so the subnormal part of the error bound matters
+    base = synth.dirichlet(78, 4000, 15, np.float64) ** 6
+    base = base / base.sum(axis=1, keepdims=True)
+    P = np.maximum(base, 1e-12).astype(np.float32)
+    assert (P < 2.0 ** -14).mean() > 0.3
+    g, _ = full_compare(P, 15, 12, seed=10, precision=prec)
+    assert sum(s["rescues"] for s in g["stats"]) > 0
+
+
+def test_config3_mixed_bf16_full_size():
+    g, _ = check_against_golden(3, knnd.KNND_PREC_MIXED_BF16)
+    resc = sum(s["rescues"] for s in g["stats"])
+    alg = sum(s["evals_alg"] for s in g["stats"])
+    say(f"config 3 bf16: rescued {resc} of {alg} evaluations ({100.0 * resc / alg:.2f}%)")
+
+
+def test_config4_mixed_fp16_full_size():
+    g, _ = check_against_golden(4, knnd.KNND_PREC_MIXED_FP16)
+    resc = sum(s["rescues"] for s in g["stats"])
+    alg = sum(s["evals_alg"] for s in g["stats"])
+    say(f"config 4 fp16: rescued {resc} of {alg} evaluations ({100.0 * resc / alg:.2f}%)")
 
 
 def test_config3_full_size():
