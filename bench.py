@@ -31,13 +31,67 @@ METRIC = "comparator evals/sec + time-to-graph (n=1e6,d=20,K=30), mixed vs plain
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_recv_c3.json")
+KERNEL_SOURCES = ["paper_2202_00517_amd/csrc/knnd_kernels.hip", "paper_2202_00517_amd/csrc/knnd_device.h"]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def join_bytes_per_eval(D):
-    # gather of the candidate's FP64 log row plus its 4-byte index
-    return 8 * D + 4
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision):
+    """HBM bytes per receiver pass from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs recorded under profiles/, or None when the kernel sources changed
+    since those counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch", {}).get(precision)
+
+
+def copy_calibration():
+    """A plain device copy of 1 GiB: the reference for scaling FETCH_SIZE and
+    WRITE_SIZE (run under rocprofv3 --pmc)."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log("copied 1 GiB")
+
+
+def recv_bytes(n, K, D, mixed, rescues, psize=4):
+    """Algorithmic HBM bytes of one receiver pass (every size class of
+    k_recv, one round), as the kernel's algorithm moves them:
+      per receiver  its list ids and keys read (K*12), rowptr pair (16), the
+                    new list written (K*12)
+      per edge      the co-friend entry (col 4 B + slot 1 B) read twice: as a
+                    candidate and as the row of its friends
+      per occurrence (n(K + 2K^2) in all: co-friends, friends of friends,
+                    friends of co-friends) one 4-byte id for the K^2 + cK row
+                    entries and one key slot (8 B FP64 key; 4 B FP32 cross
+                    term in the mixed form)
+      mixed form    S(x), x's row and logs per receiver, and the candidate's
+                    FP64 log row per rescue"""
+    s = 4 if mixed else 8
+    b = n * (K * 24 + 16) + n * K * (10 + s) + 2 * n * K * K * (4 + s)
+    if mixed:
+        b += n * (8 + D * (psize + 8)) + rescues * D * 8
+    return b
 
 
 def cpu_baseline(P, d, K, seed, receivers, threads):
@@ -61,15 +115,20 @@ def cpu_baseline(P, d, K, seed, receivers, threads):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "plain"])
     ap.add_argument("--no-plain", action="store_true",
                     help="with --precision mixed, skip timing the plain descent beside it")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-receivers", type=int, default=60_000)
+    ap.add_argument("--cpu-receivers", type=int, default=400_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB on the device (reference run for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -134,18 +193,25 @@ def main():
                  "speedup_mixed_over_plain": pel / elapsed,
                  "identical_graph": bool(same)}
 
-    # roofline of the dominant kernel: the join (steps a2-a5), all launches of
-    # one round; algorithmic bytes = keys computed x (8 D + 4) bytes
-    join_ms = sum(s["ms_join"] for o, _ in results for s in o["stats"][1:])
-    join_rounds = sum(o["rounds"] for o, _ in results)
-    perf = sum(s["evals_performed"] for o, _ in results for s in o["stats"][1:])
-    bytes_alg = perf * join_bytes_per_eval(D)
-    achieved = bytes_alg / (join_ms * 1e-3) / 1e9 if join_ms > 0 else 0.0
+    # roofline of the dominant kernel: the receiver pass (k_recv, one launch
+    # per table-size class, steps a2-a5 on the receiver side), timed with HIP
+    # events on the library's stream around its launches in every timed round
+    rounds = [s for o, _ in results for s in o["stats"][1:]]
+    recv_ms = [s["ms_recv"] for s in rounds]
+    hub_ms = [s["ms_hub"] for s in rounds]
+    bytes_alg = sum(recv_bytes(n, K, D, mixed, s["rescues"]) for s in rounds)
+    achieved = bytes_alg / (sum(recv_ms) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "k_join (all receiver classes of one round)",
-                "avg_launch_ms": round(join_ms / max(join_rounds, 1), 3),
-                "bytes_per_launch": int(bytes_alg / max(join_rounds, 1))}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic(args.precision),
+                "kernel": "k_recv (all table-size classes of one round)",
+                "avg_launch_ms": round(sum(recv_ms) / len(recv_ms), 3),
+                "bytes_per_launch": int(bytes_alg / len(recv_ms))}
+    hub = {"kernel": "k_hub_mfma (split 16-bit MFMA cross terms)" if mixed
+           else "k_hub_reg (FP64 keys)", "avg_launch_ms": round(sum(hub_ms) / len(hub_ms), 3),
+           "evals_per_launch": int(sum(s["evals_performed"] - s["rescues"] for s in rounds)
+                                   / len(rounds))}
+    steps_ms = sorted(1e3 * t for _, t in results)
 
     line = {
         "metric": METRIC,
@@ -166,9 +232,11 @@ def main():
         "time_to_graph_ms": ms_per_step,
         "rounds": last["rounds"],
         "evals_alg": evals[0],
+        "median_ms_per_step": steps_ms[len(steps_ms) // 2],
         "per_round_ms": [round(s["ms"], 3) for s in last["stats"]],
         "rescues": sum(s["rescues"] for s in last["stats"]),
         "roofline": roofline,
+        "hub": hub,
     }
     if plain is not None:
         line["plain"] = plain

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define KNND_ABI_VERSION 1
+#define KNND_ABI_VERSION 2
 
 typedef enum {
     KNND_OK = 0,
@@ -64,10 +64,21 @@ typedef enum {
 
 typedef enum { KNND_F32 = 0, KNND_F64 = 1 } knnd_dtype;
 
+/*
+ * Precision of the key evaluation.  Every mode returns the same lists and
+ * keys (the canonical FP64 ones); the mixed modes only change speed and the
+ * `rescues` count.  In a mixed mode the cross term sum_i x_i log c_i is
+ * formed on the matrix cores from 16-bit operands, each split into a high
+ * and a low part (three products per pair, FP32 accumulation), and bounded
+ * by a proven error bound; a candidate gets its canonical FP64 key when its
+ * bound interval says it may enter the list.  The mixed modes apply when
+ * d+1 <= 64, every coordinate is <= 1 (points of the simplex) and the logs
+ * fit the 16-bit range; otherwise the exact hub form runs (same results).
+ */
 typedef enum {
     KNND_PREC_FP64 = 0,         /* every key computed in canonical FP64 */
-    KNND_PREC_MIXED_BF16 = 1,   /* reserved: BF16 cross term with FP64 recheck */
-    KNND_PREC_MIXED_FP16 = 2    /* reserved: FP16 cross term with FP64 recheck */
+    KNND_PREC_MIXED_BF16 = 1,   /* BF16 split operands, FP64 rescue */
+    KNND_PREC_MIXED_FP16 = 2    /* FP16 split operands, FP64 rescue */
 } knnd_precision;
 
 /* flags */
@@ -96,6 +107,10 @@ typedef struct {
     int64_t rescues;            /* FP64 rechecks (mixed precision only) */
     double ms;                  /* device time of the round (HIP events) */
     double ms_join;             /* device time of the join kernels (steps a2-a5) */
+    double ms_hub;              /* part of ms_join: the hub kernel (keys or cross
+                                   terms per snapshot edge; 0 in the pull form) */
+    double ms_recv;             /* part of ms_join: the receiver kernels (dedup,
+                                   rescue, merge, every size class) */
 } knnd_round_stats;
 
 /* Fill *p with the defaults (FP64, F32 points, M = min(n,10000), 100 rounds). */

@@ -35,6 +35,9 @@ EXPORTED = [
 ]
 
 
+ABI_VERSION = 2
+
+
 class knnd_params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("fcr_samples", ctypes.c_int64), ("max_rounds", ctypes.c_int32),
@@ -45,7 +48,8 @@ class knnd_round_stats(ctypes.Structure):
     _fields_ = [("updates", ctypes.c_int64), ("fcr_hits", ctypes.c_int64),
                 ("evals_alg", ctypes.c_int64), ("evals_performed", ctypes.c_int64),
                 ("rescues", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("ms_join", ctypes.c_double)]
+                ("ms_join", ctypes.c_double), ("ms_hub", ctypes.c_double),
+                ("ms_recv", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -93,6 +97,9 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    if L.knnd_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {L.knnd_abi_version()}, this binding "
+                           f"expects {ABI_VERSION}; rebuild the library")
     _lib = L
     return L
 

@@ -47,6 +47,7 @@ void free_ctx(Ctx& c) {
   if (c.ev1) (void)hipEventDestroy(c.ev1);
   if (c.evj0) (void)hipEventDestroy(c.evj0);
   if (c.evj1) (void)hipEventDestroy(c.evj1);
+  if (c.evh) (void)hipEventDestroy(c.evh);
   c = Ctx();
 }
 
@@ -135,6 +136,7 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   if (e == hipSuccess) e = hipEventCreate(&c.ev1);
   if (e == hipSuccess) e = hipEventCreate(&c.evj0);
   if (e == hipSuccess) e = hipEventCreate(&c.evj1);
+  if (e == hipSuccess) e = hipEventCreate(&c.evh);
   if (e != hipSuccess) return map_err(e);
   // Hub form: candidate rows of a hub must fit in LDS, and the key slots
   // (K(2K+1) per point) must fit in memory; otherwise the pull form.  The
@@ -227,9 +229,13 @@ int prepare_mixed(Ctx& c, size_t nK) {
 int read_stats(Ctx& c, knnd_round_stats* st, bool joined) {
   KNND_HIP(hipMemcpyAsync(c.hstats, c.dstats, knnd::STAT_N * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
   KNND_HIP(hipStreamSynchronize(c.stream));
-  float ms = 0.f, msj = 0.f;
+  float ms = 0.f, msj = 0.f, msh = 0.f, msr = 0.f;
   KNND_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
-  if (joined) KNND_HIP(hipEventElapsedTime(&msj, c.evj0, c.evj1));
+  if (joined) {
+    KNND_HIP(hipEventElapsedTime(&msj, c.evj0, c.evj1));
+    KNND_HIP(hipEventElapsedTime(&msh, c.evj0, c.evh));
+    KNND_HIP(hipEventElapsedTime(&msr, c.evh, c.evj1));
+  }
   if (st) {
     st->updates = c.hstats[knnd::STAT_UPDATES];
     st->fcr_hits = c.hstats[knnd::STAT_HITS];
@@ -238,6 +244,8 @@ int read_stats(Ctx& c, knnd_round_stats* st, bool joined) {
     st->rescues = c.hstats[knnd::STAT_RESCUES];
     st->ms = ms;
     st->ms_join = msj;
+    st->ms_hub = msh;
+    st->ms_recv = msr;
   }
   // an internal consistency check failed on the device (results are unusable)
   if (c.hstats[knnd::STAT_ERR] != 0) return KNND_ERR_DEVICE;
@@ -262,7 +270,9 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
   KNND_HIP(knnd::launch_bin(c));
   KNND_HIP(hipEventRecord(c.evj0, c.stream));
-  KNND_HIP(knnd::launch_join(c, c.dstats));
+  KNND_HIP(knnd::launch_join_hub(c, c.dstats));
+  KNND_HIP(hipEventRecord(c.evh, c.stream));
+  KNND_HIP(knnd::launch_join_recv(c, c.dstats));
   KNND_HIP(hipEventRecord(c.evj1, c.stream));
   KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], c.round + 1, c.dstats + knnd::STAT_HITS));
   KNND_HIP(hipEventRecord(c.ev1, c.stream));

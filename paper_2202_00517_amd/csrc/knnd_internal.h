@@ -71,7 +71,7 @@ struct Ctx {
   int64_t* dstats = nullptr;  // [STAT_N] device
   int64_t* hstats = nullptr;  // [STAT_N] pinned host
   int32_t* dflag = nullptr;   // device scratch flag
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, evj0 = nullptr, evj1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evj0 = nullptr, evj1 = nullptr, evh = nullptr;
 };
 
 struct JoinArgs {
@@ -107,7 +107,8 @@ hipError_t launch_init_graph(const Ctx& c);
 hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits);
 hipError_t launch_csr(const Ctx& c, const uint32_t* F);
 hipError_t launch_bin(const Ctx& c);
-hipError_t launch_join(const Ctx& c, int64_t* stats);
+hipError_t launch_join_hub(const Ctx& c, int64_t* stats);
+hipError_t launch_join_recv(const Ctx& c, int64_t* stats);
 hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits);
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out);
 hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad);

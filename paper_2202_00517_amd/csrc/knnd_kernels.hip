@@ -1508,7 +1508,7 @@ hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits) {
   return hipGetLastError();
 }
 
-hipError_t launch_join(const Ctx& c, int64_t* stats) {
+static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   JoinArgs a;
   a.P = c.P;
   a.L = c.L;
@@ -1538,17 +1538,23 @@ hipError_t launch_join(const Ctx& c, int64_t* stats) {
   a.S = c.S;
   a.eps_relq = c.eps_relq;
   a.eps_abs = c.eps_abs;
-  hipError_t e;
-  if (c.mixed) {
-    e = launch_hub_mfma(c, a);
-    if (e != hipSuccess) return e;
-    return c.dtype == 0 ? launch_recv_all<float, 2>(c, a) : launch_recv_all<double, 2>(c, a);
-  }
-  if (c.use_hub) {
-    e = c.dtype == 0 ? launch_hub<float>(c, a) : launch_hub<double>(c, a);
-    if (e != hipSuccess) return e;
-    return c.dtype == 0 ? launch_recv_all<float, 1>(c, a) : launch_recv_all<double, 1>(c, a);
-  }
+  return a;
+}
+
+// a2-a3: the hub kernel (keys or cross terms into the edge-indexed slots);
+// nothing in the pull form
+hipError_t launch_join_hub(const Ctx& c, int64_t* stats) {
+  const JoinArgs a = join_args(c, stats);
+  if (c.mixed) return launch_hub_mfma(c, a);
+  if (c.use_hub) return c.dtype == 0 ? launch_hub<float>(c, a) : launch_hub<double>(c, a);
+  return hipSuccess;
+}
+
+// a2-a5 receiver side: every size class of k_recv
+hipError_t launch_join_recv(const Ctx& c, int64_t* stats) {
+  const JoinArgs a = join_args(c, stats);
+  if (c.mixed) return c.dtype == 0 ? launch_recv_all<float, 2>(c, a) : launch_recv_all<double, 2>(c, a);
+  if (c.use_hub) return c.dtype == 0 ? launch_recv_all<float, 1>(c, a) : launch_recv_all<double, 1>(c, a);
   return c.dtype == 0 ? launch_recv_all<float, 0>(c, a) : launch_recv_all<double, 0>(c, a);
 }
 

@@ -40,7 +40,7 @@ def test_abi_version_and_status_strings():
 
 def test_params_struct_layout_matches_header():
     assert ctypes.sizeof(knnd.knnd_params) == 24
-    assert ctypes.sizeof(knnd.knnd_round_stats) == 56
+    assert ctypes.sizeof(knnd.knnd_round_stats) == 72
     p = knnd.default_params()
     assert (p.precision, p.dtype, p.fcr_samples, p.max_rounds, p.flags) == (0, 0, 0, 100, 0)
 
