@@ -156,6 +156,43 @@ int knnd_build_ex(const void* points, int64_t n, int32_t d, int32_t K, uint64_t 
                   int32_t* out_rounds);
 
 /*
+ * Batched form: B independent descents in one call (each instance exactly
+ * what knnd_build_ex would return for it with the same params).
+ *   inst        host array [B].  Per instance, inputs: points ([n][d+1] in
+ *               p->dtype, host or device memory per on_device), n, d, K, seed;
+ *               outputs: out_idx [n][K] int32 and optional out_kl [n][K] FP64
+ *               (same memory kind as points), optional host stats
+ *               [max_rounds + 1], host out_rounds, and status (KNND_OK or
+ *               KNND_WARN_MAX_ROUNDS).
+ *   p           shared parameters (NULL = defaults); fcr_samples <= 0 gives
+ *               each instance min(n, 10000) samples.
+ *   stream      as in knnd_build_ex; the host synchronises once per round for
+ *               all instances together.
+ * Instances are grouped by K and number of coordinates; a group runs as one
+ * set of launches per round, and an instance leaves its group's rounds after
+ * its own stop test.  Per-round times in an instance's stats are those of its
+ * group's round.  Returns KNND_OK, KNND_WARN_MAX_ROUNDS when some instance hit
+ * the round cap, or the first error (then every output is unspecified);
+ * argument errors of any instance are reported before any device work.
+ */
+typedef struct {
+    const void* points;
+    int64_t n;
+    int32_t d;
+    int32_t K;
+    uint64_t seed;
+    int32_t* out_idx;
+    double* out_kl;
+    knnd_round_stats* stats;
+    int32_t* out_rounds;
+    int32_t status;
+    int32_t reserved;
+} knnd_instance;
+
+int knnd_build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t on_device,
+                       void* stream);
+
+/*
  * Step-by-step interface (the same path, one call per step).  A context owns
  * its device buffers until knnd_ctx_destroy.  Pointers marked "kind" are host
  * memory when on_device == 0 and device memory when on_device != 0.

@@ -31,7 +31,7 @@ EXPORTED = [
     "knnd_default_params", "knnd_status_string", "knnd_abi_version", "knnd_build",
     "knnd_build_ex", "knnd_ctx_create", "knnd_ctx_init_graph", "knnd_ctx_set_graph",
     "knnd_ctx_round", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
-    "knnd_ctx_destroy",
+    "knnd_ctx_destroy", "knnd_build_batched",
 ]
 
 
@@ -53,6 +53,14 @@ class knnd_round_stats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class knnd_instance(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("seed", ctypes.c_uint64), ("out_idx", ctypes.c_void_p),
+                ("out_kl", ctypes.c_void_p), ("stats", ctypes.POINTER(knnd_round_stats)),
+                ("out_rounds", ctypes.POINTER(ctypes.c_int32)), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class KnndError(RuntimeError):
@@ -92,6 +100,7 @@ def lib():
         "knnd_ctx_get_log_table": (ctypes.c_int, [vp, vp, i32]),
         "knnd_ctx_rounds": (ctypes.c_int, [vp]),
         "knnd_ctx_destroy": (ctypes.c_int, [vp]),
+        "knnd_build_batched": (ctypes.c_int, [P(knnd_instance), i32, P(knnd_params), i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -202,6 +211,44 @@ def knnd_build_ex(points, d, K, seed, params=None, stream=None, with_kl=True):
     r = rounds.value
     return {"status": st, "idx": idx, "kl": kl, "rounds": r,
             "stats": [stats[i].as_dict() for i in range(r + 1)]}
+
+
+def knnd_build_batched(instances, params=None, stream=None, with_kl=True):
+    """Batched call.  instances: list of (points, d, K, seed), every points
+    array on the same side (numpy host arrays or torch device tensors) and of
+    the same dtype.  Returns (status, list of dicts like knnd_build_ex's)."""
+    if not instances:
+        raise ValueError("no instances")
+    p = params if params is not None else default_params()
+    p.dtype = _dtype_code(instances[0][0])
+    R = (p.max_rounds if p.max_rounds > 0 else 100) + 1
+    arr = (knnd_instance * len(instances))()
+    keep = []
+    dev = 1 if _is_device(instances[0][0]) else 0
+    for b, (points, d, K, seed) in enumerate(instances):
+        points = _check_points(points, d)
+        if (1 if _is_device(points) else 0) != dev or _dtype_code(points) != p.dtype:
+            raise ValueError("every instance must have the same memory kind and dtype")
+        n = points.shape[0]
+        idx = _empty(points, (n, K), np.int32)
+        kl = _empty(points, (n, K), np.float64) if with_kl else None
+        stats = (knnd_round_stats * R)()
+        rounds = ctypes.c_int32(0)
+        keep.append((points, idx, kl, stats, rounds))
+        arr[b].points, arr[b].n, arr[b].d, arr[b].K, arr[b].seed = _ptr(points), n, d, K, seed
+        arr[b].out_idx, arr[b].out_kl = _ptr(idx), _ptr(kl)
+        arr[b].stats = stats
+        arr[b].out_rounds = ctypes.pointer(rounds)
+    st = lib().knnd_build_batched(arr, len(instances), ctypes.byref(p), dev,
+                                  _stream_of(instances[0][0], stream))
+    if st < 0:
+        raise KnndError(st, "knnd_build_batched")
+    out = []
+    for b, (points, idx, kl, stats, rounds) in enumerate(keep):
+        r = rounds.value
+        out.append({"status": arr[b].status, "idx": idx, "kl": kl, "rounds": r,
+                    "stats": [stats[i].as_dict() for i in range(r + 1)]})
+    return st, out
 
 
 class Context:

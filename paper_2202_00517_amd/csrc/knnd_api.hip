@@ -9,7 +9,10 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "knnd.h"
 #include "knnd_internal.h"
@@ -39,10 +42,12 @@ void free_ctx(Ctx& c) {
   void* bufs[] = {c.P,      c.L,      c.F[0],   c.F[1],      c.keys[0],     c.keys[1],  c.deg,
                   c.fill,   c.rowptr, c.col,    c.colslot,   c.seg,
                   c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.gckey, c.bcand, c.bckey,
-                  c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32};
+                  c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32,
+                  c.inst_of, c.ioff, c.iseed, c.iM, c.iD, c.iactive, c.istats, c.vcnt};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c.hstats) (void)hipHostFree(c.hstats);
+  if (c.histats) (void)hipHostFree(c.histats);
   if (c.ev0) (void)hipEventDestroy(c.ev0);
   if (c.ev1) (void)hipEventDestroy(c.ev1);
   if (c.evj0) (void)hipEventDestroy(c.evj0);
@@ -76,14 +81,10 @@ int check_shape(int64_t n, int32_t d, int32_t K) {
 
 int prepare_mixed(Ctx& c, size_t nK);
 
-int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,
-           int32_t on_device, void* stream, Ctx& c) {
-  int st = check_shape(n, d, K);
-  if (st != KNND_OK) return st;
-  knnd_params prm;
-  st = resolve_params(p, n, &prm);
-  if (st != KNND_OK) return st;
-
+// Device check, fields and every device buffer of a context of n points
+// (a single instance, or a batched group with its per-instance arrays
+// allocated by the caller).
+int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params& prm, void* stream) {
   KNND_HIP(hipGetDevice(&c.device));
   hipDeviceProp_t prop;
   KNND_HIP(hipGetDeviceProperties(&prop, c.device));
@@ -161,11 +162,17 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
     c.use_hub = false;
   }
 
-  const size_t pbytes = (size_t)n * c.D * esz;
-  KNND_HIP(hipMemcpyAsync(c.P, points, pbytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                          c.stream));
+  return KNND_OK;
+}
+
+// After the points are in c.P: tail padding, log table with the domain
+// check, and the mixed-precision operands.
+int finish_create(Ctx& c) {
+  const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
+  const size_t nK = (size_t)c.n * c.K;
+  const size_t pbytes = (size_t)c.n * c.D * esz;
   KNND_HIP(hipMemsetAsync(static_cast<char*>(c.P) + pbytes, 0, knnd::HUB_MAXD * esz, c.stream));
-  KNND_HIP(hipMemsetAsync(c.L + (size_t)n * c.Dp, 0, knnd::HUB_MAXD * sizeof(double), c.stream));
+  KNND_HIP(hipMemsetAsync(c.L + (size_t)c.n * c.Dp, 0, knnd::HUB_MAXD * sizeof(double), c.stream));
   KNND_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int32_t), c.stream));
   KNND_HIP(knnd::launch_log_table(c, c.dflag));
   int32_t bad = 0;
@@ -174,6 +181,21 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   if (bad) return KNND_ERR_DOMAIN;
   if (c.mixed) return prepare_mixed(c, nK);
   return KNND_OK;
+}
+
+int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,
+           int32_t on_device, void* stream, Ctx& c) {
+  int st = check_shape(n, d, K);
+  if (st != KNND_OK) return st;
+  knnd_params prm;
+  st = resolve_params(p, n, &prm);
+  if (st != KNND_OK) return st;
+  st = setup(c, n, d, K, seed, prm, stream);
+  if (st != KNND_OK) return st;
+  const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
+  KNND_HIP(hipMemcpyAsync(c.P, points, (size_t)n * c.D * esz,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.stream));
+  return finish_create(c);
 }
 
 // Split 16-bit operand copies and the error-bound constants of the mixed
@@ -299,6 +321,241 @@ int get_graph(Ctx& c, int32_t* idx, double* kl, int32_t on_device) {
 
 bool should_stop(int64_t hits_prev, int64_t hits, int64_t updates, int r, int max_rounds) {
   return hits <= hits_prev || updates == 0 || r >= max_rounds;
+}
+
+// ---------------------------------------------------------------------------
+// Batched instances.  Instances with the same K and a similar number of
+// coordinates form a group: one context whose points are the instances'
+// points one after the other, zero-padded to the group's largest d+1 (a
+// padded coordinate has log entry 0 and adds exactly nothing to any key).
+// Every list stays inside its instance, so a round of the group is a round of
+// each instance still running.  The stop test is taken per instance; a
+// stopped instance's lists are copied out and it is left out of later rounds
+// (its hubs and receivers are skipped).
+// ---------------------------------------------------------------------------
+int coord_bucket(int D) {
+  static const int b[] = {8, 12, 16, 24, 32, 40, 52, 64};
+  for (int v : b)
+    if (D <= v) return v;
+  return (D + 15) / 16 * 16;
+}
+
+struct Group {
+  Ctx c;
+  std::vector<int> members;     // indices into the caller's instance array
+  std::vector<int64_t> off;     // [nb+1] first point of each member
+  std::vector<int32_t> active;  // host copy of c.iactive
+  std::vector<int64_t> hits_prev;
+  int32_t* staging = nullptr;   // device [max n_b][K]: host-bound lists
+  bool dirty = false;           // active flags changed since the last upload
+  int running = 0;
+};
+
+void free_group(Group& g) {
+  if (g.staging) (void)hipFree(g.staging);
+  g.staging = nullptr;
+  free_ctx(g.c);
+}
+
+int create_group(Group& g, const knnd_instance* inst, const knnd_params& prm, int32_t on_device, void* stream) {
+  Ctx& c = g.c;
+  const int nb = (int)g.members.size();
+  const knnd_instance& first = inst[g.members[0]];
+  int64_t N = 0, nmax = 0;
+  int Dmax = 0;
+  g.off.assign(nb + 1, 0);
+  for (int j = 0; j < nb; ++j) {
+    const knnd_instance& in = inst[g.members[j]];
+    g.off[j] = N;
+    N += in.n;
+    nmax = std::max(nmax, in.n);
+    Dmax = std::max(Dmax, in.d + 1);
+  }
+  g.off[nb] = N;
+  if (N >= (int64_t)knnd::IDMASK_HOST) return KNND_ERR_ARG;
+  int st = setup(c, N, Dmax - 1, first.K, 0, prm, stream);
+  if (st != KNND_OK) return st;
+  c.nb = nb;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = dalloc(&c.inst_of, (size_t)N);
+  if (e == hipSuccess) e = dalloc(&c.ioff, (size_t)nb + 1);
+  if (e == hipSuccess) e = dalloc(&c.iseed, (size_t)nb);
+  if (e == hipSuccess) e = dalloc(&c.iM, (size_t)nb);
+  if (e == hipSuccess) e = dalloc(&c.iD, (size_t)nb);
+  if (e == hipSuccess) e = dalloc(&c.iactive, (size_t)nb);
+  if (e == hipSuccess) e = dalloc(&c.istats, (size_t)nb * knnd::STAT_N);
+  if (e == hipSuccess) e = dalloc(&c.vcnt, (size_t)N * knnd::VC_N);
+  if (e == hipSuccess && !on_device) e = dalloc(&g.staging, (size_t)nmax * c.K);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&c.histats), (size_t)nb * knnd::STAT_N * sizeof(int64_t));
+  if (e != hipSuccess) return map_err(e);
+
+  std::vector<int32_t> inst_of((size_t)N), iD(nb), act(nb, 1);
+  std::vector<uint64_t> iseed(nb);
+  std::vector<int64_t> iM(nb);
+  for (int j = 0; j < nb; ++j) {
+    const knnd_instance& in = inst[g.members[j]];
+    std::fill(inst_of.begin() + g.off[j], inst_of.begin() + g.off[j + 1], j);
+    iD[j] = in.d + 1;
+    iseed[j] = in.seed;
+    iM[j] = prm.fcr_samples > 0 ? prm.fcr_samples : std::min<int64_t>(in.n, 10000);
+    c.Mmax = std::max(c.Mmax, iM[j]);
+  }
+  KNND_HIP(hipMemcpy(c.inst_of, inst_of.data(), (size_t)N * 4, hipMemcpyHostToDevice));
+  KNND_HIP(hipMemcpy(c.ioff, g.off.data(), ((size_t)nb + 1) * 8, hipMemcpyHostToDevice));
+  KNND_HIP(hipMemcpy(c.iseed, iseed.data(), (size_t)nb * 8, hipMemcpyHostToDevice));
+  KNND_HIP(hipMemcpy(c.iM, iM.data(), (size_t)nb * 8, hipMemcpyHostToDevice));
+  KNND_HIP(hipMemcpy(c.iD, iD.data(), (size_t)nb * 4, hipMemcpyHostToDevice));
+  KNND_HIP(hipMemcpy(c.iactive, act.data(), (size_t)nb * 4, hipMemcpyHostToDevice));
+  g.active = act;
+  g.hits_prev.assign(nb, 0);
+  g.running = nb;
+
+  // points, zero-padded to Dmax coordinates
+  const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
+  KNND_HIP(hipMemsetAsync(c.P, 0, (size_t)N * c.D * esz, c.stream));
+  for (int j = 0; j < nb; ++j) {
+    const knnd_instance& in = inst[g.members[j]];
+    const size_t w = (size_t)(in.d + 1) * esz;
+    KNND_HIP(hipMemcpy2DAsync(static_cast<char*>(c.P) + (size_t)g.off[j] * c.D * esz, (size_t)c.D * esz,
+                              in.points, w, w, (size_t)in.n,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.stream));
+  }
+  return finish_create(c);
+}
+
+// Enqueue round r (r = 0: the start graph and its FCR) of every running
+// instance of the group, and the copy of the per-instance counters.
+int group_round(Group& g, int r) {
+  Ctx& c = g.c;
+  KNND_HIP(knnd::launch_zero_i64(c.istats, (int64_t)c.nb * knnd::STAT_N, c.stream));
+  KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
+  KNND_HIP(hipEventRecord(c.ev0, c.stream));
+  if (r == 0) {
+    KNND_HIP(knnd::launch_init_graph(c));
+    KNND_HIP(knnd::launch_fcr(c, c.F[c.cur], 0, nullptr));
+  } else {
+    KNND_HIP(knnd::launch_zero_i32(c.vcnt, c.n * knnd::VC_N, c.stream));
+    KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
+    KNND_HIP(knnd::launch_bin(c));
+    KNND_HIP(hipEventRecord(c.evj0, c.stream));
+    KNND_HIP(knnd::launch_join_hub(c, c.dstats));
+    KNND_HIP(hipEventRecord(c.evh, c.stream));
+    KNND_HIP(knnd::launch_join_recv(c, c.dstats));
+    KNND_HIP(hipEventRecord(c.evj1, c.stream));
+    KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], r, nullptr));
+    KNND_HIP(knnd::launch_batch_reduce(c));
+    c.cur ^= 1;
+  }
+  KNND_HIP(hipEventRecord(c.ev1, c.stream));
+  c.round = r;
+  KNND_HIP(hipMemcpyAsync(c.histats, c.istats, (size_t)c.nb * knnd::STAT_N * 8, hipMemcpyDeviceToHost, c.stream));
+  KNND_HIP(hipMemcpyAsync(c.hstats, c.dstats, knnd::STAT_N * 8, hipMemcpyDeviceToHost, c.stream));
+  return KNND_OK;
+}
+
+// Copy member j's current lists (and keys) to its outputs.
+int group_emit(Group& g, int j, const knnd_instance& in, int32_t on_device) {
+  Ctx& c = g.c;
+  const int64_t off = g.off[j], cnt = in.n * (int64_t)c.K;
+  const double* kl = c.keys[c.cur] + off * c.K;
+  if (on_device) {
+    KNND_HIP(knnd::launch_emit(c, off, in.n, in.out_idx));
+    if (in.out_kl) KNND_HIP(hipMemcpyAsync(in.out_kl, kl, cnt * 8, hipMemcpyDeviceToDevice, c.stream));
+  } else {
+    KNND_HIP(knnd::launch_emit(c, off, in.n, g.staging));
+    KNND_HIP(hipMemcpyAsync(in.out_idx, g.staging, cnt * 4, hipMemcpyDeviceToHost, c.stream));
+    if (in.out_kl) KNND_HIP(hipMemcpyAsync(in.out_kl, kl, cnt * 8, hipMemcpyDeviceToHost, c.stream));
+  }
+  return KNND_OK;
+}
+
+int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t on_device, void* stream) {
+  if (!inst || B < 1) return KNND_ERR_ARG;
+  knnd_params prm;
+  int st = resolve_params(p, 0, &prm);  // fcr_samples stays 0: per instance min(n, 10000)
+  if (st != KNND_OK) return st;
+  std::map<std::pair<int, int>, std::vector<int>> by_shape;
+  for (int b = 0; b < B; ++b) {
+    const knnd_instance& in = inst[b];
+    if (!in.points || !in.out_idx || !in.out_rounds) return KNND_ERR_ARG;
+    st = check_shape(in.n, in.d, in.K);
+    if (st != KNND_OK) return st;
+    by_shape[{in.K, coord_bucket(in.d + 1)}].push_back(b);
+  }
+  std::vector<Group> groups(by_shape.size());
+  size_t gi = 0;
+  for (auto& kv : by_shape) groups[gi++].members = kv.second;
+  int worst = KNND_OK;
+  auto fail = [&](int s) {
+    for (Group& g : groups) {
+      (void)hipStreamSynchronize(g.c.stream);
+      free_group(g);
+    }
+    return s;
+  };
+  for (Group& g : groups) {
+    st = create_group(g, inst, prm, on_device, stream);
+    if (st != KNND_OK) return fail(st);
+  }
+  int running = B;
+  for (int r = 0; running > 0; ++r) {
+    for (Group& g : groups)
+      if (g.running > 0 && (st = group_round(g, r)) != KNND_OK) return fail(st);
+    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return fail(KNND_ERR_DEVICE);
+    for (Group& g : groups) {
+      if (g.running == 0 || g.c.round != r) continue;
+      Ctx& c = g.c;
+      if (c.hstats[knnd::STAT_ERR] != 0) return fail(KNND_ERR_DEVICE);
+      float ms = 0.f, msj = 0.f, msh = 0.f, msr = 0.f;
+      if (hipEventElapsedTime(&ms, c.ev0, c.ev1) != hipSuccess) return fail(KNND_ERR_DEVICE);
+      if (r > 0 && (hipEventElapsedTime(&msj, c.evj0, c.evj1) != hipSuccess ||
+                    hipEventElapsedTime(&msh, c.evj0, c.evh) != hipSuccess ||
+                    hipEventElapsedTime(&msr, c.evh, c.evj1) != hipSuccess))
+        return fail(KNND_ERR_DEVICE);
+      for (int j = 0; j < c.nb; ++j) {
+        if (!g.active[j]) continue;
+        knnd_instance& in = inst[g.members[j]];
+        const int64_t* s = c.histats + (size_t)j * knnd::STAT_N;
+        knnd_round_stats rs;
+        rs.updates = s[knnd::STAT_UPDATES];
+        rs.fcr_hits = s[knnd::STAT_HITS];
+        rs.evals_alg = s[knnd::STAT_EVALS];
+        rs.evals_performed = s[knnd::STAT_PERF];
+        rs.rescues = s[knnd::STAT_RESCUES];
+        rs.ms = ms;
+        rs.ms_join = msj;
+        rs.ms_hub = msh;
+        rs.ms_recv = msr;
+        if (in.stats) in.stats[r] = rs;
+        if (r == 0) {
+          g.hits_prev[j] = rs.fcr_hits;
+          continue;
+        }
+        if (should_stop(g.hits_prev[j], rs.fcr_hits, rs.updates, r, prm.max_rounds)) {
+          const bool capped = r >= prm.max_rounds && rs.fcr_hits > g.hits_prev[j] && rs.updates != 0;
+          in.status = capped ? KNND_WARN_MAX_ROUNDS : KNND_OK;
+          if (capped) worst = KNND_WARN_MAX_ROUNDS;
+          *in.out_rounds = r;
+          if ((st = group_emit(g, j, in, on_device)) != KNND_OK) return fail(st);
+          g.active[j] = 0;
+          g.dirty = true;
+          --g.running;
+          --running;
+        } else {
+          g.hits_prev[j] = rs.fcr_hits;
+        }
+      }
+      if (g.dirty && g.running > 0) {
+        if (hipMemcpyAsync(c.iactive, g.active.data(), (size_t)c.nb * 4, hipMemcpyHostToDevice, c.stream) !=
+            hipSuccess)
+          return fail(KNND_ERR_DEVICE);
+        g.dirty = false;
+      }
+    }
+  }
+  (void)fail(KNND_OK);
+  return worst;
 }
 
 }  // namespace
@@ -432,6 +689,10 @@ int knnd_build_ex(const void* points, int64_t n, int32_t d, int32_t K, uint64_t 
   }
   knnd_ctx_destroy(h);
   return st;
+}
+
+int knnd_build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t on_device, void* stream) {
+  return build_batched(inst, B, p, on_device, stream);
 }
 
 int knnd_build(const float* points, int64_t n, int32_t d, int32_t K, uint64_t seed, int32_t* out_idx,

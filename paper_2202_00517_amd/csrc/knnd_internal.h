@@ -20,6 +20,10 @@ constexpr uint32_t CLASS_CAP_MIN = 512;
 
 // Per-round device counters
 enum { STAT_UPDATES = 0, STAT_HITS = 1, STAT_EVALS = 2, STAT_PERF = 3, STAT_RESCUES = 4, STAT_ERR = 5, STAT_N = 8 };
+// Per-point counters of one round in a batched group (summed per instance):
+// evaluations and updates of receiver x, keys computed by hub x, keys
+// computed by receiver x (pull form and rescues), rescues of receiver x
+enum { VC_EVALS = 0, VC_UPD = 1, VC_HUBPERF = 2, VC_RECVPERF = 3, VC_RESC = 4, VC_N = 5 };
 
 struct Ctx {
   int device = 0;
@@ -72,6 +76,21 @@ struct Ctx {
   int64_t* hstats = nullptr;  // [STAT_N] pinned host
   int32_t* dflag = nullptr;   // device scratch flag
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evj0 = nullptr, evj1 = nullptr, evh = nullptr;
+
+  // Batched group (nb > 0): nb independent instances laid out one after the
+  // other in [0, n); every list stays inside its instance, so one round of
+  // the group is one round of each active instance.
+  int nb = 0;
+  int32_t* inst_of = nullptr;  // [n] instance of each point
+  int64_t* ioff = nullptr;     // [nb+1] first point of each instance (ioff[nb] = n)
+  uint64_t* iseed = nullptr;   // [nb] seed of each instance
+  int64_t* iM = nullptr;       // [nb] FCR samples of each instance
+  int32_t* iD = nullptr;       // [nb] coordinates of each instance (<= D; the rest is zero padding)
+  int32_t* iactive = nullptr;  // [nb] nonzero while the instance runs
+  int64_t* istats = nullptr;   // [nb][STAT_N] per-instance counters of the round
+  int64_t* histats = nullptr;  // [nb][STAT_N] pinned host copy
+  int32_t* vcnt = nullptr;     // [n][VC_N] per-point counters of the round
+  int64_t Mmax = 0;            // largest iM
 };
 
 struct JoinArgs {
@@ -99,6 +118,10 @@ struct JoinArgs {
   int64_t gstride;
   uint32_t* bcand;
   double* bckey;
+  // batched groups (null otherwise)
+  const int32_t* inst_of;
+  const int32_t* iactive;
+  int32_t* vcnt;
 };
 
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
@@ -112,5 +135,9 @@ hipError_t launch_join_recv(const Ctx& c, int64_t* stats);
 hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits);
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out);
 hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad);
+// batched groups
+hipError_t launch_batch_reduce(const Ctx& c);
+hipError_t launch_emit(const Ctx& c, int64_t off, int64_t n_b, int32_t* out_idx);
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
 
 }  // namespace knnd

@@ -50,15 +50,18 @@ __global__ void k_load_idx(const int32_t* __restrict__ idx, int64_t cnt, int64_t
 // ---------------------------------------------------------------------------
 // a0: log table (and domain check of every coordinate)
 // ---------------------------------------------------------------------------
+// In a batched group, coordinates past an instance's own d+1 are zero padding
+// (log entry 0, not checked): they add exactly nothing to any key.
 template <typename PT>
 __global__ void k_log_table(const PT* __restrict__ P, int64_t n, int D, int Dp, double* __restrict__ L,
-                            int32_t* __restrict__ bad) {
+                            int32_t* __restrict__ bad, const int32_t* __restrict__ inst_of,
+                            const int32_t* __restrict__ iD) {
   const int64_t total = n * Dp;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = t / Dp;
     const int i = (int)(t - j * Dp);
     double out = 0.0;
-    if (i < D) {
+    if (i < (inst_of ? iD[inst_of[j]] : D)) {
       const double v = (double)P[j * D + i];
       if (!(v > 0.0) || isinf(v)) {
         atomicOr(bad, 1);
@@ -74,21 +77,35 @@ __global__ void k_log_table(const PT* __restrict__ P, int64_t n, int D, int Dp, 
 // a0: random K-out start, one wave per point (Section 3.2).  Draw a of x is
 // y = r + (r >= x), r = bound(H(seed,1,x,a), n-1); the first K distinct draws
 // are kept, 64 draws at a time (one per lane), then sorted by (key, index).
+// In a batched group x, y, n and seed are those of x's instance (indices
+// local to it, stored offset by its first point).
 // ---------------------------------------------------------------------------
 template <typename PT>
 __global__ __launch_bounds__(256) void k_init_graph(const PT* __restrict__ P, const double* __restrict__ L,
                                                     int64_t n, int D, int Dp, int K, uint64_t seed,
-                                                    uint32_t* __restrict__ F, double* __restrict__ keys) {
+                                                    uint32_t* __restrict__ F, double* __restrict__ keys,
+                                                    const int32_t* __restrict__ inst_of,
+                                                    const int64_t* __restrict__ ioff,
+                                                    const uint64_t* __restrict__ iseed) {
   __shared__ uint32_t slot[4][WAVE];
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
   const int64_t x = (int64_t)blockIdx.x * 4 + wave;
   if (x >= n) return;  // whole wave; no block-level barrier follows
+  int64_t base = 0, nn = n;
+  uint64_t sd = seed;
+  if (inst_of) {
+    const int b = inst_of[x];
+    base = ioff[b];
+    nn = ioff[b + 1] - base;
+    sd = iseed[b];
+  }
+  const uint64_t xl = (uint64_t)(x - base);
   uint32_t mine = IDMASK;
   int count = 0;
   for (uint64_t a0 = 0; count < K; a0 += WAVE) {
-    const uint64_t r = bound(hash4(seed, 1, (uint64_t)x, a0 + lane), (uint64_t)(n - 1));
-    const uint32_t y = (uint32_t)(r + (r >= (uint64_t)x ? 1 : 0));
+    const uint64_t r = bound(hash4(sd, 1, xl, a0 + lane), (uint64_t)(nn - 1));
+    const uint32_t y = (uint32_t)(base + r + (r >= xl ? 1 : 0));
     bool dup = false;
     for (int j = 0; j < count; ++j) dup |= (shfl_u32(mine, j) == y);
     for (int l = 0; l < WAVE - 1; ++l) {
@@ -137,6 +154,74 @@ __global__ __launch_bounds__(256) void k_fcr(const uint32_t* __restrict__ F, int
   }
   const uint64_t m = __ballot(hit);
   if (lane_id() == 0 && m) atomicAdd((unsigned long long*)hits, (unsigned long long)__popcll(m));
+}
+
+// The same sample for every active instance of a batched group (grid y =
+// instance), in the instance's own indices and seed.
+__global__ __launch_bounds__(256) void k_fcr_batched(const uint32_t* __restrict__ F, int K,
+                                                     const int64_t* __restrict__ ioff,
+                                                     const uint64_t* __restrict__ iseed,
+                                                     const int64_t* __restrict__ iM,
+                                                     const int32_t* __restrict__ iactive, int64_t round,
+                                                     int64_t* __restrict__ istats) {
+  const int b = blockIdx.y;
+  if (!iactive[b]) return;  // whole block
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t base = ioff[b], nn = ioff[b + 1] - base;
+  const uint64_t seed = iseed[b];
+  bool hit = false;
+  if (s < iM[b]) {
+    const int64_t x = base + (int64_t)bound(hash4(seed, 2, (uint64_t)round, (uint64_t)s), (uint64_t)nn);
+    const int av = (int)bound(hash4(seed, 3, (uint64_t)round, (uint64_t)s), (uint64_t)K);
+    const int bp = (int)bound(hash4(seed, 4, (uint64_t)round, (uint64_t)s), (uint64_t)(K - 1));
+    const int bv = bp + (bp >= av ? 1 : 0);
+    const uint32_t y = F[x * K + av] & IDMASK;
+    const uint32_t z = F[x * K + bv] & IDMASK;
+    for (int j = 0; j < K; ++j)
+      hit |= ((F[(int64_t)z * K + j] & IDMASK) == y) || ((F[(int64_t)y * K + j] & IDMASK) == z);
+  }
+  const uint64_t m = __ballot(hit);
+  if (lane_id() == 0 && m)
+    atomicAdd((unsigned long long*)&istats[(int64_t)b * STAT_N + STAT_HITS], (unsigned long long)__popcll(m));
+}
+
+// Per-instance sums of the per-point counters of one round (one block per
+// active instance).
+__global__ __launch_bounds__(256) void k_batch_reduce(const int32_t* __restrict__ vcnt,
+                                                      const int64_t* __restrict__ ioff,
+                                                      const int32_t* __restrict__ iactive,
+                                                      int64_t* __restrict__ istats) {
+  const int b = blockIdx.x;
+  if (!iactive[b]) return;  // whole block
+  __shared__ int64_t s_sum[VC_N][4];
+  int64_t acc[VC_N] = {0, 0, 0, 0, 0};
+  for (int64_t v = ioff[b] + threadIdx.x; v < ioff[b + 1]; v += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < VC_N; ++q) acc[q] += vcnt[v * VC_N + q];
+  }
+#pragma unroll
+  for (int q = 0; q < VC_N; ++q) {
+    int64_t t = acc[q];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) t += (int64_t)shfl_xor_u64((uint64_t)t, o);
+    if (lane_id() == 0) s_sum[q][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t tot[VC_N];
+    for (int q = 0; q < VC_N; ++q) tot[q] = s_sum[q][0] + s_sum[q][1] + s_sum[q][2] + s_sum[q][3];
+    int64_t* st = istats + (int64_t)b * STAT_N;
+    st[STAT_EVALS] = tot[VC_EVALS];
+    st[STAT_UPDATES] = tot[VC_UPD];
+    st[STAT_PERF] = tot[VC_HUBPERF] + tot[VC_RECVPERF];
+    st[STAT_RESCUES] = tot[VC_RESC];
+  }
+}
+
+// Rows [off, off + nb) of the lists, as indices local to their instance.
+__global__ void k_emit(const uint32_t* __restrict__ F, int64_t off, int64_t cnt, int K, int32_t* __restrict__ out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cnt; t += (int64_t)gridDim.x * blockDim.x)
+    out[t] = (int32_t)((int64_t)(F[off * K + t] & IDMASK) - off);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,13 +326,16 @@ __device__ __forceinline__ int64_t table_need(int64_t c, int K, int64_t n) {
 }
 
 __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr, int64_t n, int K,
-                                             int32_t* __restrict__ counts, int32_t* __restrict__ lists) {
+                                             int32_t* __restrict__ counts, int32_t* __restrict__ lists,
+                                             const int32_t* __restrict__ inst_of,
+                                             const int32_t* __restrict__ iactive) {
   const int lane = lane_id();
   // uniform trip count so that every lane takes part in the ballots
   for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = x0 + threadIdx.x;
     int cls = -1;
-    if (x < n) {
+    // (receivers of a stopped instance of a batched group are not binned)
+    if (x < n && (!inst_of || iactive[inst_of[x]])) {
       const int64_t c = rowptr[x + 1] - rowptr[x];
       const int64_t need2 = 2 * table_need(c, K, n);
       if (need2 <= (int64_t)(CLASS_CAP_MIN << 4)) {  // exact bound fits a small table
@@ -286,6 +374,18 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* sh /*[4]*/) {
   const int64_t t = sh[0] + sh[1] + sh[2] + sh[3];
   __syncthreads();
   return t;
+}
+
+// Batched groups: hubs and receivers of a stopped instance are skipped, and
+// the keys one hub computed go to its per-point counter (one wave per hub).
+__device__ __forceinline__ bool inactive(const JoinArgs& a, int64_t v) {
+  return a.iactive && !a.iactive[a.inst_of[v]];
+}
+__device__ __forceinline__ void hub_count(const JoinArgs& a, int64_t v, int64_t d) {
+  if (!a.vcnt) return;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) d += (int64_t)shfl_xor_u64((uint64_t)d, o);
+  if (lane_id() == 0) a.vcnt[v * VC_N + VC_HUBPERF] = (int32_t)d;
 }
 
 // ---------------------------------------------------------------------------
@@ -329,6 +429,8 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
   int64_t my_perf = 0;
 
   for (int64_t v = blockIdx.x; v < a.n; v += gridDim.x) {
+    if (inactive(a, v)) continue;  // whole block
+    const int64_t pf0 = my_perf;
     const int64_t rp = a.rowptr[v];
     const int cv = (int)(a.rowptr[v + 1] - rp);
     bool anynew = !a.skip;
@@ -388,6 +490,7 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
         ++my_perf;
       }
     }
+    if (a.vcnt && my_perf != pf0) atomicAdd(&a.vcnt[v * VC_N + VC_HUBPERF], (int32_t)(my_perf - pf0));
     __syncthreads();
   }
   __shared__ int64_t s_red[4];
@@ -432,6 +535,8 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   int64_t my_perf = 0;
   for (int64_t v = (int64_t)blockIdx.x * 4 + wv; v < a.n; v += nwaves) {
+    if (inactive(a, v)) continue;  // whole wave
+    const int64_t pf0 = my_perf;
     const int64_t rp = a.rowptr[v];
     const int cv = (int)(a.rowptr[v + 1] - rp);
     const uint32_t fv = lane < K ? a.F[v * K + lane] : 0u;  // lane j holds F(v)[j]
@@ -519,6 +624,7 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
         }
       }
     }
+    hub_count(a, v, my_perf - pf0);
   }
   __shared__ int64_t s_red[4];
   const int64_t pf = block_sum(my_perf, s_red);
@@ -607,6 +713,8 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   int64_t my_perf = 0;
   for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < a.n; v += nwaves) {
+    if (inactive(a, v)) continue;  // whole wave
+    const int64_t pf0 = my_perf;
     const int64_t rp = a.rowptr[v];
     const int cv = (int)(a.rowptr[v + 1] - rp);
     const uint32_t fv = lane < K ? a.F[v * K + lane] : 0u;
@@ -702,6 +810,7 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
         }
       }
     }
+    hub_count(a, v, my_perf - pf0);
   }
   __shared__ int64_t s_red[4];
   const int64_t pf = block_sum(my_perf, s_red);
@@ -881,6 +990,7 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
   if (lane == 0) {
     my_upd += (int64_t)__popcll(um);
     my_err += (int64_t)__popcll(bm);
+    if (a.vcnt) a.vcnt[x * VC_N + VC_UPD] = (int32_t)__popcll(um);
   }
 }
 
@@ -930,6 +1040,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
   __shared__ uint64_t s_tau;
   __shared__ double s_theta;
   __shared__ int s_ncand, s_nuniq, s_over, s_ns, s_bstar;
+  __shared__ int s_iev, s_ipf, s_irs;  // batched groups: this receiver's counters
   __shared__ int64_t s_red[NW];
   __shared__ double s_dred[NW];
 
@@ -973,10 +1084,14 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
 
     // A: clear
     for (uint32_t s = tid; s < cap; s += NT) tab[s] = EMPTY;
+    const int64_t pf_item0 = my_perf;
     if (tid == 0) {
       s_ncand = 0;
       s_nuniq = 0;
       s_over = 0;
+      s_iev = 0;
+      s_ipf = 0;
+      s_irs = 0;
       s_tau = key_bits(a.keys[x * K + K - 1]);
     }
     __syncthreads();
@@ -1092,6 +1207,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
         if (over) break;
       }
     }
+    if (a.vcnt && item_evals) atomicAdd(&s_iev, (int)item_evals);
     __syncthreads();
     if (GUARD && s_over) {  // table too small: the global-memory class redoes this receiver
       if (tid == 0) {
@@ -1131,6 +1247,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
       __syncthreads();
       const int ns = s_ns;
       my_resc += tid == 0 ? ns : 0;
+      if (tid == 0) s_irs = ns;  // (read after the item's last barrier)
       if (ns <= SEL_SURV) {
         // canonical keys of the rescue set, then wave 0 merges them into the
         // old list
@@ -1321,7 +1438,13 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
         write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
       }
     }
+    if (a.vcnt && my_perf != pf_item0) atomicAdd(&s_ipf, (int)(my_perf - pf_item0));
     __syncthreads();
+    if (a.vcnt && tid == 0) {
+      a.vcnt[x * VC_N + VC_EVALS] = s_iev;
+      a.vcnt[x * VC_N + VC_RECVPERF] = s_ipf + s_irs;
+      a.vcnt[x * VC_N + VC_RESC] = s_irs;
+    }
   }
   const int64_t ev = block_sum_nw<NW>(my_evals, s_red);
   const int64_t pf = block_sum_nw<NW>(my_perf, s_red);
@@ -1360,10 +1483,10 @@ hipError_t launch_log_table(const Ctx& c, int32_t* bad) {
   const int g = grid_for(total, 256, 65536);
   if (c.dtype == 0)
     hipLaunchKernelGGL(k_log_table<float>, dim3(g), dim3(256), 0, c.stream, (const float*)c.P, c.n, c.D, c.Dp,
-                       c.L, bad);
+                       c.L, bad, c.inst_of, c.iD);
   else
     hipLaunchKernelGGL(k_log_table<double>, dim3(g), dim3(256), 0, c.stream, (const double*)c.P, c.n, c.D, c.Dp,
-                       c.L, bad);
+                       c.L, bad, c.inst_of, c.iD);
   return hipGetLastError();
 }
 
@@ -1373,16 +1496,40 @@ hipError_t launch_init_graph(const Ctx& c) {
   double* keys = c.keys[c.cur];
   if (c.dtype == 0)
     hipLaunchKernelGGL(k_init_graph<float>, dim3(g), dim3(256), 0, c.stream, (const float*)c.P, c.L, c.n, c.D,
-                       c.Dp, c.K, c.seed, F, keys);
+                       c.Dp, c.K, c.seed, F, keys, c.inst_of, c.ioff, c.iseed);
   else
     hipLaunchKernelGGL(k_init_graph<double>, dim3(g), dim3(256), 0, c.stream, (const double*)c.P, c.L, c.n, c.D,
-                       c.Dp, c.K, c.seed, F, keys);
+                       c.Dp, c.K, c.seed, F, keys, c.inst_of, c.ioff, c.iseed);
   return hipGetLastError();
 }
 
+// (batched group: per-instance samples, hits into istats; `hits` unused)
 hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits) {
+  if (c.nb > 0) {
+    const int gx = grid_for(c.Mmax, 256, 1 << 30);
+    hipLaunchKernelGGL(k_fcr_batched, dim3(gx, c.nb), dim3(256), 0, c.stream, F, c.K, c.ioff, c.iseed, c.iM,
+                       c.iactive, round, c.istats);
+    return hipGetLastError();
+  }
   const int g = grid_for(c.M, 256, 1 << 30);
   hipLaunchKernelGGL(k_fcr, dim3(g), dim3(256), 0, c.stream, F, c.n, c.K, c.seed, round, c.M, hits);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(const Ctx& c) {
+  hipLaunchKernelGGL(k_batch_reduce, dim3(c.nb), dim3(256), 0, c.stream, c.vcnt, c.ioff, c.iactive, c.istats);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit(const Ctx& c, int64_t off, int64_t n_b, int32_t* out_idx) {
+  const int64_t cnt = n_b * c.K;
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(cnt, 256, 4096)), dim3(256), 0, c.stream, c.F[c.cur], off, cnt, c.K,
+                     out_idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
@@ -1408,7 +1555,7 @@ hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
 hipError_t launch_bin(const Ctx& c) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c.stream, c.class_count, (int64_t)NCLASS);
   hipLaunchKernelGGL(k_bin, dim3(grid_for(c.n, 256, 8192)), dim3(256), 0, c.stream, c.rowptr, c.n, c.K,
-                     c.class_count, c.class_list);
+                     c.class_count, c.class_list, c.inst_of, c.iactive);
   return hipGetLastError();
 }
 
@@ -1538,6 +1685,9 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   a.S = c.S;
   a.eps_relq = c.eps_relq;
   a.eps_abs = c.eps_abs;
+  a.inst_of = c.inst_of;
+  a.iactive = c.iactive;
+  a.vcnt = c.vcnt;
   return a;
 }
 

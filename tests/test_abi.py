@@ -63,3 +63,20 @@ def test_null_pointers_are_argument_errors():
     assert lib.knnd_ctx_round(None, None) == knnd.KNND_ERR_ARG
     assert lib.knnd_ctx_destroy(None) == knnd.KNND_ERR_ARG
     assert lib.knnd_ctx_rounds(None) == -1
+
+
+def test_batched_struct_layout_and_argument_errors():
+    assert ctypes.sizeof(knnd.knnd_instance) == 72
+    lib = knnd.lib()
+    assert lib.knnd_build_batched(None, 1, None, 0, None) == knnd.KNND_ERR_ARG
+    arr = (knnd.knnd_instance * 2)()
+    P = np.full((10, 4), 0.25, dtype=np.float32)
+    idx = np.empty((10, 3), dtype=np.int32)
+    r = ctypes.c_int32()
+    for b in range(2):
+        arr[b].points, arr[b].n, arr[b].d, arr[b].K, arr[b].seed = P.ctypes.data, 10, 3, 3, b
+        arr[b].out_idx = idx.ctypes.data
+        arr[b].out_rounds = ctypes.pointer(r)
+    assert lib.knnd_build_batched(arr, 0, None, 0, None) == knnd.KNND_ERR_ARG
+    arr[1].K = 10  # K > n - 1 in the second instance
+    assert lib.knnd_build_batched(arr, 2, None, 0, None) == knnd.KNND_ERR_ARG

@@ -391,3 +391,80 @@ def test_config4_full_size_and_recall():
     rec = np.mean([len(set(g["idx"][q].tolist()) & set(b.tolist())) / c["K"] for q, b in zip(qs, bf)])
     say(f"config 4 recall@{c['K']} on 2000 queries: {rec:.4f}")
     assert 0.0 < rec <= 1.0
+
+
+# ---------------------------------------------------------------------------
+# Batched instances (knnd_build_batched): each instance must come out exactly
+# as the oracle's descent of that instance alone.
+# ---------------------------------------------------------------------------
+def _compare_instance(g, P, d, K, seed, what):
+    o = oracle.build_graph(P, d, K, seed)
+    assert g["status"] == o.status, what
+    assert g["rounds"] == o.rounds, (what, g["rounds"], o.rounds)
+    for r in range(o.rounds + 1):
+        s = g["stats"][r]
+        assert s["fcr_hits"] == o.hits[r], (what, r)
+        if r:
+            assert (s["updates"], s["evals_alg"]) == (o.updates[r], o.evals[r]), (what, r, s)
+    assert_same_graph(g["idx"], g["kl"], o.idx, o.keys, what)
+
+
+# (n, d, K, data seed, seed): several K, coordinates that share a padded
+# group (d+1 = 13, 14, 16) or not, tiny and uneven n, n = K + 1
+BATCH_MIX = [(900, 12, 8, 11, 21), (2500, 13, 8, 12, 22), (1300, 15, 8, 13, 23), (33, 3, 8, 14, 24),
+             (4000, 5, 16, 15, 25), (17, 2, 16, 16, 26), (3100, 20, 16, 17, 27), (700, 7, 4, 18, 28),
+             (5000, 9, 32, 19, 29), (64, 30, 32, 20, 30), (1200, 1, 2, 21, 31), (6000, 19, 16, 22, 32)]
+
+
+@pytest.mark.parametrize("prec", [knnd.KNND_PREC_FP64, knnd.KNND_PREC_MIXED_BF16], ids=["plain", "bf16"])
+def test_batched_mix_vs_oracle(prec):
+    inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX]
+    say(f"batched: {len(inst)} instances, precision {prec}")
+    st, outs = knnd.knnd_build_batched(inst, knnd.default_params(precision=prec))
+    assert st == knnd.KNND_OK
+    for (P, d, K, s), g in zip(inst, outs):
+        _compare_instance(g, P, d, K, s, f"instance n={P.shape[0]} d={d} K={K}")
+
+
+def test_batched_device_pointers_match_host():
+    torch = pytest.importorskip("torch")
+    inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX[:6]]
+    say("batched: device pointers")
+    _, host = knnd.knnd_build_batched(inst)
+    dev_inst = [(torch.from_numpy(P).cuda(), d, K, s) for P, d, K, s in inst]
+    st, dev = knnd.knnd_build_batched(dev_inst)
+    torch.cuda.synchronize()
+    assert st == knnd.KNND_OK
+    for h, g in zip(host, dev):
+        assert h["rounds"] == g["rounds"]
+        assert np.array_equal(h["idx"], g["idx"].cpu().numpy())
+        assert np.array_equal(h["kl"].view(np.uint64), g["kl"].cpu().numpy().view(np.uint64))
+
+
+def test_batched_round_cap_stops_every_instance():
+    inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX[:5]]
+    st, outs = knnd.knnd_build_batched(inst, knnd.default_params(max_rounds=1))
+    assert st in (knnd.KNND_OK, knnd.KNND_WARN_MAX_ROUNDS)
+    for (P, d, K, s), g in zip(inst, outs):
+        o = oracle.build_graph(P, d, K, s, max_rounds=1)
+        assert g["rounds"] == 1 and g["status"] == o.status
+        assert_same_graph(g["idx"], g["kl"], o.idx, o.keys, "capped instance")
+
+
+@pytest.mark.parametrize("prec", [knnd.KNND_PREC_FP64, knnd.KNND_PREC_MIXED_BF16], ids=["plain", "bf16"])
+def test_config5_batched_full_size(prec):
+    gold = _golden("c5")["instances"]
+    inst = []
+    for b in range(synth.BATCH_INSTANCES):
+        n, d, K, ds, s = synth.instance(synth.BATCH_BASE_SEED, b)
+        inst.append((synth.dirichlet(ds, n, d, np.float32), d, K, s))
+    say(f"config 5: {len(inst)} instances vs stored oracle digests, precision {prec}")
+    st, outs = knnd.knnd_build_batched(inst, knnd.default_params(precision=prec))
+    assert st == knnd.KNND_OK
+    for b, (g, o) in enumerate(zip(outs, gold)):
+        assert (g["status"], g["rounds"]) == (o["status"], o["rounds"]), b
+        assert [s["updates"] for s in g["stats"][1:]] == o["updates"][1:], b
+        assert [s["fcr_hits"] for s in g["stats"]] == o["fcr_hits"], b
+        assert [s["evals_alg"] for s in g["stats"][1:]] == o["evals_alg"][1:], b
+        assert _digest(g["idx"]) == o["idx_sha256"], b
+        assert _digest(g["kl"]) == o["kl_sha256"], b
