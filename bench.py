@@ -62,6 +62,39 @@ def measured_traffic(precision):
     return rec.get("bytes_per_launch", {}).get(precision)
 
 
+def batched_leg(knnd, synth, torch, steps):
+    """The batched workload (512 instances of uneven n, d, K) as one batched
+    call, next to the same instances run one by one through knnd_build_ex;
+    both on device-resident points, plain FP64 keys."""
+    inst = []
+    for b in range(synth.BATCH_INSTANCES):
+        n, d, K, ds, s = synth.instance(synth.BATCH_BASE_SEED, b)
+        inst.append((torch.from_numpy(synth.dirichlet(ds, n, d, np.float32)).cuda(), d, K, s))
+    prm = knnd.default_params(precision=knnd.KNND_PREC_FP64)
+    knnd.knnd_build_batched(inst, prm)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        _, outs = knnd.knnd_build_batched(inst, prm)
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t) / steps
+    evals = sum(s["evals_alg"] for o in outs for s in o["stats"])
+    t = time.perf_counter()
+    ev1 = 0
+    for P, d, K, s in inst:
+        o = knnd.knnd_build_ex(P, d, K, s, prm)
+        ev1 += sum(x["evals_alg"] for x in o["stats"])
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t
+    assert ev1 == evals, "batched and one-by-one evaluation counts differ"
+    return {"workload": f"{len(inst)} instances, n in [500, 20000], d+1 in [4, 21], K in {{8,16,32}}, "
+                        f"base seed {synth.BATCH_BASE_SEED}, {sum(p.shape[0] for p, *_ in inst)} points",
+            "batched_ms": round(1e3 * batched_s, 2), "one_by_one_ms": round(1e3 * single_s, 2),
+            "speedup": round(single_s / batched_s, 3), "evals_alg": evals,
+            "value": evals / batched_s, "unit": "evals/s",
+            "max_rounds": max(o["rounds"] for o in outs)}
+
+
 def copy_calibration():
     """A plain device copy of 1 GiB: the reference for scaling FETCH_SIZE and
     WRITE_SIZE (run under rocprofv3 --pmc)."""
@@ -122,6 +155,8 @@ def main():
                     help="with --precision mixed, skip timing the plain descent beside it")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-instances comparison")
     ap.add_argument("--cpu-receivers", type=int, default=400_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device (reference run for HBM counters)")
@@ -240,6 +275,9 @@ def main():
     }
     if plain is not None:
         line["plain"] = plain
+    if not args.no_batched:
+        log("batched instances: one batched call vs one by one")
+        line["batched"] = batched_leg(knnd, synth, torch, args.steps)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle round 1 on {args.cpu_receivers} receivers, {threads} threads")

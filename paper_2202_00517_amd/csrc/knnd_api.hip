@@ -43,7 +43,8 @@ void free_ctx(Ctx& c) {
                   c.fill,   c.rowptr, c.col,    c.colslot,   c.seg,
                   c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.gckey, c.bcand, c.bckey,
                   c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32,
-                  c.inst_of, c.ioff, c.iseed, c.iM, c.iD, c.iactive, c.istats, c.vcnt};
+                  c.inst_of, c.ioff, c.iseed, c.iM, c.iD, c.iactive, c.istats, c.vcnt,
+                  c.sl_n, c.sl_id, c.sl_key};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c.hstats) (void)hipHostFree(c.hstats);
@@ -161,6 +162,13 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
     c.seg = nullptr;
     c.use_hub = false;
   }
+  if (c.use_hub) {
+    const size_t sl = (size_t)n * knnd::SHORT_LIST;
+    e = dalloc(&c.sl_n, (size_t)n);
+    if (e == hipSuccess) e = dalloc(&c.sl_id, sl);
+    if (e == hipSuccess && !c.mixed) e = dalloc(&c.sl_key, sl);
+    if (e != hipSuccess) return map_err(e);
+  }
 
   return KNND_OK;
 }
@@ -229,10 +237,12 @@ int prepare_mixed(Ctx& c, size_t nK) {
     c.mixed = false;
     (void)hipFree(c.seg32);
     c.seg32 = nullptr;
-    if (dalloc(&c.seg, nK * (size_t)(2 * c.K + 1)) != hipSuccess) {
+    if (dalloc(&c.seg, nK * (size_t)(2 * c.K + 1)) != hipSuccess ||
+        dalloc(&c.sl_key, (size_t)c.n * knnd::SHORT_LIST) != hipSuccess) {
       (void)hipGetLastError();
+      (void)hipFree(c.seg);
       c.seg = nullptr;
-      c.use_hub = false;
+      c.use_hub = false;  // pull form: needs neither
     }
     return KNND_OK;
   }
@@ -411,16 +421,38 @@ int create_group(Group& g, const knnd_instance* inst, const knnd_params& prm, in
   g.hits_prev.assign(nb, 0);
   g.running = nb;
 
-  // points, zero-padded to Dmax coordinates
+  // points, zero-padded to Dmax coordinates; host points go through a
+  // contiguous device staging copy first (a strided copy straight from
+  // pageable host memory would move one row at a time)
   const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
   KNND_HIP(hipMemsetAsync(c.P, 0, (size_t)N * c.D * esz, c.stream));
-  for (int j = 0; j < nb; ++j) {
+  void* stage = nullptr;
+  if (!on_device) {
+    size_t most = 0;
+    for (int j = 0; j < nb; ++j) most = std::max(most, (size_t)inst[g.members[j]].n * (inst[g.members[j]].d + 1));
+    KNND_HIP(hipMalloc(&stage, most * esz));
+  }
+  int rc = KNND_OK;
+  for (int j = 0; j < nb && rc == KNND_OK; ++j) {
     const knnd_instance& in = inst[g.members[j]];
     const size_t w = (size_t)(in.d + 1) * esz;
-    KNND_HIP(hipMemcpy2DAsync(static_cast<char*>(c.P) + (size_t)g.off[j] * c.D * esz, (size_t)c.D * esz,
-                              in.points, w, w, (size_t)in.n,
-                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.stream));
+    const void* src = in.points;
+    hipError_t e2 = hipSuccess;
+    if (!on_device) {
+      e2 = hipMemcpyAsync(stage, in.points, w * in.n, hipMemcpyHostToDevice, c.stream);
+      src = stage;
+    }
+    if (e2 == hipSuccess)
+      e2 = hipMemcpy2DAsync(static_cast<char*>(c.P) + (size_t)g.off[j] * c.D * esz, (size_t)c.D * esz, src, w, w,
+                            (size_t)in.n, hipMemcpyDeviceToDevice, c.stream);
+    if (e2 != hipSuccess) rc = map_err(e2);
   }
+  if (stage) {
+    const hipError_t e3 = hipStreamSynchronize(c.stream);
+    (void)hipFree(stage);
+    if (rc == KNND_OK && e3 != hipSuccess) rc = map_err(e3);
+  }
+  if (rc != KNND_OK) return rc;
   return finish_create(c);
 }
 

@@ -17,6 +17,7 @@ constexpr int HUB_MAXD = 64;     // register hub kernel up to this many coordina
                                  // P and L carry HUB_MAXD zeroed elements of tail padding
 constexpr uint32_t IDMASK_HOST = 0x3FFFFFFFu;  // point indices are below this
 constexpr uint32_t CLASS_CAP_MIN = 512;
+constexpr int SHORT_LIST = 128;  // candidate lists up to this long are merged by k_merge
 
 // Per-round device counters
 enum { STAT_UPDATES = 0, STAT_HITS = 1, STAT_EVALS = 2, STAT_PERF = 3, STAT_RESCUES = 4, STAT_ERR = 5, STAT_N = 8 };
@@ -61,6 +62,10 @@ struct Ctx {
   float* seg32 = nullptr;     // [nK(2K+1)] cross terms C~ by snapshot edge
   double eps_relq = 0.0, eps_abs = 0.0;  // mixed-form error bound: e_rel / (1 - e_rel) and e_abs
   bool use_hub = false;
+  // short candidate lists handed from the receiver kernel to k_merge (hub form)
+  int32_t* sl_n = nullptr;     // [n] list length, -1 when the receiver kernel merged itself
+  uint32_t* sl_id = nullptr;   // [n][SHORT_LIST]
+  double* sl_key = nullptr;    // [n][SHORT_LIST] (exact hub form only)
   int64_t* tilesum = nullptr;
   int32_t* class_count = nullptr;  // [NCLASS]
   int32_t* class_list = nullptr;   // [NCLASS][n]
@@ -122,6 +127,10 @@ struct JoinArgs {
   const int32_t* inst_of;
   const int32_t* iactive;
   int32_t* vcnt;
+  // short lists (hub form)
+  int32_t* sl_n;
+  uint32_t* sl_id;
+  double* sl_key;
 };
 
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);

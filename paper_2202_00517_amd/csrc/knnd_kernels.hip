@@ -972,14 +972,14 @@ __device__ double kth_upper_bound(int K, int ncand, const double* kx, double hi,
 // [0, n) (impossible for a correct list) is never written: the lane keeps the
 // old entry and the round reports an internal error.
 __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, int lane, uint64_t lk, uint32_t li,
-                                          const uint32_t* s_fx, int64_t& my_upd, int64_t& my_err) {
+                                          uint32_t old_raw, int64_t& my_upd, int64_t& my_err) {
   bool bad = false;
   if (lane < K) {
     uint32_t id = li;
     double key = bits_key(lk);
     if ((int64_t)(id & IDMASK) >= a.n) {
       bad = true;
-      id = s_fx[lane] & IDMASK;
+      id = old_raw & IDMASK;
       key = a.keys[x * K + lane];
     }
     a.Fn[x * K + lane] = id;
@@ -1222,8 +1222,21 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
     const int ncand = (int)min((int64_t)s_ncand, ccap);
     const double* kx = s_kx;  // the old list's keys
     bool done = false;
+    if (SEG) {
+      // a short list goes to k_merge (one wave per receiver, no block
+      // barriers); the mixed form's rescue of it happens there too
+      const bool short_list = ncand <= SHORT_LIST;
+      if (short_list) {
+        for (int i = tid; i < ncand; i += NT) {
+          a.sl_id[x * SHORT_LIST + i] = cid[i];
+          if (!MIX) a.sl_key[x * SHORT_LIST + i] = ckey[i];
+        }
+      }
+      if (tid == 0) a.sl_n[x] = short_list ? ncand : -1;
+      done = short_list;
+    }
 
-    if (MIX) {
+    if (MIX && !done) {
       // Theta: an upper bound on the K-th smallest upper bound among the old
       // list (exact keys) and the listed candidates (k~ + eps).  A candidate
       // whose lower bound exceeds Theta has K entries strictly better than
@@ -1268,7 +1281,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
             wave_sort(bk, bi);
             wave_merge(lk, li, bk, bi);
           }
-          write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
+          write_row(a, x, K, lane, lk, li, lane < K ? s_fx[lane] : 0u, my_upd, my_err);
         }
       } else {
         // a large rescue set: canonical keys in place, +inf for the rest
@@ -1298,7 +1311,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
           wave_sort(bk, bi);
           wave_merge(lk, li, bk, bi);
         }
-        write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
+        write_row(a, x, K, lane, lk, li, lane < K ? s_fx[lane] : 0u, my_upd, my_err);
       }
     } else if (!done && SEG) {
       // D (hub form): every key is known and every listed candidate has key
@@ -1374,7 +1387,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
             wave_sort(bk, bi);
             wave_merge(lk, li, bk, bi);
           }
-          write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
+          write_row(a, x, K, lane, lk, li, lane < K ? s_fx[lane] : 0u, my_upd, my_err);
         }
       }
     }
@@ -1435,7 +1448,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
       __syncthreads();
       if (wave == 0) {
         for (int w = 0; w < NW - 1; ++w) wave_merge(lk, li, s_lk[w][lane], s_li[w][lane]);
-        write_row(a, x, K, lane, lk, li, s_fx, my_upd, my_err);
+        write_row(a, x, K, lane, lk, li, lane < K ? s_fx[lane] : 0u, my_upd, my_err);
       }
     }
     if (a.vcnt && my_perf != pf_item0) atomicAdd(&s_ipf, (int)(my_perf - pf_item0));
@@ -1460,6 +1473,63 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
     if (ev) atomicAdd((unsigned long long*)&a.stats[STAT_EVALS], (unsigned long long)ev);
     if (pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
     if (up) atomicAdd((unsigned long long*)&a.stats[STAT_UPDATES], (unsigned long long)up);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a4/a5 for short candidate lists (hub form): one wave per receiver, no block
+// barriers.  The list (at most SHORT_LIST candidates that can beat the
+// round-start K-th, each listed once) is sorted in 64-wide batches and merged
+// into the old list held in registers.  In the mixed form every listed
+// candidate gets its canonical FP64 key here (the rescue): the list's members
+// passed the lower-bound test, and bounding Theta first would cost more than
+// these few gathers.
+// ---------------------------------------------------------------------------
+template <typename PT, bool MIX>
+__global__ __launch_bounds__(256) void k_merge(JoinArgs a) {
+  const int lane = lane_id();
+  const int K = a.K, D = a.D, Dp = a.Dp;
+  const PT* P = reinterpret_cast<const PT*>(a.P);
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  int64_t my_upd = 0, my_err = 0, my_resc = 0;
+  for (int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); x < a.n; x += nwaves) {
+    if (inactive(a, x)) continue;  // whole wave
+    const int nc = a.sl_n[x];
+    if (nc < 0) continue;           // merged by the receiver kernel
+    const uint32_t old = lane < K ? a.F[x * K + lane] : 0u;
+    uint64_t lk = lane < K ? key_bits(a.keys[x * K + lane]) : KEY_SENTINEL;
+    uint32_t li = lane < K ? (old & IDMASK) : IDMASK;
+    for (int b0 = 0; b0 < nc; b0 += WAVE) {
+      const bool ok = b0 + lane < nc;
+      const uint32_t z = ok ? a.sl_id[x * SHORT_LIST + b0 + lane] : 0u;
+      double key = 0.0;
+      if (ok) key = MIX ? canonical_key(P + x * D, a.L + x * Dp, a.L + (int64_t)z * Dp, D)
+                        : a.sl_key[x * SHORT_LIST + b0 + lane];
+      uint64_t bk = ok ? key_bits(key) : KEY_SENTINEL;
+      uint32_t bi = ok ? (z | NEWBIT) : IDMASK;
+      wave_sort(bk, bi);
+      wave_merge(lk, li, bk, bi);
+    }
+    write_row(a, x, K, lane, lk, li, old, my_upd, my_err);
+    if (MIX) {
+      if (lane == 0) my_resc += nc;
+      if (a.vcnt && lane == 0) {
+        a.vcnt[x * VC_N + VC_RESC] = nc;
+        a.vcnt[x * VC_N + VC_RECVPERF] = nc;
+      }
+    }
+  }
+  __shared__ int64_t s_red[4];
+  const int64_t up = block_sum(my_upd, s_red);
+  const int64_t er = block_sum(my_err, s_red);
+  const int64_t rs = block_sum(my_resc, s_red);
+  if (threadIdx.x == 0) {
+    if (up) atomicAdd((unsigned long long*)&a.stats[STAT_UPDATES], (unsigned long long)up);
+    if (er) atomicAdd((unsigned long long*)&a.stats[STAT_ERR], (unsigned long long)er);
+    if (rs) {
+      atomicAdd((unsigned long long*)&a.stats[STAT_RESCUES], (unsigned long long)rs);
+      atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)rs);
+    }
   }
 }
 
@@ -1688,6 +1758,9 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   a.inst_of = c.inst_of;
   a.iactive = c.iactive;
   a.vcnt = c.vcnt;
+  a.sl_n = c.sl_n;
+  a.sl_id = c.sl_id;
+  a.sl_key = c.sl_key;
   return a;
 }
 
@@ -1695,16 +1768,36 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
 // nothing in the pull form
 hipError_t launch_join_hub(const Ctx& c, int64_t* stats) {
   const JoinArgs a = join_args(c, stats);
+  if (c.use_hub && (c.mixed ? (!c.seg32 || !c.Ph || !c.Lh || !c.S) : !c.seg)) return hipErrorInvalidValue;
   if (c.mixed) return launch_hub_mfma(c, a);
   if (c.use_hub) return c.dtype == 0 ? launch_hub<float>(c, a) : launch_hub<double>(c, a);
   return hipSuccess;
 }
 
-// a2-a5 receiver side: every size class of k_recv
+template <typename PT, bool MIX>
+static hipError_t launch_merge(const Ctx& c, const JoinArgs& a) {
+  hipLaunchKernelGGL((k_merge<PT, MIX>), dim3(grid_for(c.n, 4, 16 * c.num_cu)), dim3(256), 0, c.stream, a);
+  return hipGetLastError();
+}
+
+// a2-a5 receiver side: every size class of k_recv, then (hub form) k_merge
+// for the receivers whose candidate list was short
 hipError_t launch_join_recv(const Ctx& c, int64_t* stats) {
   const JoinArgs a = join_args(c, stats);
-  if (c.mixed) return c.dtype == 0 ? launch_recv_all<float, 2>(c, a) : launch_recv_all<double, 2>(c, a);
-  if (c.use_hub) return c.dtype == 0 ? launch_recv_all<float, 1>(c, a) : launch_recv_all<double, 1>(c, a);
+  hipError_t e;
+  // every buffer the chosen form writes must exist (checked before launch)
+  if (c.use_hub && (!c.sl_n || !c.sl_id || (c.mixed ? !c.seg32 : (!c.seg || !c.sl_key))))
+    return hipErrorInvalidValue;
+  if (c.mixed) {
+    e = c.dtype == 0 ? launch_recv_all<float, 2>(c, a) : launch_recv_all<double, 2>(c, a);
+    if (e != hipSuccess) return e;
+    return c.dtype == 0 ? launch_merge<float, true>(c, a) : launch_merge<double, true>(c, a);
+  }
+  if (c.use_hub) {
+    e = c.dtype == 0 ? launch_recv_all<float, 1>(c, a) : launch_recv_all<double, 1>(c, a);
+    if (e != hipSuccess) return e;
+    return c.dtype == 0 ? launch_merge<float, false>(c, a) : launch_merge<double, false>(c, a);
+  }
   return c.dtype == 0 ? launch_recv_all<float, 0>(c, a) : launch_recv_all<double, 0>(c, a);
 }
 
