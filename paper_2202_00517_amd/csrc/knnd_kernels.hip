@@ -852,6 +852,41 @@ __device__ __forceinline__ int tab_insert(uint32_t* tab, uint32_t mask, uint32_t
   }
 }
 
+// The rest of tab_insert after its first probe at slot h returned `old`
+// (lets a thread issue the first probes of several ids back to back).
+__device__ __forceinline__ int tab_finish(uint32_t* tab, uint32_t mask, uint32_t z, uint32_t flag, uint32_t h,
+                                          uint32_t old) {
+  for (;;) {
+    if (old == EMPTY) return 1 | ((flag & NEWBIT) ? 2 : 0);
+    if ((old & IDMASK) == z) {
+      if ((flag & NEWBIT) && !(old & (NEWBIT | EXCLBIT))) {
+        const uint32_t prev = atomicOr(&tab[h], NEWBIT);
+        if (!(prev & NEWBIT)) return 2;
+      }
+      return 0;
+    }
+    h = (h + 1) & mask;
+    old = atomicCAS(&tab[h], EMPTY, z | flag);
+  }
+}
+
+__device__ __forceinline__ uint32_t tab_slot(uint32_t z, uint32_t mask) {
+  const uint32_t h = z * 0x9E3779B1u;
+  return (h ^ (h >> 15)) & mask;
+}
+
+// Exclusive prefix sum of one small int per lane across the wave.
+__device__ __forceinline__ int wave_exscan(int v) {
+  const int lane = lane_id();
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int t = __shfl(incl, lane >= o ? lane - o : 0, WAVE);
+    if (lane >= o) incl += t;
+  }
+  return incl - v;
+}
+
 // Block-wide exclusive scan of one int64 per thread (NW waves).
 template <int NW>
 __device__ __forceinline__ int64_t block_exscan_nw(int64_t v, int64_t* sh /*[NW]*/) {
@@ -1000,8 +1035,17 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
 // per block.  Classes with CAP > 8192 size their tables optimistically and
 // hand a receiver that overflows to the global-memory class.
 
+// Occupancy targets: the tables of up to 2048 slots leave LDS for four blocks
+// per CU (receivers there have at most 1023 occurrences: four per thread in
+// flight cover them), the 4096-slot class for three.
+template <int CAP>
+constexpr int recv_waves_per_eu() {
+  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? 3 : 1);
+}
+
 template <int CAP, typename PT, int MODE, int NW>
-__global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restrict__ lists,
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(recv_waves_per_eu<CAP>())))
+void k_recv(JoinArgs a, int32_t* __restrict__ lists,
                                                   int32_t* __restrict__ counts, int cls) {
   constexpr bool SEG = MODE >= 1;  // keys (or cross terms) come from the hub kernel
   constexpr bool MIX = MODE == 2;  // cross terms from MFMA, exact keys only where needed
@@ -1011,7 +1055,7 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
   constexpr bool GUARD = BIG;
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
-  constexpr int U = GLOB ? 4 : 8;            // occurrences per thread in flight
+  constexpr int U = (GLOB || CAP <= 2048) ? 4 : 8;  // occurrences per thread in flight
   // a guarded class overshoots LIMIT by at most one batch (U per thread)
   static_assert(!BIG || LIMIT + U * NT <= BIG_CAND, "candidate list of the big classes too small");
   // occurrence counter: T < 2^32 in the LDS classes (their binning bounds
@@ -1024,6 +1068,8 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
   __shared__ double s_ckey[SEG ? CC : 1];
   __shared__ uint32_t s_fx[WAVE];
   __shared__ double s_kx[WAVE];
+  __shared__ uint32_t s_col[NT];  // the co-friend list, when it has at most NT entries
+  __shared__ uint8_t s_csl[NT];
   // mixed form: x's row and its logs for the rescue (D <= HUB_MAXD)
   __shared__ double s_xr[MIX ? HUB_MAXD + 16 : 1], s_lr[MIX ? HUB_MAXD + 16 : 1];
   __shared__ uint64_t s_lk[NW - 1][WAVE];
@@ -1099,7 +1145,14 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
       s_xr[tid] = (double)P[x * D + tid];
       s_lr[tid] = a.L[x * Dp + tid];
     }
-    // B: excluded entries
+    // B: excluded entries; a co-friend list of at most NT entries is staged
+    // in LDS (its loads overlap those of x's own list), so that enumerating
+    // friends of co-friends needs one global round trip instead of two
+    const bool staged = c <= NT;
+    if (staged && tid < c) {
+      s_col[tid] = a.col[rp + tid];
+      s_csl[tid] = a.colslot[rp + tid];
+    }
     if (tid < K) {
       const uint32_t raw = a.F[x * K + tid];
       s_fx[tid] = raw;
@@ -1122,21 +1175,35 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
       int rg[U];  // 1 co-friend, 2 friend of friend, 3 friend of co-friend, 0 none
       int ss[U];
       uint32_t cw[U], fw[U], sl[U];
-      // stage 1: the edge each occurrence comes through
+      // stage 1: the edge each occurrence comes through (co-friend entries
+      // from LDS when staged)
+      auto stage1 = [&](auto fetch) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const IT t = t0 + tid + NT * u;
-        const bool inC = t < (IT)c;
-        const bool inFF = !inC && t < (IT)(c + KK);
-        const bool inFC = !inC && !inFF && t < (IT)T;
-        rg[u] = inC ? 1 : (inFF ? 2 : (inFC ? 3 : 0));
-        const IT uu = inFF ? t - (IT)c : t - (IT)(c + KK);  // meaningful in regions 2 and 3
-        const IT q = uu / (IT)K;                              // friend j or co-friend q
-        ss[u] = (int)(uu - q * (IT)K);                        // entry s of that row
-        const int64_t ci = inC ? rp + (int64_t)t : (inFC ? rp + (int64_t)q : 0);
-        cw[u] = a.col[ci];
-        sl[u] = SEG ? (uint32_t)a.colslot[ci] : 0u;
-        fw[u] = s_fx[inFF ? (int)q : 0];
+        for (int u = 0; u < U; ++u) {
+          const IT t = t0 + tid + NT * u;
+          const bool inC = t < (IT)c;
+          const bool inFF = !inC && t < (IT)(c + KK);
+          const bool inFC = !inC && !inFF && t < (IT)T;
+          rg[u] = inC ? 1 : (inFF ? 2 : (inFC ? 3 : 0));
+          const IT uu = inFF ? t - (IT)c : t - (IT)(c + KK);  // meaningful in regions 2 and 3
+          const IT q = uu / (IT)K;                              // friend j or co-friend q
+          ss[u] = (int)(uu - q * (IT)K);                        // entry s of that row
+          fetch(inC ? (int64_t)t : (inFC ? (int64_t)q : -1), cw[u], sl[u]);
+          fw[u] = s_fx[inFF ? (int)q : 0];
+        }
+      };
+      if (staged) {
+        stage1([&](int64_t qi, uint32_t& w, uint32_t& s) {
+          const int i = qi < 0 ? 0 : (int)qi;
+          w = s_col[i];
+          s = s_csl[i];
+        });
+      } else {
+        stage1([&](int64_t qi, uint32_t& w, uint32_t& s) {
+          const int64_t g = qi < 0 ? 0 : rp + qi;
+          w = a.col[g];
+          s = SEG ? (uint32_t)a.colslot[g] : 0u;
+        });
       }
       // stage 2: candidate ids and their keys
       uint32_t zr[U];
@@ -1162,41 +1229,58 @@ __global__ __launch_bounds__(NW * 64) void k_recv(JoinArgs a, int32_t* __restric
         z[u] = rg[u] == 1 ? (srcw & IDMASK) : (zr[u] & IDMASK);
         nw[u] = (rg[u] == 1 ? srcw : (srcw | zr[u])) & NEWBIT;
       }
-      int res[U];
-      int fresh = 0;
+      // insert: the first probe of every occurrence goes out at once; the
+      // rare collision probes further one slot at a time
+      uint32_t old0[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        res[u] = 0;
+        old0[u] = 0;
+        if (t0 + tid + NT * u < (IT)T)
+          old0[u] = atomicCAS(&tab[tab_slot(z[u], mask)], EMPTY, z[u] | (a.skip ? nw[u] : NEWBIT));
+      }
+      int fresh = 0;
+      uint32_t newm = 0;  // bit u: occurrence u marked its candidate new first
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
         if (t0 + tid + NT * u < (IT)T) {
-          res[u] = tab_insert(tab, mask, z[u], a.skip ? nw[u] : NEWBIT);
-          fresh += res[u] & 1;
+          const int r = tab_finish(tab, mask, z[u], a.skip ? nw[u] : NEWBIT, tab_slot(z[u], mask), old0[u]);
+          fresh += r & 1;
+          newm |= (uint32_t)((r >> 1) & 1) << u;
         }
       }
       item_evals += fresh;
+      // list the candidates that can beat the round-start K-th (for the mixed
+      // form: whose lower bound can), one list reservation per wave
+      auto key_of = [&](int u) { return SEG ? (MIX ? Sx - (double)kr[u] : (double)kr[u]) : 0.0; };
+      uint32_t appm = 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        // list only candidates that can beat the round-start K-th (for the
-        // mixed form: whose lower bound can)
-        double kv = 0.0;
-        if (SEG) kv = MIX ? Sx - (double)kr[u] : (double)kr[u];
-        const bool app = (res[u] & 2) != 0 &&
-                         (!SEG || (MIX ? kv - mix_eps(a, Sx, kv) <= tau0 : kv <= tau0));
-        const uint64_t m = __ballot(app);
-        if (m) {
-          int base = 0;
-          if (lane == 0) base = atomicAdd(&s_ncand, (int)__popcll(m));
+        if (!((newm >> u) & 1)) continue;
+        const double kv = key_of(u);
+        if (!SEG || (MIX ? kv - mix_eps(a, Sx, kv) <= tau0 : kv <= tau0)) appm |= 1u << u;
+      }
+      {
+        const int napp = __popc(appm);
+        const int pre = wave_exscan(napp);
+        const int tot = __shfl(pre + napp, WAVE - 1, WAVE);
+        int base = 0;
+        if (tot) {
+          if (lane == 0) base = atomicAdd(&s_ncand, tot);
           base = __shfl(base, 0, WAVE);
-          if (app) {
-            const int at = base + (int)rank_in(m);
-            if (at < ccap) {
-              cid[at] = z[u];
-              if (SEG) ckey[at] = kv;
-            } else if (GUARD) {
-              s_over = 1;  // list full: the global-memory class redoes this receiver
-            } else {
-              ++my_err;  // cannot happen with exact sizing
-            }
+        }
+        int at = base + pre;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (!((appm >> u) & 1)) continue;
+          if (at < ccap) {
+            cid[at] = z[u];
+            if (SEG) ckey[at] = key_of(u);
+          } else if (GUARD) {
+            s_over = 1;  // list full: the global-memory class redoes this receiver
+          } else {
+            ++my_err;  // cannot happen with exact sizing
           }
+          ++at;
         }
       }
       if (GUARD) {
