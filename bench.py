@@ -229,7 +229,7 @@ def main():
                  "identical_graph": bool(same)}
 
     # roofline of the dominant kernel: the receiver pass (k_recv, one launch
-    # per table-size class, steps a2-a5 on the receiver side), timed with HIP
+    # per table-size class, then k_merge; steps a2-a5 on the receiver side), timed with HIP
     # events on the library's stream around its launches in every timed round
     rounds = [s for o, _ in results for s in o["stats"][1:]]
     recv_ms = [s["ms_recv"] for s in rounds]
@@ -239,7 +239,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": measured_traffic(args.precision),
-                "kernel": "k_recv (all table-size classes of one round)",
+                "kernel": "receiver pass: k_recv (every table-size class) + k_merge, one round",
                 "avg_launch_ms": round(sum(recv_ms) / len(recv_ms), 3),
                 "bytes_per_launch": int(bytes_alg / len(recv_ms))}
     hub = {"kernel": "k_hub_mfma (split 16-bit MFMA cross terms)" if mixed
