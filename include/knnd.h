@@ -193,6 +193,28 @@ int knnd_build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int
                        void* stream);
 
 /*
+ * Exact K nearest neighbours of query points by exhaustive comparison (the
+ * problem of Section 2.3 solved directly; the accuracy measure of Section 4.3
+ * compares a descent's lists with these).  For query point q every other
+ * point p is ranked by the same canonical key D(q||p) and (key, index) order
+ * as the descent.
+ *   points   [n][d+1] of dtype (knnd_dtype), host or device memory per
+ *            on_device; every coordinate finite and > 0; d+1 <= 256
+ *   queries  [nq] int32 point indices (same memory kind), each in [0, n)
+ *   tau      optional [nq] FP64 (same kind): an upper bound on each query's
+ *            K-th smallest key, e.g. the K-th key of a descent's list for that
+ *            point (saves one pass over the points); NULL: computed here
+ *   out_idx  [nq][K] int32 (same kind): the K nearest in (key, index) order
+ *   out_kl   optional [nq][K] FP64 keys (same kind)
+ * Device scratch: about 49 KB per query.  Returns KNND_ERR_ARG for bad sizes,
+ * a query index out of range or a tau below the K-th key,
+ * KNND_ERR_UNSUPPORTED for d+1 > 256, KNND_ERR_DOMAIN for bad coordinates.
+ */
+int knnd_exact_knn(const void* points, int64_t n, int32_t d, int32_t K, int32_t dtype,
+                   const int32_t* queries, int64_t nq, const double* tau, int32_t on_device,
+                   void* stream, int32_t* out_idx, double* out_kl);
+
+/*
  * Step-by-step interface (the same path, one call per step).  A context owns
  * its device buffers until knnd_ctx_destroy.  Pointers marked "kind" are host
  * memory when on_device == 0 and device memory when on_device != 0.

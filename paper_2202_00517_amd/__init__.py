@@ -31,7 +31,7 @@ EXPORTED = [
     "knnd_default_params", "knnd_status_string", "knnd_abi_version", "knnd_build",
     "knnd_build_ex", "knnd_ctx_create", "knnd_ctx_init_graph", "knnd_ctx_set_graph",
     "knnd_ctx_round", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
-    "knnd_ctx_destroy", "knnd_build_batched",
+    "knnd_ctx_destroy", "knnd_build_batched", "knnd_exact_knn",
 ]
 
 
@@ -101,6 +101,7 @@ def lib():
         "knnd_ctx_rounds": (ctypes.c_int, [vp]),
         "knnd_ctx_destroy": (ctypes.c_int, [vp]),
         "knnd_build_batched": (ctypes.c_int, [P(knnd_instance), i32, P(knnd_params), i32, vp]),
+        "knnd_exact_knn": (ctypes.c_int, [vp, i64, i32, i32, i32, vp, i64, vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -249,6 +250,33 @@ def knnd_build_batched(instances, params=None, stream=None, with_kl=True):
         out.append({"status": arr[b].status, "idx": idx, "kl": kl, "rounds": r,
                     "stats": [stats[i].as_dict() for i in range(r + 1)]})
     return st, out
+
+
+def knnd_exact_knn(points, d, K, queries, tau=None, stream=None, with_kl=True):
+    """Exact K nearest neighbours of the points listed in `queries` (int32
+    indices), by exhaustive comparison.  points/queries/tau: numpy host
+    arrays or torch device tensors (all on the same side); outputs on that
+    side.  Returns (idx [nq][K], kl [nq][K] or None)."""
+    points = _check_points(points, d)
+    n = points.shape[0]
+    dev = 1 if _is_device(points) else 0
+    if dev:
+        import torch
+        queries = queries.to(device=points.device, dtype=torch.int32).contiguous()
+        if tau is not None:
+            tau = tau.to(device=points.device, dtype=torch.float64).contiguous()
+    else:
+        queries = np.ascontiguousarray(queries, dtype=np.int32)
+        if tau is not None:
+            tau = np.ascontiguousarray(tau, dtype=np.float64)
+    nq = queries.shape[0]
+    idx = _empty(points, (nq, K), np.int32)
+    kl = _empty(points, (nq, K), np.float64) if with_kl else None
+    st = lib().knnd_exact_knn(_ptr(points), n, d, K, _dtype_code(points), _ptr(queries), nq, _ptr(tau),
+                              dev, _stream_of(points, stream), _ptr(idx), _ptr(kl))
+    if st < 0:
+        raise KnndError(st, "knnd_exact_knn")
+    return idx, kl
 
 
 class Context:

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libknnd.so")
-SOURCES = ["knnd_api.hip", "knnd_kernels.hip"]
+SOURCES = ["knnd_api.hip", "knnd_kernels.hip", "knnd_exact.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

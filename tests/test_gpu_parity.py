@@ -387,10 +387,65 @@ def test_config4_full_size_and_recall():
     P64 = oracle.widen(P)
     L = oracle.log_table(P64)
     qs = synth.subsample(c["seed"], c["n"], 2000)
-    bf, _ = oracle.bruteforce(P64, L, c["K"], qs)
+    bf, bk = oracle.bruteforce(P64, L, c["K"], qs)
     rec = np.mean([len(set(g["idx"][q].tolist()) & set(b.tolist())) / c["K"] for q, b in zip(qs, bf)])
     say(f"config 4 recall@{c['K']} on 2000 queries: {rec:.4f}")
     assert 0.0 < rec <= 1.0
+    # the library's exhaustive search, bounded by the descent's K-th keys
+    ei, ek = knnd.knnd_exact_knn(P, c["d"], c["K"], qs.astype(np.int32), tau=g["kl"][qs, -1])
+    assert np.array_equal(ei, bf)
+    assert np.array_equal(bits(ek), bits(bk))
+
+
+# ---------------------------------------------------------------------------
+# Exhaustive search (knnd_exact_knn) against the oracle's brute force
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,d,K,dtype", [(5000, 9, 16, np.float32), (3001, 20, 30, np.float32),
+                                         (700, 3, 64, np.float64), (12000, 59, 20, np.float32),
+                                         (65, 1, 64, np.float32)])
+def test_exact_knn_matches_oracle(n, d, K, dtype):
+    P = synth.dirichlet(n + 5, n, d, dtype)
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    qs = synth.subsample(n, n, min(n, 203))
+    say(f"exact knn n={n} d={d} K={K} {np.dtype(dtype).name}, {qs.size} queries")
+    bf, bk = oracle.bruteforce(P64, L, K, qs)
+    ei, ek = knnd.knnd_exact_knn(P, d, K, qs.astype(np.int32))
+    assert np.array_equal(ei, bf)
+    assert np.array_equal(bits(ek), bits(bk))
+
+
+def test_exact_knn_ties_and_bound_refinement():
+    # 2 distinct points, 5000 copies each: every query has 4999 keys of exactly
+    # zero; a bound of 0.0 admits all of them (more than one 4096-entry buffer
+    # holds), so the bound must be tightened until the ties are settled by index
+    base = synth.dirichlet(91, 2, 6, np.float32)
+    P = np.repeat(base, 5000, axis=0)
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    qs = np.array([0, 1, 4999, 5000, 9999, 7321], dtype=np.int64)
+    bf, bk = oracle.bruteforce(P64, L, 12, qs)
+    for tau in (None, np.zeros(qs.size)):
+        ei, ek = knnd.knnd_exact_knn(P, 6, 12, qs.astype(np.int32), tau=tau)
+        assert np.array_equal(ei, bf)
+        assert np.array_equal(bits(ek), bits(bk))
+
+
+def test_exact_knn_device_pointers_and_errors():
+    torch = pytest.importorskip("torch")
+    P = synth.dirichlet(17, 2000, 7, np.float32)
+    qs = synth.subsample(5, 2000, 64).astype(np.int32)
+    hi, hk = knnd.knnd_exact_knn(P, 7, 10, qs)
+    di, dk = knnd.knnd_exact_knn(torch.from_numpy(P).cuda(), 7, 10, torch.from_numpy(qs).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(hi, di.cpu().numpy())
+    assert np.array_equal(bits(hk), bits(dk.cpu().numpy()))
+    with pytest.raises(knnd.KnndError) as e:  # a bound below the K-th key
+        knnd.knnd_exact_knn(P, 7, 10, qs, tau=np.full(qs.size, -1.0))
+    assert e.value.status == knnd.KNND_ERR_ARG
+    with pytest.raises(knnd.KnndError) as e:  # query out of range
+        knnd.knnd_exact_knn(P, 7, 10, np.array([3, 2000], dtype=np.int32))
+    assert e.value.status == knnd.KNND_ERR_ARG
 
 
 # ---------------------------------------------------------------------------
