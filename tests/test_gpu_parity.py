@@ -523,3 +523,33 @@ def test_config5_batched_full_size(prec):
         assert [s["evals_alg"] for s in g["stats"][1:]] == o["evals_alg"][1:], b
         assert _digest(g["idx"]) == o["idx_sha256"], b
         assert _digest(g["kl"]) == o["kl_sha256"], b
+
+
+# ---------------------------------------------------------------------------
+# The paper's printed statistics (Section 4, Tables 3 and 4), reproduced on
+# the GPU path with other random draws: tolerance bands, not equality.
+# ---------------------------------------------------------------------------
+def test_paper_tables_statistics_on_gpu():
+    torch = pytest.importorskip("torch")
+    from paper_2202_00517_amd import paper_tables as pt
+    t3 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_table3.json")))["rows"]
+    t4 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_table4.json")))
+    for i, p in enumerate(t3[:4]):  # n = 2e4 and 2e5, 10 coordinates
+        r = pt.run_row(p["n"], p["coordinates"], p["K"], 3100 + i, 3200 + i, torch, knnd.KNND_PREC_MIXED_BF16)
+        say(f"table 3 row {i}: {r}")
+        assert r["rounds"] <= p["round_bound"] and abs(r["rounds"] - p["rounds"]) <= 2
+        assert abs(r["fcc"] - p["fcc"]) < 0.05
+        assert r["accuracy_2000"] >= 0.85
+    acc = {}
+    for i, p in enumerate(t4["rows"]):
+        r = pt.run_row(t4["n"], p["coordinates"], p["K"], 4100 + i, 4200 + i, torch, knnd.KNND_PREC_MIXED_BF16)
+        say(f"table 4 row {i}: {r}")
+        assert r["rounds"] <= r["round_bound"]
+        assert abs(r["fcc"] - p["fcc"]) < 0.03
+        assert abs(r["accuracy_2000"] - p["accuracy"]) < 0.25
+        acc[(p["K"], p["coordinates"])] = r["accuracy_2000"]
+    # accuracy declines with dimension, and K = 64 is more accurate than K = 16
+    for K in (16, 64):
+        assert acc[(K, 10)] > acc[(K, 40)] and acc[(K, 20)] > acc[(K, 60)]
+    for c in (10, 20, 40, 60):
+        assert acc[(64, c)] > acc[(16, c)]
