@@ -51,7 +51,8 @@ def _load():
         "oracle_bruteforce": (c_int, [vp, vp, i64, c_int, c_int, vp, i64, vp, vp, c_int]),
         "oracle_should_stop": (c_int, [i64, i64, i64, c_int, c_int]),
         "oracle_build": (c_int, [vp, c_int, i64, c_int, c_int, u64, i64, c_int, c_int, vp, vp,
-                                 vp, vp, vp, vp, vp]),
+                                 vp, vp, vp, vp, vp, c_int, ctypes.c_double]),
+        "oracle_stop_rule": (c_int, [c_int, ctypes.c_double, i64, c_int, i64, i64, i64, c_int, c_int, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -174,6 +175,17 @@ def should_stop(hits_prev, hits_cur, updates, rnd, max_rounds):
     return bool(_load().oracle_should_stop(hits_prev, hits_cur, updates, rnd, max_rounds))
 
 
+STOP_FCR, STOP_FIXED_POINT, STOP_DELTA = 0, 1, 2
+
+
+def stop_rule(rule, delta, n, K, hits_prev, hits_cur, updates, rnd, max_rounds):
+    """(stop?, stopped only by the round cap?) under one of the stop rules."""
+    capped = ctypes.c_int(0)
+    s = _load().oracle_stop_rule(rule, delta, n, K, hits_prev, hits_cur, updates, rnd, max_rounds,
+                                 ctypes.byref(capped))
+    return bool(s), bool(capped.value)
+
+
 class Result:
     """Outcome of a whole descent."""
 
@@ -183,7 +195,7 @@ class Result:
         self.rounds, self.seconds = rounds, seconds
 
 
-def build_graph(points, d, K, seed, M=0, max_rounds=100, threads=0):
+def build_graph(points, d, K, seed, M=0, max_rounds=100, threads=0, stop_rule=0, delta=0.0):
     """Run the whole descent on points [n][d+1] (FP32 or FP64)."""
     points = np.ascontiguousarray(points)
     if points.dtype == np.float32:
@@ -203,6 +215,6 @@ def build_graph(points, d, K, seed, M=0, max_rounds=100, threads=0):
     rounds = ctypes.c_int32(0)
     st = _load().oracle_build(_p(points), dtype, n, d, K, seed, M, max_rounds, threads, _p(idx),
                               _p(keys), _p(upd), _p(hits), _p(evals), ctypes.byref(rounds),
-                              _p(secs))
+                              _p(secs), stop_rule, delta)
     r = rounds.value
     return Result(st, idx, keys, upd[:r + 1], hits[:r + 1], evals[:r + 1], r, secs[:r + 1])

@@ -362,6 +362,29 @@ int oracle_should_stop(int64_t hits_prev, int64_t hits_cur, int64_t updates, int
   return 0;
 }
 
+// The other terminations the paper names among K-NN descent implementations
+// (Section 2, Table 1 and item (b)):
+//   rule 1, "no possible update": stop after the first round that changed no
+//           list (a fixed point of the round map);
+//   rule 2, the delta-proportion rule of Dong et al.: stop after the first
+//           round whose update count is at most delta * n * K (the product
+//           taken in FP64, left to right);
+// and rule 0 is the statistical criterion above.  Every rule also stops at
+// the round cap.  Returns 1 to stop; *capped is set when only the cap
+// stopped the run.
+int oracle_stop_rule(int rule, double delta, int64_t n, int K, int64_t hits_prev, int64_t hits_cur,
+                     int64_t updates, int round, int max_rounds, int* capped) {
+  bool rule_stops;
+  if (rule == 1)
+    rule_stops = updates == 0;
+  else if (rule == 2)
+    rule_stops = (double)updates <= delta * (double)n * (double)K;
+  else
+    rule_stops = hits_cur <= hits_prev || updates == 0;
+  if (capped) *capped = !rule_stops && round >= max_rounds;
+  return rule_stops || round >= max_rounds;
+}
+
 // Whole descent: validate, log table, random K-out graph, FCR of the initial
 // graph, then synchronous rounds until the stop rule fires.
 //   points: [n][d+1] row-major, FP32 (dtype 0) or FP64 (dtype 1); widened to
@@ -370,12 +393,14 @@ int oracle_should_stop(int64_t hits_prev, int64_t hits_cur, int64_t updates, int
 //   M <= 0 selects the default sample size min(n, 10000).
 //   Per-round outputs have max_rounds+1 entries; entry 0 is the initial graph.
 // Returns 0, 1 when the round cap stopped the run, or a negative error.
+//   stop_rule / delta: see oracle_stop_rule (0 = the paper's criterion).
 int oracle_build(const void* points, int dtype, int64_t n, int d, int K, uint64_t seed,
                  int64_t M, int max_rounds, int threads, int32_t* out_idx, double* out_keys,
                  int64_t* out_updates, int64_t* out_hits, int64_t* out_evals,
-                 int32_t* out_rounds, double* out_seconds) {
+                 int32_t* out_rounds, double* out_seconds, int stop_rule, double delta) {
   if (!points || !out_idx || n < 2 || d < 1 || K < 2 || K > n - 1 || max_rounds < 1 ||
-      (dtype != 0 && dtype != 1) || n > ((int64_t)1 << 30))
+      (dtype != 0 && dtype != 1) || n > ((int64_t)1 << 30) || stop_rule < 0 || stop_rule > 2 ||
+      !(delta >= 0.0) || !std::isfinite(delta))
     return ORC_ERR_ARG;
   const int D = d + 1;
   const size_t cnt = (size_t)n * D;
@@ -418,8 +443,9 @@ int oracle_build(const void* points, int dtype, int64_t n, int d, int K, uint64_
     if (out_hits) out_hits[r] = hits;
     if (out_evals) out_evals[r] = ev;
     if (out_seconds) out_seconds[r] = secs(tr);
-    if (oracle_should_stop(hits_prev, hits, upd, r, max_rounds)) {
-      if (r >= max_rounds && hits > hits_prev && upd != 0) status = ORC_WARN_MAX_ROUNDS;
+    int capped = 0;
+    if (oracle_stop_rule(stop_rule, delta, n, K, hits_prev, hits, upd, r, max_rounds, &capped)) {
+      if (capped) status = ORC_WARN_MAX_ROUNDS;
       break;
     }
     hits_prev = hits;

@@ -240,3 +240,56 @@ def test_paper_table3_first_row_statistics():
     bf, _ = oracle.bruteforce(P64, L, K, qs)
     acc = np.mean([len(set(res.idx[q].tolist()) & set(b.tolist())) / K for q, b in zip(qs, bf)])
     assert acc >= 0.9
+
+
+# ---------------------------------------------------------------------------
+# Other terminations (Section 2, Table 1 and item (b)): "no possible update"
+# and Dong et al.'s delta-proportion rule.  All rules follow one trajectory
+# and differ only in the round they stop at.
+# ---------------------------------------------------------------------------
+def test_stop_rules_on_hand_built_sequences():
+    n, K = 1000, 10
+    # fixed point: only a round without updates (or the cap) stops
+    assert oracle.stop_rule(1, 0.0, n, K, 50, 40, 7, 3, 100) == (False, False)
+    assert oracle.stop_rule(1, 0.0, n, K, 50, 60, 0, 3, 100) == (True, False)
+    assert oracle.stop_rule(1, 0.0, n, K, 50, 60, 7, 100, 100) == (True, True)
+    # delta: updates <= delta n K = 100
+    assert oracle.stop_rule(2, 0.01, n, K, 50, 40, 101, 3, 100) == (False, False)
+    assert oracle.stop_rule(2, 0.01, n, K, 50, 60, 100, 3, 100) == (True, False)
+    assert oracle.stop_rule(2, 0.01, n, K, 50, 60, 101, 9, 9) == (True, True)
+    # the statistical criterion is the default rule
+    assert oracle.stop_rule(0, 0.0, n, K, 50, 50, 7, 3, 100) == (True, False)
+    assert oracle.stop_rule(0, 0.0, n, K, 50, 51, 7, 3, 100) == (False, False)
+
+
+def test_fixed_point_rule_reaches_a_fixed_point():
+    P = synth.dirichlet(515, 400, 4, np.float64)
+    fp = oracle.build_graph(P, 4, 6, seed=21, stop_rule=oracle.STOP_FIXED_POINT)
+    assert fp.status == oracle.OK and fp.updates[-1] == 0
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    Fn, kn, upd, _ = oracle.round_step(P64, L, fp.idx, fp.keys)
+    assert upd == 0 and np.array_equal(Fn, fp.idx) and np.array_equal(kn, fp.keys)
+    # the statistical rule stops on the same trajectory, no later
+    st = oracle.build_graph(P, 4, 6, seed=21)
+    assert st.rounds <= fp.rounds
+    assert np.array_equal(st.updates, fp.updates[:st.rounds + 1])
+    assert np.array_equal(st.hits, fp.hits[:st.rounds + 1])
+
+
+def test_delta_rule_stops_at_first_small_round():
+    n, d, K = 600, 5, 8
+    P = synth.dirichlet(616, n, d, np.float64)
+    fp = oracle.build_graph(P, d, K, seed=22, stop_rule=oracle.STOP_FIXED_POINT)
+    for delta in (0.05, 0.01, 0.001):
+        first = next(r for r in range(1, fp.rounds + 1) if fp.updates[r] <= delta * n * K)
+        dl = oracle.build_graph(P, d, K, seed=22, stop_rule=oracle.STOP_DELTA, delta=delta)
+        assert dl.status == oracle.OK and dl.rounds == first
+        cut = oracle.build_graph(P, d, K, seed=22, stop_rule=oracle.STOP_FIXED_POINT, max_rounds=first)
+        assert np.array_equal(dl.idx, cut.idx) and np.array_equal(dl.keys, cut.keys)
+
+
+def test_stop_rule_arguments():
+    P = synth.dirichlet(3, 50, 3, np.float64)
+    assert oracle.build_graph(P, 3, 4, 1, stop_rule=3).status == oracle.ERR_ARG
+    assert oracle.build_graph(P, 3, 4, 1, stop_rule=2, delta=-1.0).status == oracle.ERR_ARG
