@@ -29,11 +29,13 @@
  *                a = bnd(H(seed,3,r,s), K), b' = bnd(H(seed,4,r,s), K-1),
  *                b = b' + (b' >= a); hit when F(x)[b] is a friend of
  *                F(x)[a] or F(x)[a] is a friend of F(x)[b].
- *   stop       : after round r when hits_r <= hits_{r-1}, or no list changed
- *                (fixed point), or r == max_rounds.
+ *   stop       : by default (KNND_STOP_FCR) after round r when
+ *                hits_r <= hits_{r-1}, or no list changed (fixed point), or
+ *                r == max_rounds; knnd_stop_rule lists the other rules.
  *   H          : SplitMix64-finalizer hash
  *                H(s,t,a,b) = mix64(mix64(mix64(s ^ t*0x9E3779B97F4A7C15) ^ a) ^ b).
- * Results depend only on (points, K, seed, fcr_samples, max_rounds): not on
+ * Results depend only on (points, K, seed, fcr_samples, max_rounds, the stop
+ * rule and its delta): not on
  * the precision mode, on tiling or on scheduling.
  *
  * Threading: calls on distinct contexts/outputs may run concurrently.
@@ -49,7 +51,7 @@
 extern "C" {
 #endif
 
-#define KNND_ABI_VERSION 2
+#define KNND_ABI_VERSION 3
 
 typedef enum {
     KNND_OK = 0,
@@ -89,12 +91,35 @@ typedef enum {
                                    candidates' log rows) instead of hub form
                                    (same result) */
 
+/*
+ * Termination (Section 2, Table 1 and item (b)).  Every rule runs the same
+ * rounds and differs only in the round after which it stops, so a run under
+ * one rule is a prefix of the run under any rule that stops later.  Every
+ * rule also stops at r == max_rounds (status KNND_WARN_MAX_ROUNDS when the
+ * rule itself would not have stopped there).
+ */
+typedef enum {
+    KNND_STOP_FCR = 0,          /* the paper's statistical criterion: stop after
+                                   round r when hits_r <= hits_{r-1} (friend
+                                   clustering rate no longer rising) or no list
+                                   changed */
+    KNND_STOP_FIXED_POINT = 1,  /* stop after the first round in which no list
+                                   changed: no possible update remains */
+    KNND_STOP_DELTA = 2         /* Dong et al.'s rule: stop after the first round
+                                   whose update count u_r satisfies
+                                   (double)u_r <= delta * (double)n * (double)K,
+                                   evaluated in FP64 left to right */
+} knnd_stop_rule;
+
 typedef struct {
     int32_t precision;          /* knnd_precision */
     int32_t dtype;              /* knnd_dtype of `points` */
     int64_t fcr_samples;        /* M; <= 0 selects min(n, 10000) */
     int32_t max_rounds;         /* <= 0 selects 100 */
     int32_t flags;              /* KNND_FLAG_* */
+    int32_t stop_rule;          /* knnd_stop_rule */
+    int32_t reserved;           /* must be 0 */
+    double delta;               /* KNND_STOP_DELTA only: finite, >= 0 */
 } knnd_params;
 
 /* Per-round record.  Entry 0 describes the initial graph (fcr_hits only). */
@@ -113,7 +138,8 @@ typedef struct {
                                    rescue, merge, every size class) */
 } knnd_round_stats;
 
-/* Fill *p with the defaults (FP64, F32 points, M = min(n,10000), 100 rounds). */
+/* Fill *p with the defaults (FP64, F32 points, M = min(n,10000), 100 rounds,
+   KNND_STOP_FCR, delta 0, flags 0). */
 void knnd_default_params(knnd_params* p);
 
 /* Human-readable name of a knnd_status value (static storage). */

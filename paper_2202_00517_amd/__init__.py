@@ -26,6 +26,7 @@ KNND_F32, KNND_F64 = 0, 1
 KNND_PREC_FP64, KNND_PREC_MIXED_BF16, KNND_PREC_MIXED_FP16 = 0, 1, 2
 KNND_FLAG_NO_SKIP = 0x1
 KNND_FLAG_PULL = 0x2
+KNND_STOP_FCR, KNND_STOP_FIXED_POINT, KNND_STOP_DELTA = 0, 1, 2
 
 EXPORTED = [
     "knnd_default_params", "knnd_status_string", "knnd_abi_version", "knnd_build",
@@ -35,13 +36,14 @@ EXPORTED = [
 ]
 
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class knnd_params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("fcr_samples", ctypes.c_int64), ("max_rounds", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("stop_rule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("delta", ctypes.c_double)]
 
 
 class knnd_round_stats(ctypes.Structure):

@@ -70,6 +70,8 @@ int resolve_params(const knnd_params* p, int64_t n, knnd_params* out) {
   if (out->max_rounds <= 0) out->max_rounds = 100;
   if (out->dtype != KNND_F32 && out->dtype != KNND_F64) return KNND_ERR_ARG;
   if (out->precision < KNND_PREC_FP64 || out->precision > KNND_PREC_MIXED_FP16) return KNND_ERR_ARG;
+  if (out->stop_rule < KNND_STOP_FCR || out->stop_rule > KNND_STOP_DELTA || out->reserved != 0) return KNND_ERR_ARG;
+  if (!(out->delta >= 0.0) || !std::isfinite(out->delta)) return KNND_ERR_ARG;
   return KNND_OK;
 }
 
@@ -329,8 +331,19 @@ int get_graph(Ctx& c, int32_t* idx, double* kl, int32_t on_device) {
   return KNND_OK;
 }
 
-bool should_stop(int64_t hits_prev, int64_t hits, int64_t updates, int r, int max_rounds) {
-  return hits <= hits_prev || updates == 0 || r >= max_rounds;
+// Stop test after round r of an instance with n points (Section 2, Table 1
+// and item (b)); *capped tells whether only the round cap stopped it.
+bool should_stop(const knnd_params& p, int64_t n, int K, int64_t hits_prev, int64_t hits, int64_t updates,
+                 int r, bool* capped) {
+  bool rule;
+  if (p.stop_rule == KNND_STOP_FIXED_POINT)
+    rule = updates == 0;
+  else if (p.stop_rule == KNND_STOP_DELTA)
+    rule = (double)updates <= p.delta * (double)n * (double)K;
+  else
+    rule = hits <= hits_prev || updates == 0;
+  *capped = !rule && r >= p.max_rounds;
+  return rule || r >= p.max_rounds;
 }
 
 // ---------------------------------------------------------------------------
@@ -564,8 +577,8 @@ int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t 
           g.hits_prev[j] = rs.fcr_hits;
           continue;
         }
-        if (should_stop(g.hits_prev[j], rs.fcr_hits, rs.updates, r, prm.max_rounds)) {
-          const bool capped = r >= prm.max_rounds && rs.fcr_hits > g.hits_prev[j] && rs.updates != 0;
+        bool capped = false;
+        if (should_stop(prm, in.n, in.K, g.hits_prev[j], rs.fcr_hits, rs.updates, r, &capped)) {
           in.status = capped ? KNND_WARN_MAX_ROUNDS : KNND_OK;
           if (capped) worst = KNND_WARN_MAX_ROUNDS;
           *in.out_rounds = r;
@@ -601,6 +614,9 @@ void knnd_default_params(knnd_params* p) {
   p->fcr_samples = 0;
   p->max_rounds = 100;
   p->flags = 0;
+  p->stop_rule = KNND_STOP_FCR;
+  p->reserved = 0;
+  p->delta = 0.0;
 }
 
 const char* knnd_status_string(int s) {
@@ -698,6 +714,8 @@ int knnd_build_ex(const void* points, int64_t n, int32_t d, int32_t K, uint64_t 
   int st = knnd_ctx_create(points, n, d, K, seed, p, on_device, stream, &h);
   if (st != KNND_OK) return st;
   Ctx& c = h->c;
+  knnd_params prm;
+  (void)resolve_params(p, n, &prm);  // already accepted by knnd_ctx_create
   knnd_round_stats rs;
   st = init_graph(c, &rs);
   if (st == KNND_OK) {
@@ -707,8 +725,9 @@ int knnd_build_ex(const void* points, int64_t n, int32_t d, int32_t K, uint64_t 
       st = run_round(c, &rs);
       if (st != KNND_OK) break;
       if (stats) stats[c.round] = rs;
-      if (should_stop(hits_prev, rs.fcr_hits, rs.updates, c.round, c.max_rounds)) {
-        if (c.round >= c.max_rounds && rs.fcr_hits > hits_prev && rs.updates != 0) st = KNND_WARN_MAX_ROUNDS;
+      bool capped = false;
+      if (should_stop(prm, c.n, c.K, hits_prev, rs.fcr_hits, rs.updates, c.round, &capped)) {
+        if (capped) st = KNND_WARN_MAX_ROUNDS;
         break;
       }
       hits_prev = rs.fcr_hits;

@@ -9,7 +9,12 @@ Inputs are synthetic Dirichlet(1,...,1) points (the paper's workload), FP32
 storage, generated with fixed seeds; the paper's random draws are not
 reproducible, so its rounds, FCC and accuracy are context, not targets.
 
-    python -m paper_2202_00517_amd.paper_tables [--table 3|4|all] [--json out.json]
+`--table stop` runs the other terminations of Section 2 (Table 1, item (b))
+on the n = 1e6, 21-coordinate, K = 30 workload: the statistical FCR test,
+Dong et al.'s delta-proportion rule at two deltas, and the fixed point, each
+with its rounds, time to graph, evaluations and accuracy.
+
+    python -m paper_2202_00517_amd.paper_tables [--table 3|4|stop|all] [--json out.json]
 """
 import argparse
 import json
@@ -43,10 +48,10 @@ def accuracy(idx, P, d, K, queries, kl_bound, torch):
     return float(np.mean([len(set(a.tolist()) & set(b.tolist())) / K for a, b in zip(got, tru)]))
 
 
-def run_row(n, coords, K, data_seed, seed, torch, precision):
+def run_row(n, coords, K, data_seed, seed, torch, precision, stop_rule=0, delta=0.0):
     d = coords - 1
     P = torch.from_numpy(synth.dirichlet(data_seed, n, d, np.float32)).cuda()
-    prm = knnd.default_params(precision=precision)
+    prm = knnd.default_params(precision=precision, stop_rule=stop_rule, delta=delta)
     t = time.perf_counter()
     out = knnd.knnd_build_ex(P, d, K, seed, prm)
     torch.cuda.synchronize()
@@ -57,7 +62,8 @@ def run_row(n, coords, K, data_seed, seed, torch, precision):
            "round_bound": 2 * math.ceil(math.log(n) / math.log(K)),
            "fcc": st[-1]["fcr_hits"] / M, "first_round_ms": round(st[1]["ms"], 2),
            "last_round_ms": round(st[-1]["ms"], 2), "time_to_graph_ms": round(1e3 * wall, 1),
-           "evals_alg": int(sum(s["evals_alg"] for s in st))}
+           "evals_alg": int(sum(s["evals_alg"] for s in st)), "last_updates": int(st[-1]["updates"]),
+           "status": out["status"]}
     idx, kl = out["idx"], out["kl"]
     for name, m in (("accuracy_6", 6), ("accuracy_2000", 2000)):
         q = _sample(seed + m, n, m)
@@ -92,6 +98,33 @@ def table4(torch, precision):
     return rows
 
 
+STOP_RULES = [("FCR test (paper)", knnd.KNND_STOP_FCR, 0.0), ("delta = 0.01", knnd.KNND_STOP_DELTA, 0.01),
+              ("delta = 0.001", knnd.KNND_STOP_DELTA, 0.001), ("fixed point", knnd.KNND_STOP_FIXED_POINT, 0.0)]
+
+
+def stop_rules(torch, precision, n=1000000, coords=21, K=30):
+    rows = []
+    for name, rule, delta in STOP_RULES:
+        r = run_row(n, coords, K, 5100, 5200, torch, precision, rule, delta)
+        r["rule"] = name
+        print(json.dumps(r), flush=True)
+        rows.append(r)
+    return rows
+
+
+def markdown_stop(rows):
+    if not rows:
+        return ""
+    r0 = rows[0]
+    lines = [f"Stop rules (n = {r0['n']:.0e}, {r0['coordinates']} coordinates, K = {r0['K']}):", "",
+             "| rule | rounds | updates in last round | evaluations | time to graph ms | accuracy 2000 pts |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {r['rule']} | {r['rounds']} | {r['last_updates']} | {r['evals_alg']:.3e} | "
+                     f"{r['time_to_graph_ms']} | {r['accuracy_2000']:.4f} |")
+    return "\n".join(lines)
+
+
 def markdown(t3, t4):
     lines = []
     if t3:
@@ -117,7 +150,7 @@ def markdown(t3, t4):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--table", default="all", choices=["3", "4", "all"])
+    ap.add_argument("--table", default="all", choices=["3", "4", "stop", "all"])
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "plain"])
     ap.add_argument("--json", default=None)
     args = ap.parse_args()
@@ -126,10 +159,12 @@ def main():
             "plain": knnd.KNND_PREC_FP64}[args.precision]
     t3 = table3(torch, prec) if args.table in ("3", "all") else []
     t4 = table4(torch, prec) if args.table in ("4", "all") else []
+    sr = stop_rules(torch, prec) if args.table in ("stop", "all") else []
     print(markdown(t3, t4), flush=True)
+    print(markdown_stop(sr), flush=True)
     if args.json:
         with open(args.json, "w") as f:
-            json.dump({"table3": t3, "table4": t4}, f, indent=1)
+            json.dump({"table3": t3, "table4": t4, "stop_rules": sr}, f, indent=1)
 
 
 if __name__ == "__main__":

@@ -39,10 +39,30 @@ def test_abi_version_and_status_strings():
 
 
 def test_params_struct_layout_matches_header():
-    assert ctypes.sizeof(knnd.knnd_params) == 24
+    assert ctypes.sizeof(knnd.knnd_params) == 40
+    assert knnd.knnd_params.delta.offset == 32
     assert ctypes.sizeof(knnd.knnd_round_stats) == 72
     p = knnd.default_params()
     assert (p.precision, p.dtype, p.fcr_samples, p.max_rounds, p.flags) == (0, 0, 0, 100, 0)
+    assert (p.stop_rule, p.reserved, p.delta) == (knnd.KNND_STOP_FCR, 0, 0.0)
+
+
+@pytest.mark.parametrize("kw", [dict(stop_rule=3), dict(stop_rule=-1), dict(reserved=1),
+                                dict(stop_rule=2, delta=-0.5), dict(stop_rule=2, delta=float("nan")),
+                                dict(stop_rule=2, delta=float("inf")), dict(precision=3)])
+def test_bad_params_are_argument_errors_before_device_work(kw):
+    P = np.full((10, 4), 0.25, dtype=np.float32)
+    idx = np.empty((10, 3), dtype=np.int32)
+    r = ctypes.c_int32()
+    p = knnd.default_params(**kw)
+    st = knnd.lib().knnd_build_ex(P.ctypes.data, 10, 3, 3, 1, ctypes.byref(p), 0, None,
+                                  idx.ctypes.data, None, None, ctypes.byref(r))
+    assert st == knnd.KNND_ERR_ARG
+    arr = (knnd.knnd_instance * 1)()
+    arr[0].points, arr[0].n, arr[0].d, arr[0].K, arr[0].seed = P.ctypes.data, 10, 3, 3, 1
+    arr[0].out_idx = idx.ctypes.data
+    arr[0].out_rounds = ctypes.pointer(r)
+    assert knnd.lib().knnd_build_batched(arr, 1, ctypes.byref(p), 0, None) == knnd.KNND_ERR_ARG
 
 
 @pytest.mark.parametrize("n,d,K", [(1, 3, 2), (10, 0, 2), (10, 3, 1), (10, 3, 10), (200, 3, 65)])

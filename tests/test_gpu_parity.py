@@ -44,13 +44,14 @@ def assert_same_graph(gi, gk, oi, ok, what):
     assert kb.size == 0, f"{what}: keys differ in {kb.size} rows, first x={kb[:5].tolist()}"
 
 
-def full_compare(P, d, K, seed, M=0, flags=0, max_rounds=100, precision=0):
+def full_compare(P, d, K, seed, M=0, flags=0, max_rounds=100, precision=0, stop_rule=0, delta=0.0):
     say(f"full build n={P.shape[0]} d={d} K={K} seed={seed} {P.dtype} M={M} flags={flags} "
-        f"precision={precision}")
+        f"precision={precision} stop_rule={stop_rule} delta={delta}")
     prm = knnd.default_params(fcr_samples=M, flags=flags, max_rounds=max_rounds,
-                              precision=precision)
+                              precision=precision, stop_rule=stop_rule, delta=delta)
     g = knnd.knnd_build_ex(P, d, K, seed, prm)
-    o = oracle.build_graph(P, d, K, seed, M=M, max_rounds=max_rounds)
+    o = oracle.build_graph(P, d, K, seed, M=M, max_rounds=max_rounds, stop_rule=stop_rule,
+                           delta=delta)
     assert g["status"] == o.status
     assert g["rounds"] == o.rounds, (g["rounds"], o.rounds)
     for r in range(o.rounds + 1):
@@ -220,6 +221,26 @@ def test_skipping_old_paths_changes_nothing(form):
     else:  # the hub form computes every candidate occurrence except x itself
         n, K = 6000, 16
         assert b["stats"][1]["evals_performed"] == n * K * (2 * K + 1) - n * K
+
+
+STOP_CASES = [(knnd.KNND_STOP_FIXED_POINT, 0.0), (knnd.KNND_STOP_DELTA, 0.01),
+              (knnd.KNND_STOP_DELTA, 0.001), (knnd.KNND_STOP_DELTA, 0.0)]
+
+
+@pytest.mark.parametrize("form", [FORMS[0], FORMS[2]], ids=["hub", "bf16"])
+@pytest.mark.parametrize("rule,delta", STOP_CASES, ids=["fixed_point", "delta1e-2", "delta1e-3", "delta0"])
+@pytest.mark.parametrize("n,d,K,ds,seed", [(3001, 20, 30, 5, 7), (20000, 10, 20, 6, 8), (5000, 4, 8, 9, 3)])
+def test_stop_rules_full(n, d, K, ds, seed, rule, delta, form):
+    P = synth.dirichlet(ds, n, d, np.float32)
+    g, o = full_compare(P, d, K, seed, flags=form[0], precision=form[1], stop_rule=rule, delta=delta)
+    if rule == knnd.KNND_STOP_FIXED_POINT or delta == 0.0:
+        assert g["stats"][g["rounds"]]["updates"] == 0
+
+
+def test_stop_rule_round_cap_warns():
+    P = synth.dirichlet(9, 5000, 4, np.float32)
+    g, o = full_compare(P, 4, 8, 3, max_rounds=4, stop_rule=knnd.KNND_STOP_FIXED_POINT)
+    assert g["status"] == knnd.KNND_WARN_MAX_ROUNDS and g["rounds"] == 4
 
 
 def test_round_cap_and_fcr_sample_size():
@@ -452,8 +473,8 @@ def test_exact_knn_device_pointers_and_errors():
 # Batched instances (knnd_build_batched): each instance must come out exactly
 # as the oracle's descent of that instance alone.
 # ---------------------------------------------------------------------------
-def _compare_instance(g, P, d, K, seed, what):
-    o = oracle.build_graph(P, d, K, seed)
+def _compare_instance(g, P, d, K, seed, what, stop_rule=0, delta=0.0):
+    o = oracle.build_graph(P, d, K, seed, stop_rule=stop_rule, delta=delta)
     assert g["status"] == o.status, what
     assert g["rounds"] == o.rounds, (what, g["rounds"], o.rounds)
     for r in range(o.rounds + 1):
@@ -479,6 +500,20 @@ def test_batched_mix_vs_oracle(prec):
     assert st == knnd.KNND_OK
     for (P, d, K, s), g in zip(inst, outs):
         _compare_instance(g, P, d, K, s, f"instance n={P.shape[0]} d={d} K={K}")
+
+
+# Other stop rules (Section 2, Table 1 and item (b)): same rounds, another
+# stopping round; each instance stops on its own n.
+@pytest.mark.parametrize("rule,delta", [(knnd.KNND_STOP_FIXED_POINT, 0.0), (knnd.KNND_STOP_DELTA, 0.002)],
+                         ids=["fixed_point", "delta"])
+def test_batched_stop_rules_vs_oracle(rule, delta):
+    inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX]
+    say(f"batched: stop rule {rule} delta {delta}")
+    st, outs = knnd.knnd_build_batched(inst, knnd.default_params(precision=knnd.KNND_PREC_MIXED_BF16,
+                                                                 stop_rule=rule, delta=delta))
+    assert st == knnd.KNND_OK
+    for (P, d, K, s), g in zip(inst, outs):
+        _compare_instance(g, P, d, K, s, f"instance n={P.shape[0]} d={d} K={K}", rule, delta)
 
 
 def test_batched_device_pointers_match_host():
