@@ -92,9 +92,10 @@ typedef enum {
                                    (same result) */
 
 /*
- * Termination (Section 2, Table 1 and item (b)).  Every rule runs the same
- * rounds and differs only in the round after which it stops, so a run under
- * one rule is a prefix of the run under any rule that stops later.  Every
+ * Termination (Section 1.2, Table 1, and Section 1.3, item (b)).  Every
+ * rule runs the same rounds and differs only in the round after which it
+ * stops, so a run under one rule is a prefix of the run under any rule that
+ * stops later.  Every
  * rule also stops at r == max_rounds (status KNND_WARN_MAX_ROUNDS when the
  * rule itself would not have stopped there).
  */

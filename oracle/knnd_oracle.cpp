@@ -363,7 +363,7 @@ int oracle_should_stop(int64_t hits_prev, int64_t hits_cur, int64_t updates, int
 }
 
 // The other terminations the paper names among K-NN descent implementations
-// (Section 2, Table 1 and item (b)):
+// (Section 1.2, Table 1, and Section 1.3, item (b)):
 //   rule 1, "no possible update": stop after the first round that changed no
 //           list (a fixed point of the round map);
 //   rule 2, the delta-proportion rule of Dong et al.: stop after the first

@@ -331,8 +331,8 @@ int get_graph(Ctx& c, int32_t* idx, double* kl, int32_t on_device) {
   return KNND_OK;
 }
 
-// Stop test after round r of an instance with n points (Section 2, Table 1
-// and item (b)); *capped tells whether only the round cap stopped it.
+// Stop test after round r of an instance with n points (Section 1.2, Table 1,
+// and Section 1.3, item (b)); *capped tells whether only the round cap stopped it.
 bool should_stop(const knnd_params& p, int64_t n, int K, int64_t hits_prev, int64_t hits, int64_t updates,
                  int r, bool* capped) {
   bool rule;

@@ -9,10 +9,11 @@ Inputs are synthetic Dirichlet(1,...,1) points (the paper's workload), FP32
 storage, generated with fixed seeds; the paper's random draws are not
 reproducible, so its rounds, FCC and accuracy are context, not targets.
 
-`--table stop` runs the other terminations of Section 2 (Table 1, item (b))
-on the n = 1e6, 21-coordinate, K = 30 workload: the statistical FCR test,
-Dong et al.'s delta-proportion rule at two deltas, and the fixed point, each
-with its rounds, time to graph, evaluations and accuracy.
+`--table stop` runs the other terminations of Section 1.2 (Table 1) and
+Section 1.3 (item (b)) on the n = 1e6, 21-coordinate, K = 30 workload: the
+statistical FCR test, Dong et al.'s delta-proportion rule at two deltas, and
+the fixed point, each with its rounds, time to graph, evaluations and
+accuracy.
 
     python -m paper_2202_00517_amd.paper_tables [--table 3|4|stop|all] [--json out.json]
 """

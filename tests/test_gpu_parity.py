@@ -502,7 +502,7 @@ def test_batched_mix_vs_oracle(prec):
         _compare_instance(g, P, d, K, s, f"instance n={P.shape[0]} d={d} K={K}")
 
 
-# Other stop rules (Section 2, Table 1 and item (b)): same rounds, another
+# Other stop rules (Section 1.2, Table 1, and Section 1.3, item (b)): same rounds, another
 # stopping round; each instance stops on its own n.
 @pytest.mark.parametrize("rule,delta", [(knnd.KNND_STOP_FIXED_POINT, 0.0), (knnd.KNND_STOP_DELTA, 0.002)],
                          ids=["fixed_point", "delta"])

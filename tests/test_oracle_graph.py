@@ -243,7 +243,7 @@ def test_paper_table3_first_row_statistics():
 
 
 # ---------------------------------------------------------------------------
-# Other terminations (Section 2, Table 1 and item (b)): "no possible update"
+# Other terminations (Section 1.2, Table 1, and Section 1.3, item (b)): "no possible update"
 # and Dong et al.'s delta-proportion rule.  All rules follow one trajectory
 # and differ only in the round they stop at.
 # ---------------------------------------------------------------------------
