@@ -15,6 +15,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, WARN_MAX_ROUNDS, ERR_ARG, ERR_DOMAIN = 0, 1, -1, -2
+# comparators: D(x||y) (the paper's), D(y||x), sum (sqrt x - sqrt y)^2, sum (x - y)^2
+CMP_KL, CMP_KL_REVERSE, CMP_HELLINGER, CMP_L2 = 0, 1, 2, 3
 
 
 def build():
@@ -40,18 +42,18 @@ def _load():
         "oracle_hash": (u64, [u64, u64, u64, u64]),
         "oracle_bound": (u64, [u64, u64]),
         "oracle_log_table": (None, [vp, i64, vp, c_int]),
-        "oracle_key": (ctypes.c_double, [vp, vp, c_int, i64, i64]),
-        "oracle_initial_graph": (c_int, [vp, vp, i64, c_int, c_int, u64, vp, vp, c_int]),
+        "oracle_key": (ctypes.c_double, [vp, vp, c_int, i64, i64, c_int]),
+        "oracle_initial_graph": (c_int, [vp, vp, i64, c_int, c_int, u64, vp, vp, c_int, c_int]),
         "oracle_fcr": (i64, [vp, i64, c_int, u64, i64, i64]),
         "oracle_fcr_exhaustive": (None, [vp, i64, c_int, vp, vp]),
         "oracle_candidates": (i64, [vp, i64, c_int, i64, vp, i64]),
-        "oracle_round": (c_int, [vp, vp, i64, c_int, c_int, vp, vp, vp, vp, vp, vp, c_int]),
+        "oracle_round": (c_int, [vp, vp, i64, c_int, c_int, vp, vp, vp, vp, vp, vp, c_int, c_int]),
         "oracle_round_subset": (c_int, [vp, vp, i64, c_int, c_int, vp, vp, vp, i64, vp, vp,
-                                        vp, vp, c_int]),
-        "oracle_bruteforce": (c_int, [vp, vp, i64, c_int, c_int, vp, i64, vp, vp, c_int]),
+                                        vp, vp, c_int, c_int]),
+        "oracle_bruteforce": (c_int, [vp, vp, i64, c_int, c_int, vp, i64, vp, vp, c_int, c_int]),
         "oracle_should_stop": (c_int, [i64, i64, i64, c_int, c_int]),
         "oracle_build": (c_int, [vp, c_int, i64, c_int, c_int, u64, i64, c_int, c_int, vp, vp,
-                                 vp, vp, vp, vp, vp, c_int, ctypes.c_double]),
+                                 vp, vp, vp, vp, vp, c_int, ctypes.c_double, c_int]),
         "oracle_stop_rule": (c_int, [c_int, ctypes.c_double, i64, c_int, i64, i64, i64, c_int, c_int, vp]),
     }
     for name, (res, args) in sig.items():
@@ -90,15 +92,16 @@ def log_table(P64, threads=0):
     return L
 
 
-def key(P64, L, x, y):
-    return float(_load().oracle_key(_p(P64), _p(L), P64.shape[1], x, y))
+def key(P64, L, x, y, cmp=CMP_KL):
+    return float(_load().oracle_key(_p(P64), _p(L), P64.shape[1], x, y, cmp))
 
 
-def initial_graph(P64, L, K, seed, threads=0):
+def initial_graph(P64, L, K, seed, threads=0, cmp=CMP_KL):
     n, D = P64.shape
     F = np.empty((n, K), dtype=np.int32)
     keys = np.empty((n, K), dtype=np.float64)
-    rc = _load().oracle_initial_graph(_p(P64), _p(L), n, D, K, seed, _p(F), _p(keys), threads)
+    rc = _load().oracle_initial_graph(_p(P64), _p(L), n, D, K, seed, _p(F), _p(keys), threads,
+                                      cmp)
     if rc != OK:
         raise ValueError(f"oracle_initial_graph status {rc}")
     return F, keys
@@ -128,7 +131,7 @@ def candidates(F, x):
     return out[:m].copy()
 
 
-def round_step(P64, L, F, keys, threads=0):
+def round_step(P64, L, F, keys, threads=0, cmp=CMP_KL):
     """One synchronous round; returns (F_next, keys_next, updates, evals)."""
     n, D = P64.shape
     K = F.shape[1]
@@ -138,12 +141,14 @@ def round_step(P64, L, F, keys, threads=0):
     kn = np.empty_like(keys)
     u = np.zeros(1, dtype=np.int64)
     e = np.zeros(1, dtype=np.int64)
-    _load().oracle_round(_p(P64), _p(L), n, D, K, _p(F), _p(keys), _p(Fn), _p(kn), _p(u), _p(e),
-                         threads)
+    rc = _load().oracle_round(_p(P64), _p(L), n, D, K, _p(F), _p(keys), _p(Fn), _p(kn), _p(u),
+                              _p(e), threads, cmp)
+    if rc != OK:
+        raise ValueError(f"oracle_round status {rc}")
     return Fn, kn, int(u[0]), int(e[0])
 
 
-def round_subset(P64, L, F, keys, xs, threads=0):
+def round_subset(P64, L, F, keys, xs, threads=0, cmp=CMP_KL):
     """The round's update for vertices xs only: (F rows, key rows, updates, evals)."""
     n, D = P64.shape
     K = F.shape[1]
@@ -155,17 +160,17 @@ def round_subset(P64, L, F, keys, xs, threads=0):
     ev = np.empty(m, dtype=np.int64)
     _load().oracle_round_subset(_p(P64), _p(L), n, D, K, _p(np.ascontiguousarray(F, np.int32)),
                                 _p(np.ascontiguousarray(keys, np.float64)), _p(xs), m, _p(Fo),
-                                _p(ko), _p(up), _p(ev), threads)
+                                _p(ko), _p(up), _p(ev), threads, cmp)
     return Fo, ko, up, ev
 
 
-def bruteforce(P64, L, K, qs, threads=0):
+def bruteforce(P64, L, K, qs, threads=0, cmp=CMP_KL):
     n, D = P64.shape
     qs = np.ascontiguousarray(qs, dtype=np.int64)
     out = np.empty((qs.size, K), dtype=np.int32)
     keys = np.empty((qs.size, K), dtype=np.float64)
     rc = _load().oracle_bruteforce(_p(P64), _p(L), n, D, K, _p(qs), qs.size, _p(out), _p(keys),
-                                   threads)
+                                   threads, cmp)
     if rc != OK:
         raise ValueError(f"oracle_bruteforce status {rc}")
     return out, keys
@@ -195,7 +200,8 @@ class Result:
         self.rounds, self.seconds = rounds, seconds
 
 
-def build_graph(points, d, K, seed, M=0, max_rounds=100, threads=0, stop_rule=0, delta=0.0):
+def build_graph(points, d, K, seed, M=0, max_rounds=100, threads=0, stop_rule=0, delta=0.0,
+                cmp=CMP_KL):
     """Run the whole descent on points [n][d+1] (FP32 or FP64)."""
     points = np.ascontiguousarray(points)
     if points.dtype == np.float32:
@@ -215,6 +221,6 @@ def build_graph(points, d, K, seed, M=0, max_rounds=100, threads=0, stop_rule=0,
     rounds = ctypes.c_int32(0)
     st = _load().oracle_build(_p(points), dtype, n, d, K, seed, M, max_rounds, threads, _p(idx),
                               _p(keys), _p(upd), _p(hits), _p(evals), ctypes.byref(rounds),
-                              _p(secs), stop_rule, delta)
+                              _p(secs), stop_rule, delta, cmp)
     r = rounds.value
     return Result(st, idx, keys, upd[:r + 1], hits[:r + 1], evals[:r + 1], r, secs[:r + 1])

@@ -1,5 +1,5 @@
 // CPU oracle for comparator-based K-nearest-neighbor descent (NND) with the
-// Kullback-Leibler comparator.
+// Kullback-Leibler comparator and a small family of other comparators.
 //
 // TEST INFRASTRUCTURE ONLY.  This file defines what the GPU library must
 // compute, in plain, slow, obviously-correct C++ (FP64, correctly rounded log,
@@ -14,7 +14,9 @@
 // Pins (what ties this code to the paper rather than to itself) live in
 // tests/test_oracle_*.py: closed-form KL values, the published SplitMix64 test
 // vector, brute-force exact K-NN on tiny inputs, a matrix-algebra formulation
-// of the candidate set, exhaustive friend-clustering rates, and invariants.
+// of the candidate set, exhaustive friend-clustering rates, and invariants;
+// for the other comparators, closed forms, exact symmetry, acyclic ranking
+// digraphs of the metric ones (Section 2.1's theorem) and k-d tree searches.
 // Parity unpinned: the round counts, FCR values and update counts at the
 // benchmark sizes have no printed value in the paper; only GPU-vs-oracle
 // parity and the paper's soft round bound apply there.
@@ -102,6 +104,46 @@ double kl_key(const double* P, const double* L, int D, int64_t x, int64_t y) {
   return acc;
 }
 
+// Other comparators.  The method only needs, for each x, a total order on the
+// other points (Section 2.1: a ranking system, one Comparator per x; Section
+// 1.3 (a)); these keys give such orders, each with the same (key, index)
+// tie rule and the same fixed rounding (ascending fold, one fma per term):
+//   CMP_KL          D(x||y) as above;
+//   CMP_KL_REVERSE  D(y||x) = sum_i y_i (log y_i - log x_i): KL with the roles
+//                   of the two points exchanged (still asymmetric);
+//   CMP_HELLINGER   sum_i (sqrt x_i - sqrt y_i)^2, twice the squared Hellinger
+//                   distance between the two distributions (a metric after
+//                   the square root, so it induces a metric ranking system);
+//   CMP_L2          sum_i (x_i - y_i)^2, the squared Euclidean distance.
+// Square roots are IEEE (correctly rounded) FP64 square roots of the widened
+// coordinates, taken here per pair.
+enum { CMP_KL = 0, CMP_KL_REVERSE = 1, CMP_HELLINGER = 2, CMP_L2 = 3 };
+
+double cmp_key(int cmp, const double* P, const double* L, int D, int64_t x, int64_t y) {
+  const double* px = P + (size_t)x * D;
+  const double* py = P + (size_t)y * D;
+  double acc = 0.0;
+  if (cmp == CMP_KL) return kl_key(P, L, D, x, y);
+  if (cmp == CMP_KL_REVERSE) {
+    const double* lx = L + (size_t)x * D;
+    const double* ly = L + (size_t)y * D;
+    for (int i = 0; i < D; ++i) acc = std::fma(py[i], ly[i] - lx[i], acc);
+  } else if (cmp == CMP_HELLINGER) {
+    for (int i = 0; i < D; ++i) {
+      const double t = std::sqrt(px[i]) - std::sqrt(py[i]);
+      acc = std::fma(t, t, acc);
+    }
+  } else {
+    for (int i = 0; i < D; ++i) {
+      const double t = px[i] - py[i];
+      acc = std::fma(t, t, acc);
+    }
+  }
+  return acc;
+}
+
+bool cmp_valid(int cmp) { return cmp >= CMP_KL && cmp <= CMP_L2; }
+
 using Entry = std::pair<double, int32_t>;  // (key, index): lexicographic order
 
 // Reverse neighbors (Section 4.2: the co-friend map is derived from the friend
@@ -153,7 +195,7 @@ std::vector<int32_t> candidates(const int32_t* F, int K, const std::vector<int64
 // and the candidates.  Former friends keep their stored keys (they are the
 // same canonical values).  Returns the number of candidate evaluations and
 // writes the number of new entries in the list.
-int64_t update_vertex(const double* P, const double* L, int D, int K, const int32_t* F,
+int64_t update_vertex(int cmp, const double* P, const double* L, int D, int K, const int32_t* F,
                       const double* keys, const std::vector<int64_t>& rowptr,
                       const std::vector<int32_t>& col, int64_t x, int32_t* outF,
                       double* outKeys, int64_t* updates) {
@@ -162,7 +204,7 @@ int64_t update_vertex(const double* P, const double* L, int D, int K, const int3
   pool.reserve(U.size() + K);
   for (int j = 0; j < K; ++j)
     pool.emplace_back(keys[(size_t)x * K + j], F[(size_t)x * K + j]);
-  for (int32_t z : U) pool.emplace_back(kl_key(P, L, D, x, z), z);
+  for (int32_t z : U) pool.emplace_back(cmp_key(cmp, P, L, D, x, z), z);
   std::sort(pool.begin(), pool.end());
   std::vector<int32_t> old(F + (size_t)x * K, F + (size_t)x * K + K);
   std::sort(old.begin(), old.end());
@@ -176,9 +218,15 @@ int64_t update_vertex(const double* P, const double* L, int D, int K, const int3
   return (int64_t)U.size();
 }
 
-bool points_ok(const double* P, size_t count) {
-  for (size_t i = 0; i < count; ++i)
-    if (!(P[i] > 0.0) || !std::isfinite(P[i])) return false;
+// Domain of each comparator: the KL forms need every coordinate finite and
+// > 0 (points of the open simplex), the Hellinger form finite and >= 0, the
+// Euclidean form finite.
+bool points_ok(int cmp, const double* P, size_t count) {
+  for (size_t i = 0; i < count; ++i) {
+    if (!std::isfinite(P[i])) return false;
+    if ((cmp == CMP_KL || cmp == CMP_KL_REVERSE) && !(P[i] > 0.0)) return false;
+    if (cmp == CMP_HELLINGER && !(P[i] >= 0.0)) return false;
+  }
   return true;
 }
 
@@ -200,8 +248,9 @@ void oracle_log_table(const double* P, int64_t count, double* L, int threads) {
   });
 }
 
-double oracle_key(const double* P, const double* L, int D, int64_t x, int64_t y) {
-  return kl_key(P, L, D, x, y);
+double oracle_key(const double* P, const double* L, int D, int64_t x, int64_t y, int cmp) {
+  if (!cmp_valid(cmp)) return std::nan("");
+  return cmp_key(cmp, P, L, D, x, y);
 }
 
 // Random K-out initial graph (Section 3.2; Section 4.2): each x draws points of
@@ -210,8 +259,8 @@ double oracle_key(const double* P, const double* L, int D, int64_t x, int64_t y)
 // ordered on insertion).  Draw a of x is r = bound(hash(seed,1,x,a), n-1),
 // mapped past x as y = r + (r >= x).
 int oracle_initial_graph(const double* P, const double* L, int64_t n, int D, int K,
-                         uint64_t seed, int32_t* F, double* keys, int threads) {
-  if (n < 2 || K < 1 || K > n - 1 || D < 1) return ORC_ERR_ARG;
+                         uint64_t seed, int32_t* F, double* keys, int threads, int cmp) {
+  if (n < 2 || K < 1 || K > n - 1 || D < 1 || !cmp_valid(cmp)) return ORC_ERR_ARG;
   parallel_ranges(n, threads, [&](int64_t lo, int64_t hi, int) {
     std::vector<Entry> row;
     for (int64_t x = lo; x < hi; ++x) {
@@ -223,7 +272,7 @@ int oracle_initial_graph(const double* P, const double* L, int64_t n, int D, int
         for (const Entry& e : row) seen = seen || e.second == (int32_t)y;
         if (!seen) row.emplace_back(0.0, (int32_t)y);
       }
-      for (Entry& e : row) e.first = kl_key(P, L, D, x, e.second);
+      for (Entry& e : row) e.first = cmp_key(cmp, P, L, D, x, e.second);
       std::sort(row.begin(), row.end());
       for (int j = 0; j < K; ++j) {
         F[(size_t)x * K + j] = row[(size_t)j].second;
@@ -290,7 +339,8 @@ int64_t oracle_candidates(const int32_t* F, int64_t n, int K, int64_t x, int32_t
 // the round runs; the outputs become the next snapshot.
 int oracle_round(const double* P, const double* L, int64_t n, int D, int K, const int32_t* F,
                  const double* keys, int32_t* Fn, double* keysn, int64_t* updates,
-                 int64_t* evals, int threads) {
+                 int64_t* evals, int threads, int cmp) {
+  if (!cmp_valid(cmp)) return ORC_ERR_ARG;
   std::vector<int64_t> rowptr;
   std::vector<int32_t> col;
   build_cofriends(F, n, K, rowptr, col);
@@ -299,7 +349,7 @@ int oracle_round(const double* P, const double* L, int64_t n, int D, int K, cons
   parallel_ranges(n, T, [&](int64_t lo, int64_t hi, int t) {
     for (int64_t x = lo; x < hi; ++x) {
       int64_t u = 0;
-      ev[t] += update_vertex(P, L, D, K, F, keys, rowptr, col, x, Fn + (size_t)x * K,
+      ev[t] += update_vertex(cmp, P, L, D, K, F, keys, rowptr, col, x, Fn + (size_t)x * K,
                              keysn + (size_t)x * K, &u);
       upd[t] += u;
     }
@@ -316,13 +366,14 @@ int oracle_round(const double* P, const double* L, int64_t n, int D, int K, cons
 int oracle_round_subset(const double* P, const double* L, int64_t n, int D, int K,
                         const int32_t* F, const double* keys, const int64_t* xs, int64_t m,
                         int32_t* Fout, double* keysout, int64_t* upd, int64_t* evals,
-                        int threads) {
+                        int threads, int cmp) {
+  if (!cmp_valid(cmp)) return ORC_ERR_ARG;
   std::vector<int64_t> rowptr;
   std::vector<int32_t> col;
   build_cofriends(F, n, K, rowptr, col);
   parallel_ranges(m, threads, [&](int64_t lo, int64_t hi, int) {
     for (int64_t i = lo; i < hi; ++i)
-      evals[i] = update_vertex(P, L, D, K, F, keys, rowptr, col, xs[i], Fout + (size_t)i * K,
+      evals[i] = update_vertex(cmp, P, L, D, K, F, keys, rowptr, col, xs[i], Fout + (size_t)i * K,
                                keysout + (size_t)i * K, &upd[i]);
   });
   return ORC_OK;
@@ -331,15 +382,16 @@ int oracle_round_subset(const double* P, const double* L, int64_t n, int D, int 
 // Exact K-NN of the query points qs under the comparator, by sorting all of
 // S \ {q} (Section 2.3: the naive computation).
 int oracle_bruteforce(const double* P, const double* L, int64_t n, int D, int K,
-                      const int64_t* qs, int64_t m, int32_t* out, double* keys, int threads) {
-  if (K > n - 1) return ORC_ERR_ARG;
+                      const int64_t* qs, int64_t m, int32_t* out, double* keys, int threads,
+                      int cmp) {
+  if (K > n - 1 || !cmp_valid(cmp)) return ORC_ERR_ARG;
   parallel_ranges(m, threads, [&](int64_t lo, int64_t hi, int) {
     std::vector<Entry> all;
     for (int64_t i = lo; i < hi; ++i) {
       int64_t q = qs[i];
       all.clear();
       for (int64_t y = 0; y < n; ++y)
-        if (y != q) all.emplace_back(kl_key(P, L, D, q, y), (int32_t)y);
+        if (y != q) all.emplace_back(cmp_key(cmp, P, L, D, q, y), (int32_t)y);
       std::partial_sort(all.begin(), all.begin() + K, all.end());
       for (int j = 0; j < K; ++j) {
         out[(size_t)i * K + j] = all[(size_t)j].second;
@@ -389,18 +441,20 @@ int oracle_stop_rule(int rule, double delta, int64_t n, int K, int64_t hits_prev
 // graph, then synchronous rounds until the stop rule fires.
 //   points: [n][d+1] row-major, FP32 (dtype 0) or FP64 (dtype 1); widened to
 //           FP64 exactly, never renormalised; every coordinate must be finite
-//           and > 0 (the paper's points lie in the open simplex).
+//           and > 0 (the paper's points lie in the open simplex), or for the
+//           other comparators lie in their domain (points_ok).
 //   M <= 0 selects the default sample size min(n, 10000).
 //   Per-round outputs have max_rounds+1 entries; entry 0 is the initial graph.
 // Returns 0, 1 when the round cap stopped the run, or a negative error.
 //   stop_rule / delta: see oracle_stop_rule (0 = the paper's criterion).
+//   cmp: the comparator (CMP_KL is the paper's).
 int oracle_build(const void* points, int dtype, int64_t n, int d, int K, uint64_t seed,
                  int64_t M, int max_rounds, int threads, int32_t* out_idx, double* out_keys,
                  int64_t* out_updates, int64_t* out_hits, int64_t* out_evals,
-                 int32_t* out_rounds, double* out_seconds, int stop_rule, double delta) {
+                 int32_t* out_rounds, double* out_seconds, int stop_rule, double delta, int cmp) {
   if (!points || !out_idx || n < 2 || d < 1 || K < 2 || K > n - 1 || max_rounds < 1 ||
       (dtype != 0 && dtype != 1) || n > ((int64_t)1 << 30) || stop_rule < 0 || stop_rule > 2 ||
-      !(delta >= 0.0) || !std::isfinite(delta))
+      !(delta >= 0.0) || !std::isfinite(delta) || !cmp_valid(cmp))
     return ORC_ERR_ARG;
   const int D = d + 1;
   const size_t cnt = (size_t)n * D;
@@ -412,13 +466,13 @@ int oracle_build(const void* points, int dtype, int64_t n, int d, int K, uint64_
   } else {
     std::memcpy(P.data(), points, cnt * sizeof(double));
   }
-  if (!points_ok(P.data(), cnt)) return ORC_ERR_DOMAIN;
+  if (!points_ok(cmp, P.data(), cnt)) return ORC_ERR_DOMAIN;
   if (M <= 0) M = std::min<int64_t>(n, 10000);
-  oracle_log_table(P.data(), (int64_t)cnt, L.data(), threads);
+  if (cmp == CMP_KL || cmp == CMP_KL_REVERSE) oracle_log_table(P.data(), (int64_t)cnt, L.data(), threads);
 
   std::vector<int32_t> F((size_t)n * K), Fn((size_t)n * K);
   std::vector<double> keys((size_t)n * K), keysn((size_t)n * K);
-  oracle_initial_graph(P.data(), L.data(), n, D, K, seed, F.data(), keys.data(), threads);
+  oracle_initial_graph(P.data(), L.data(), n, D, K, seed, F.data(), keys.data(), threads, cmp);
   int64_t hits_prev = oracle_fcr(F.data(), n, K, seed, 0, M);
   auto secs = [](std::chrono::steady_clock::time_point a) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
@@ -435,7 +489,7 @@ int oracle_build(const void* points, int dtype, int64_t n, int d, int K, uint64_
     auto tr = std::chrono::steady_clock::now();
     int64_t upd = 0, ev = 0;
     oracle_round(P.data(), L.data(), n, D, K, F.data(), keys.data(), Fn.data(), keysn.data(),
-                 &upd, &ev, threads);
+                 &upd, &ev, threads, cmp);
     F.swap(Fn);
     keys.swap(keysn);
     int64_t hits = oracle_fcr(F.data(), n, K, seed, r, M);
