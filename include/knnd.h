@@ -9,6 +9,9 @@
  *   - Comparator (Section 2.2; Section 4 scaling experiment): y ranks before z
  *     for x when D(x||y) < D(x||z), D(x||y) = sum_i x_i log(x_i / y_i),
  *     summed over all d+1 stored coordinates.  Asymmetric, not a metric.
+ *     The descent needs only one total order per point (Section 2.1, a
+ *     ranking system; Section 1.3 (a)): knnd_comparator lists the others
+ *     this library offers.
  *   - Descent (Section 3.1): rounds of friend-of-a-friend candidate generation
  *     ("Meet": co-friends, friends of friends, friends of co-friends) and
  *     best-K selection ("Update"), each round computed from the round-start
@@ -35,8 +38,8 @@
  *   H          : SplitMix64-finalizer hash
  *                H(s,t,a,b) = mix64(mix64(mix64(s ^ t*0x9E3779B97F4A7C15) ^ a) ^ b).
  * Results depend only on (points, K, seed, fcr_samples, max_rounds, the stop
- * rule and its delta): not on
- * the precision mode, on tiling or on scheduling.
+ * rule and its delta, the comparator): not on the precision mode, on tiling
+ * or on scheduling.
  *
  * Threading: calls on distinct contexts/outputs may run concurrently.
  * Nothing is retained between calls except inside a knnd_ctx.  No C++
@@ -51,7 +54,7 @@
 extern "C" {
 #endif
 
-#define KNND_ABI_VERSION 3
+#define KNND_ABI_VERSION 4
 
 typedef enum {
     KNND_OK = 0,
@@ -92,6 +95,31 @@ typedef enum {
                                    (same result) */
 
 /*
+ * Comparators (Section 2.1: any family of per-point total orders; Section 1.3
+ * (a)).  Each ranks y before z for x by a key k(x, y), folded in FP64 over
+ * the d+1 coordinates in ascending order from +0.0 with one fma per term, ties
+ * to the lower index:
+ *   KNND_CMP_KL          D(x||y): acc = fma(x_i, log x_i - log y_i, acc) (the
+ *                        paper's; coordinates finite and > 0)
+ *   KNND_CMP_KL_REVERSE  D(y||x): acc = fma(y_i, log y_i - log x_i, acc)
+ *                        (coordinates finite and > 0)
+ *   KNND_CMP_HELLINGER   t = sqrt(x_i) - sqrt(y_i), acc = fma(t, t, acc): twice
+ *                        the squared Hellinger distance (coordinates finite
+ *                        and >= 0; IEEE square roots)
+ *   KNND_CMP_L2          t = x_i - y_i, acc = fma(t, t, acc): the squared
+ *                        Euclidean distance (coordinates finite)
+ * The logs are the correctly rounded FP64 logs of the coordinates, as above.
+ * The mixed precision modes apply to KNND_CMP_KL only; with another
+ * comparator every key is computed in FP64 (same results).
+ */
+typedef enum {
+    KNND_CMP_KL = 0,
+    KNND_CMP_KL_REVERSE = 1,
+    KNND_CMP_HELLINGER = 2,
+    KNND_CMP_L2 = 3
+} knnd_comparator;
+
+/*
  * Termination (Section 1.2, Table 1, and Section 1.3, item (b)).  Every
  * rule runs the same rounds and differs only in the round after which it
  * stops, so a run under one rule is a prefix of the run under any rule that
@@ -119,7 +147,7 @@ typedef struct {
     int32_t max_rounds;         /* <= 0 selects 100 */
     int32_t flags;              /* KNND_FLAG_* */
     int32_t stop_rule;          /* knnd_stop_rule */
-    int32_t reserved;           /* must be 0 */
+    int32_t comparator;         /* knnd_comparator */
     double delta;               /* KNND_STOP_DELTA only: finite, >= 0 */
 } knnd_params;
 
@@ -140,7 +168,7 @@ typedef struct {
 } knnd_round_stats;
 
 /* Fill *p with the defaults (FP64, F32 points, M = min(n,10000), 100 rounds,
-   KNND_STOP_FCR, delta 0, flags 0). */
+   KNND_STOP_FCR, delta 0, KNND_CMP_KL, flags 0). */
 void knnd_default_params(knnd_params* p);
 
 /* Human-readable name of a knnd_status value (static storage). */
@@ -223,10 +251,12 @@ int knnd_build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int
  * Exact K nearest neighbours of query points by exhaustive comparison (the
  * problem of Section 2.3 solved directly; the accuracy measure of Section 4.3
  * compares a descent's lists with these).  For query point q every other
- * point p is ranked by the same canonical key D(q||p) and (key, index) order
- * as the descent.
+ * point p is ranked by the same canonical key k(q, p) of the comparator
+ * (knnd_comparator; KNND_CMP_KL: D(q||p)) and (key, index) order as the
+ * descent.
  *   points   [n][d+1] of dtype (knnd_dtype), host or device memory per
- *            on_device; every coordinate finite and > 0; d+1 <= 256
+ *            on_device; every coordinate in the comparator's domain;
+ *            d+1 <= 256
  *   queries  [nq] int32 point indices (same memory kind), each in [0, n)
  *   tau      optional [nq] FP64 (same kind): an upper bound on each query's
  *            K-th smallest key, e.g. the K-th key of a descent's list for that
@@ -235,11 +265,12 @@ int knnd_build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int
  *   out_kl   optional [nq][K] FP64 keys (same kind)
  * Device scratch: about 49 KB per query.  Returns KNND_ERR_ARG for bad sizes,
  * a query index out of range or a tau below the K-th key,
- * KNND_ERR_UNSUPPORTED for d+1 > 256, KNND_ERR_DOMAIN for bad coordinates.
+ * an unknown comparator, KNND_ERR_UNSUPPORTED for d+1 > 256,
+ * KNND_ERR_DOMAIN for bad coordinates.
  */
 int knnd_exact_knn(const void* points, int64_t n, int32_t d, int32_t K, int32_t dtype,
-                   const int32_t* queries, int64_t nq, const double* tau, int32_t on_device,
-                   void* stream, int32_t* out_idx, double* out_kl);
+                   int32_t comparator, const int32_t* queries, int64_t nq, const double* tau,
+                   int32_t on_device, void* stream, int32_t* out_idx, double* out_kl);
 
 /*
  * Step-by-step interface (the same path, one call per step).  A context owns
@@ -248,7 +279,8 @@ int knnd_exact_knn(const void* points, int64_t n, int32_t d, int32_t K, int32_t 
  */
 typedef struct knnd_ctx knnd_ctx;
 
-/* Validate and upload points, build the log table.  points: [n][d+1] of kind. */
+/* Validate and upload points, build the comparator's feature table (the log
+   table for the KL comparators).  points: [n][d+1] of kind. */
 int knnd_ctx_create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed,
                     const knnd_params* p, int32_t on_device, void* stream, knnd_ctx** out);
 
@@ -269,7 +301,8 @@ int knnd_ctx_round(knnd_ctx* c, knnd_round_stats* st);
 /* Copy the current lists out: idx [n][K] int32, kl optional [n][K] FP64 (kind). */
 int knnd_ctx_get_graph(knnd_ctx* c, int32_t* idx, double* kl, int32_t on_device);
 
-/* Copy the log table out: L [n][d+1] FP64 (kind). */
+/* Copy the feature table out: L [n][d+1] FP64 (kind): log x for the KL
+   comparators, sqrt x for Hellinger, x for Euclidean. */
 int knnd_ctx_get_log_table(knnd_ctx* c, double* L, int32_t on_device);
 
 /* Rounds completed so far. */

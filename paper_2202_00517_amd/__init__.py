@@ -27,6 +27,7 @@ KNND_PREC_FP64, KNND_PREC_MIXED_BF16, KNND_PREC_MIXED_FP16 = 0, 1, 2
 KNND_FLAG_NO_SKIP = 0x1
 KNND_FLAG_PULL = 0x2
 KNND_STOP_FCR, KNND_STOP_FIXED_POINT, KNND_STOP_DELTA = 0, 1, 2
+KNND_CMP_KL, KNND_CMP_KL_REVERSE, KNND_CMP_HELLINGER, KNND_CMP_L2 = 0, 1, 2, 3
 
 EXPORTED = [
     "knnd_default_params", "knnd_status_string", "knnd_abi_version", "knnd_build",
@@ -36,14 +37,14 @@ EXPORTED = [
 ]
 
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class knnd_params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("fcr_samples", ctypes.c_int64), ("max_rounds", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("stop_rule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("delta", ctypes.c_double)]
+                ("comparator", ctypes.c_int32), ("delta", ctypes.c_double)]
 
 
 class knnd_round_stats(ctypes.Structure):
@@ -103,7 +104,7 @@ def lib():
         "knnd_ctx_rounds": (ctypes.c_int, [vp]),
         "knnd_ctx_destroy": (ctypes.c_int, [vp]),
         "knnd_build_batched": (ctypes.c_int, [P(knnd_instance), i32, P(knnd_params), i32, vp]),
-        "knnd_exact_knn": (ctypes.c_int, [vp, i64, i32, i32, i32, vp, i64, vp, i32, vp, vp, vp]),
+        "knnd_exact_knn": (ctypes.c_int, [vp, i64, i32, i32, i32, i32, vp, i64, vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -254,11 +255,11 @@ def knnd_build_batched(instances, params=None, stream=None, with_kl=True):
     return st, out
 
 
-def knnd_exact_knn(points, d, K, queries, tau=None, stream=None, with_kl=True):
+def knnd_exact_knn(points, d, K, queries, tau=None, stream=None, with_kl=True, comparator=KNND_CMP_KL):
     """Exact K nearest neighbours of the points listed in `queries` (int32
-    indices), by exhaustive comparison.  points/queries/tau: numpy host
-    arrays or torch device tensors (all on the same side); outputs on that
-    side.  Returns (idx [nq][K], kl [nq][K] or None)."""
+    indices), by exhaustive comparison under `comparator`.  points/queries/
+    tau: numpy host arrays or torch device tensors (all on the same side);
+    outputs on that side.  Returns (idx [nq][K], kl [nq][K] or None)."""
     points = _check_points(points, d)
     n = points.shape[0]
     dev = 1 if _is_device(points) else 0
@@ -274,8 +275,8 @@ def knnd_exact_knn(points, d, K, queries, tau=None, stream=None, with_kl=True):
     nq = queries.shape[0]
     idx = _empty(points, (nq, K), np.int32)
     kl = _empty(points, (nq, K), np.float64) if with_kl else None
-    st = lib().knnd_exact_knn(_ptr(points), n, d, K, _dtype_code(points), _ptr(queries), nq, _ptr(tau),
-                              dev, _stream_of(points, stream), _ptr(idx), _ptr(kl))
+    st = lib().knnd_exact_knn(_ptr(points), n, d, K, _dtype_code(points), comparator, _ptr(queries), nq,
+                              _ptr(tau), dev, _stream_of(points, stream), _ptr(idx), _ptr(kl))
     if st < 0:
         raise KnndError(st, "knnd_exact_knn")
     return idx, kl

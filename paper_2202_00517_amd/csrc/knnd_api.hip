@@ -70,7 +70,8 @@ int resolve_params(const knnd_params* p, int64_t n, knnd_params* out) {
   if (out->max_rounds <= 0) out->max_rounds = 100;
   if (out->dtype != KNND_F32 && out->dtype != KNND_F64) return KNND_ERR_ARG;
   if (out->precision < KNND_PREC_FP64 || out->precision > KNND_PREC_MIXED_FP16) return KNND_ERR_ARG;
-  if (out->stop_rule < KNND_STOP_FCR || out->stop_rule > KNND_STOP_DELTA || out->reserved != 0) return KNND_ERR_ARG;
+  if (out->stop_rule < KNND_STOP_FCR || out->stop_rule > KNND_STOP_DELTA) return KNND_ERR_ARG;
+  if (out->comparator < KNND_CMP_KL || out->comparator > KNND_CMP_L2) return KNND_ERR_ARG;
   if (!(out->delta >= 0.0) || !std::isfinite(out->delta)) return KNND_ERR_ARG;
   return KNND_OK;
 }
@@ -104,6 +105,9 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   c.dtype = prm.dtype;
   c.precision = prm.precision;
   c.flags = prm.flags;
+  c.cmp = prm.comparator;
+  c.ck = knnd::cmp_fold_kind(c.cmp);
+  c.tk = knnd::cmp_table_kind(c.cmp);
   c.M = prm.fcr_samples;
   c.max_rounds = prm.max_rounds;
 
@@ -144,9 +148,10 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   if (e != hipSuccess) return map_err(e);
   // Hub form: candidate rows of a hub must fit in LDS, and the key slots
   // (K(2K+1) per point) must fit in memory; otherwise the pull form.  The
-  // mixed-precision form needs the hub form and D <= 64 (MFMA K dimension).
+  // mixed-precision form needs the hub form, D <= 64 (MFMA K dimension) and
+  // the KL comparator (its error bound is derived for that key).
   c.use_hub = !(c.flags & KNND_FLAG_PULL) && (size_t)(K + 1) * c.Ds * sizeof(double) <= 64 * 1024;
-  c.mixed = c.use_hub && c.precision != KNND_PREC_FP64 && c.D <= 64;
+  c.mixed = c.use_hub && c.precision != KNND_PREC_FP64 && c.D <= 64 && c.cmp == KNND_CMP_KL;
   if (c.mixed) {
     c.dk = c.D <= 32 ? 32 : 64;
     // rows of 2 dk 16-bit values: dk high parts, then dk low parts
@@ -615,7 +620,7 @@ void knnd_default_params(knnd_params* p) {
   p->max_rounds = 100;
   p->flags = 0;
   p->stop_rule = KNND_STOP_FCR;
-  p->reserved = 0;
+  p->comparator = KNND_CMP_KL;
   p->delta = 0.0;
 }
 

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "knnd_internal.h"
+
 namespace knnd {
 
 constexpr int WAVE = 64;
@@ -124,19 +126,47 @@ __device__ inline double crlog(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// Canonical key: acc = fma(x_i, Lx_i - Lz_i, acc), i ascending, from +0.0.
+// Comparator kinds of the key fold (each point has its own order on the
+// others, Section 2.1).  L is the comparator's feature table: log x for the
+// two KL kinds, sqrt x for the Hellinger comparator, x itself for the
+// Euclidean one.  With x the receiver (first argument) and z the candidate:
+//   CK_KL   acc = fma(x_i, Lx_i - Lz_i, acc)    D(x||z)
+//   CK_REV  acc = fma(z_i, Lz_i - Lx_i, acc)    D(z||x)
+//   CK_SQ   t = Lx_i - Lz_i; acc = fma(t, t, acc)   squared distance of the features
+// i ascending, from +0.0.
+// ---------------------------------------------------------------------------
+// (CK_* and the table kinds TK_* are declared in knnd_internal.h)
+
+// One term; w is the weighing coordinate (x_i for CK_KL, z_i for CK_REV,
+// unused for CK_SQ).
+template <int CK>
+__device__ __forceinline__ double key_term(double w, double lx, double lz, double acc) {
+  if constexpr (CK == CK_KL) {
+    return fma(w, lx - lz, acc);
+  } else if constexpr (CK == CK_REV) {
+    return fma(w, lz - lx, acc);
+  } else {
+    const double t = lx - lz;
+    return fma(t, t, acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Canonical key of comparator kind CK (CK_KL: acc = fma(x_i, Lx_i - Lz_i,
+// acc), i ascending, from +0.0).
 // Adding +0.0 at the end turns a -0.0 into +0.0 so that the bit order below
 // agrees with FP64 comparison.
 // The rows are read in chunks of 8 coordinates, the next chunk requested
 // before the current one is used, every read unconditional (so that no read
 // waits for the one before it).  Reads reach element D + 22 of each row: the
 // arrays must stay readable that far past their last row (P and L carry 64
-// elements of tail padding).  lx and lz must be 16-byte aligned.
+// elements of tail padding).  lx and lz must be 16-byte aligned.  pw is the
+// weighing point row (x's for CK_KL, z's for CK_REV; not read for CK_SQ).
 // ---------------------------------------------------------------------------
-template <typename PT>
+template <typename PT, int CK = CK_KL>
 struct KeyChunk {
-  double x[8], l[8], z[8];
-  __device__ __forceinline__ void load(const PT* __restrict__ px, const double* __restrict__ lx,
+  double w[8], l[8], z[8];
+  __device__ __forceinline__ void load(const PT* __restrict__ pw, const double* __restrict__ lx,
                                        const double* __restrict__ lz, int c0) {
     const double2* lx2 = reinterpret_cast<const double2*>(lx + c0);
     const double2* lz2 = reinterpret_cast<const double2*>(lz + c0);
@@ -148,31 +178,45 @@ struct KeyChunk {
       z[2 * j] = b.x;
       z[2 * j + 1] = b.y;
     }
+    if constexpr (CK != CK_SQ) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = (double)px[c0 + j];
+      for (int j = 0; j < 8; ++j) w[j] = (double)pw[c0 + j];
+    }
   }
   __device__ __forceinline__ double fold(double acc, int c0, int D) const {
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      if (c0 + j < D) acc = fma(x[j], l[j] - z[j], acc);
+      if (c0 + j < D) acc = key_term<CK>(w[j], l[j], z[j], acc);
     return acc;
   }
 };
 
-template <typename PT>
-__device__ __forceinline__ double canonical_key(const PT* __restrict__ px,
+template <typename PT, int CK = CK_KL>
+__device__ __forceinline__ double canonical_key(const PT* __restrict__ pw,
                                                 const double* __restrict__ lx,
                                                 const double* __restrict__ lz, int D) {
   double acc = 0.0;
-  KeyChunk<PT> a, b;
-  a.load(px, lx, lz, 0);
+  KeyChunk<PT, CK> a, b;
+  a.load(pw, lx, lz, 0);
   for (int c0 = 0; c0 < D; c0 += 16) {
-    b.load(px, lx, lz, c0 + 8);
+    b.load(pw, lx, lz, c0 + 8);
     acc = a.fold(acc, c0, D);
-    a.load(px, lx, lz, c0 + 16);
+    a.load(pw, lx, lz, c0 + 16);
     acc = b.fold(acc, c0 + 8, D);
   }
   return acc + 0.0;
+}
+
+// Key of x against z for a comparator kind known only at run time (uniform
+// across the wave): rows of P [n][D] and of the feature table L [n][Dp].
+template <typename PT>
+__device__ __forceinline__ double key_of_kind(int ck, const PT* __restrict__ P, int64_t x, int64_t z,
+                                              const double* __restrict__ L, int D, int Dp) {
+  const double* lx = L + x * Dp;
+  const double* lz = L + z * Dp;
+  if (ck == CK_REV) return canonical_key<PT, CK_REV>(P + z * D, lx, lz, D);
+  if (ck == CK_SQ) return canonical_key<PT, CK_SQ>(P + x * D, lx, lz, D);
+  return canonical_key<PT, CK_KL>(P + x * D, lx, lz, D);
 }
 
 // The same key with x's row (as FP64) and its logs staged in LDS: sx and sl

@@ -2,9 +2,9 @@
 // problem statement itself (Section 2.3), used to measure the descent's
 // accuracy (Section 4.3: the share of true nearest neighbours found).
 //
-// For each query q every other point p gets its canonical key D(q||p) (the
-// same FP64 fold as the descent) and the K smallest (key, index) pairs are
-// returned in order.  Three kernels:
+// For each query q every other point p gets its canonical key k(q, p) under
+// the comparator (the same FP64 fold as the descent; D(q||p) for KL) and the
+// K smallest (key, index) pairs are returned in order.  Three kernels:
 //   bound    (when the caller gives no bound) each thread keeps the best
 //            pair of its share of the points; the K-th smallest of those
 //            minima is a pair that K distinct points reach, so it bounds the
@@ -57,15 +57,17 @@ __device__ void stage_queries(const PT* P, const double* L, int D, int Dp, const
   __syncthreads();
 }
 
-// Keys of point p for the XQ staged queries: acc_j = fold_i fma(x_j,i, l_j,i - L_p,i).
-// The point's log row is read 8 coordinates at a time (rows stay inside the
-// table's tail padding).
-__device__ __forceinline__ void point_keys(const double* __restrict__ lp, int D, const double (*sx)[XROW],
-                                           const double (*sl)[XROW], double (&acc)[XQ]) {
+// Keys of point p for the XQ staged queries, fold kind CK (CK_KL:
+// acc_j = fold_i fma(x_j,i, l_j,i - L_p,i)).  The point's feature row lp (and
+// for CK_REV its point row pp) is read 8 coordinates at a time (rows stay
+// inside the arrays' tail padding).
+template <int CK, typename PT>
+__device__ __forceinline__ void point_keys(const double* __restrict__ lp, const PT* __restrict__ pp, int D,
+                                           const double (*sx)[XROW], const double (*sl)[XROW], double (&acc)[XQ]) {
 #pragma unroll
   for (int j = 0; j < XQ; ++j) acc[j] = 0.0;
   for (int c0 = 0; c0 < D; c0 += 8) {
-    double z[8];
+    double z[8], w[8];
     const double2* l2 = reinterpret_cast<const double2*>(lp + c0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -73,11 +75,20 @@ __device__ __forceinline__ void point_keys(const double* __restrict__ lp, int D,
       z[2 * k] = v.x;
       z[2 * k + 1] = v.y;
     }
+    if constexpr (CK == CK_REV) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = (double)pp[c0 + k];
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (c0 + k < D) {
 #pragma unroll
-        for (int j = 0; j < XQ; ++j) acc[j] = fma(sx[j][c0 + k], sl[j][c0 + k] - z[k], acc[j]);
+        for (int j = 0; j < XQ; ++j) {
+          if constexpr (CK == CK_KL)
+            acc[j] = key_term<CK>(sx[j][c0 + k], sl[j][c0 + k], z[k], acc[j]);
+          else
+            acc[j] = key_term<CK>(w[k], sl[j][c0 + k], z[k], acc[j]);
+        }
       }
     }
   }
@@ -103,7 +114,7 @@ __device__ void block_smallest(uint64_t k, uint32_t id, uint64_t (*sk)[WAVE], ui
   __syncthreads();
 }
 
-template <typename PT>
+template <typename PT, int CK>
 __global__ __launch_bounds__(256) void k_exact_bound(const PT* __restrict__ P, const double* __restrict__ L,
                                                      int64_t n, int D, int Dp, int K,
                                                      const int32_t* __restrict__ queries, int64_t nq,
@@ -123,7 +134,7 @@ __global__ __launch_bounds__(256) void k_exact_bound(const PT* __restrict__ P, c
   }
   for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
     double acc[XQ];
-    point_keys(L + p * Dp, D, sx, sl, acc);
+    point_keys<CK>(L + p * Dp, P + p * D, D, sx, sl, acc);
 #pragma unroll
     for (int j = 0; j < XQ; ++j) {
       const uint64_t kb = key_bits(acc[j]);
@@ -147,7 +158,7 @@ __global__ __launch_bounds__(256) void k_exact_bound(const PT* __restrict__ P, c
 // Collect the pairs at or below each query's bound.  `sel` lists the
 // positions (in queries) still to collect; cnt[q] receives the number of
 // pairs at or below the bound (possibly more than XCAP: then only XCAP kept).
-template <typename PT>
+template <typename PT, int CK>
 __global__ __launch_bounds__(256) void k_exact_collect(const PT* __restrict__ P, const double* __restrict__ L,
                                                        int64_t n, int D, int Dp,
                                                        const int32_t* __restrict__ queries,
@@ -187,7 +198,7 @@ __global__ __launch_bounds__(256) void k_exact_collect(const PT* __restrict__ P,
   __syncthreads();
   for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
     double acc[XQ];
-    point_keys(L + p * Dp, D, sx, sl, acc);
+    point_keys<CK>(L + p * Dp, P + p * D, D, sx, sl, acc);
 #pragma unroll
     for (int j = 0; j < XQ; ++j) {
       if (spos[j] < 0 || p == sq[j]) continue;
@@ -296,8 +307,8 @@ struct XBufs {
   }
 };
 
-template <typename PT>
-int exact_knn(const void* points, int64_t n, int32_t d, int32_t K, const int32_t* queries, int64_t nq,
+template <typename PT, int CK>
+int exact_knn(const void* points, int64_t n, int32_t d, int32_t K, int tk, const int32_t* queries, int64_t nq,
               const double* tau, int32_t on_device, hipStream_t st, int32_t* out_idx, double* out_kl) {
   using namespace knnd;
   const int D = d + 1, Dp = (D + 1) & ~1;
@@ -334,6 +345,7 @@ int exact_knn(const void* points, int64_t n, int32_t d, int32_t K, const int32_t
   c.D = D;
   c.Dp = Dp;
   c.dtype = sizeof(PT) == 4 ? KNND_F32 : KNND_F64;
+  c.tk = tk;
   c.stream = st;
   KNND_XHIP(launch_log_table(c, b.flag));
   hipLaunchKernelGGL(k_check_queries, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, b.q, nq, n,
@@ -354,7 +366,7 @@ int exact_knn(const void* points, int64_t n, int32_t d, int32_t K, const int32_t
     hipLaunchKernelGGL(k_bound_from_keys, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, b.tau, nq, b.tk,
                        b.ti);
   } else {
-    hipLaunchKernelGGL((k_exact_bound<PT>), dim3(qblocks), dim3(256), 0, st, (const PT*)b.P, b.L, n, D, Dp, K, b.q,
+    hipLaunchKernelGGL((k_exact_bound<PT, CK>), dim3(qblocks), dim3(256), 0, st, (const PT*)b.P, b.L, n, D, Dp, K, b.q,
                        nq, b.tk, b.ti);
   }
   KNND_XHIP(hipGetLastError());
@@ -366,7 +378,7 @@ int exact_knn(const void* points, int64_t n, int32_t d, int32_t K, const int32_t
   for (int pass = 0; nsel > 0; ++pass) {
     if (pass > 64) return KNND_ERR_DEVICE;  // cannot happen: each pass strictly lowers the bound
     KNND_XHIP(hipMemcpyAsync(b.sel, sel.data(), (size_t)nsel * 4, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL((k_exact_collect<PT>), dim3((unsigned)((nsel + XQ - 1) / XQ)), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_exact_collect<PT, CK>), dim3((unsigned)((nsel + XQ - 1) / XQ)), dim3(256), 0, st,
                        (const PT*)b.P, b.L, n, D, Dp, b.q, b.sel, nsel, b.tk, b.ti, b.ck, b.ci, b.cnt);
     KNND_XHIP(hipGetLastError());
     KNND_XHIP(hipMemcpyAsync(cnt.data(), b.cnt, (size_t)nq * 4, hipMemcpyDeviceToHost, st));
@@ -402,9 +414,10 @@ int exact_knn(const void* points, int64_t n, int32_t d, int32_t K, const int32_t
 }  // namespace
 
 extern "C" int knnd_exact_knn(const void* points, int64_t n, int32_t d, int32_t K, int32_t dtype,
-                              const int32_t* queries, int64_t nq, const double* tau, int32_t on_device,
-                              void* stream, int32_t* out_idx, double* out_kl) {
+                              int32_t comparator, const int32_t* queries, int64_t nq, const double* tau,
+                              int32_t on_device, void* stream, int32_t* out_idx, double* out_kl) {
   if (!points || !queries || !out_idx || nq < 1) return KNND_ERR_ARG;
+  if (comparator < KNND_CMP_KL || comparator > KNND_CMP_L2) return KNND_ERR_ARG;
   if (n < 2 || d < 1 || K < 1 || K > 64 || K > n - 1 || n >= (int64_t)knnd::IDMASK_HOST) return KNND_ERR_ARG;
   if (d + 1 > knnd::XMAXD) return KNND_ERR_UNSUPPORTED;
   if (dtype != KNND_F32 && dtype != KNND_F64) return KNND_ERR_ARG;
@@ -413,7 +426,13 @@ extern "C" int knnd_exact_knn(const void* points, int64_t n, int32_t d, int32_t 
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return KNND_ERR_DEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return KNND_ERR_DEVICE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (dtype == KNND_F32)
-    return exact_knn<float>(points, n, d, K, queries, nq, tau, on_device, st, out_idx, out_kl);
-  return exact_knn<double>(points, n, d, K, queries, nq, tau, on_device, st, out_idx, out_kl);
+  const int ck = knnd::cmp_fold_kind(comparator), tk = knnd::cmp_table_kind(comparator);
+  if (dtype == KNND_F32) {
+    if (ck == knnd::CK_REV) return exact_knn<float, knnd::CK_REV>(points, n, d, K, tk, queries, nq, tau, on_device, st, out_idx, out_kl);
+    if (ck == knnd::CK_SQ) return exact_knn<float, knnd::CK_SQ>(points, n, d, K, tk, queries, nq, tau, on_device, st, out_idx, out_kl);
+    return exact_knn<float, knnd::CK_KL>(points, n, d, K, tk, queries, nq, tau, on_device, st, out_idx, out_kl);
+  }
+  if (ck == knnd::CK_REV) return exact_knn<double, knnd::CK_REV>(points, n, d, K, tk, queries, nq, tau, on_device, st, out_idx, out_kl);
+  if (ck == knnd::CK_SQ) return exact_knn<double, knnd::CK_SQ>(points, n, d, K, tk, queries, nq, tau, on_device, st, out_idx, out_kl);
+  return exact_knn<double, knnd::CK_KL>(points, n, d, K, tk, queries, nq, tau, on_device, st, out_idx, out_kl);
 }

@@ -19,6 +19,14 @@ constexpr uint32_t IDMASK_HOST = 0x3FFFFFFFu;  // point indices are below this
 constexpr uint32_t CLASS_CAP_MIN = 512;
 constexpr int SHORT_LIST = 128;  // candidate lists up to this long are merged by k_merge
 
+// Key fold kinds and feature table kinds of the comparators (knnd_comparator):
+// KL -> (CK_KL, TK_LOG), reverse KL -> (CK_REV, TK_LOG), Hellinger ->
+// (CK_SQ, TK_SQRT), Euclidean -> (CK_SQ, TK_ID).
+enum { CK_KL = 0, CK_REV = 1, CK_SQ = 2 };
+enum { TK_LOG = 0, TK_SQRT = 1, TK_ID = 2 };
+inline int cmp_fold_kind(int cmp) { return cmp == 1 ? CK_REV : (cmp >= 2 ? CK_SQ : CK_KL); }
+inline int cmp_table_kind(int cmp) { return cmp == 2 ? TK_SQRT : (cmp == 3 ? TK_ID : TK_LOG); }
+
 // Per-round device counters
 enum { STAT_UPDATES = 0, STAT_HITS = 1, STAT_EVALS = 2, STAT_PERF = 3, STAT_RESCUES = 4, STAT_ERR = 5, STAT_N = 8 };
 // Per-point counters of one round in a batched group (summed per instance):
@@ -36,6 +44,9 @@ struct Ctx {
   int dtype = 0;      // 0 F32, 1 F64
   int precision = 0;
   int flags = 0;
+  int cmp = 0;        // knnd_comparator
+  int ck = 0;         // its key fold kind (CK_*)
+  int tk = 0;         // its feature table kind (TK_*)
   int64_t M = 0;
   int max_rounds = 100;
   int round = 0;      // rounds completed
@@ -43,7 +54,7 @@ struct Ctx {
 
   // device buffers
   void* P = nullptr;          // [n][D] points (copy owned by the context)
-  double* L = nullptr;        // [n][Dp]
+  double* L = nullptr;        // [n][Dp] feature table (log x for the KL comparators)
   uint32_t* F[2] = {nullptr, nullptr};
   double* keys[2] = {nullptr, nullptr};
   int cur = 0;                // F[cur], keys[cur] hold the current snapshot
@@ -103,6 +114,7 @@ struct JoinArgs {
   const double* L;
   int64_t n;
   int D, Dp, Ds, K;
+  int ck;  // comparator kind of the key fold (CK_*)
   const uint32_t* F;
   const double* keys;
   const int64_t* rowptr;

@@ -50,12 +50,16 @@ __global__ void k_load_idx(const int32_t* __restrict__ idx, int64_t cnt, int64_t
 // ---------------------------------------------------------------------------
 // a0: log table (and domain check of every coordinate)
 // ---------------------------------------------------------------------------
+// The comparator's feature table, kind tk: TK_LOG (the KL comparators) holds
+// the correctly rounded log of each coordinate, which must be finite and
+// > 0; TK_SQRT (Hellinger) the IEEE square root, coordinates finite and >= 0;
+// TK_ID (Euclidean) the coordinate itself, finite.
 // In a batched group, coordinates past an instance's own d+1 are zero padding
-// (log entry 0, not checked): they add exactly nothing to any key.
+// (table entry 0, not checked): they add exactly nothing to any key.
 template <typename PT>
 __global__ void k_log_table(const PT* __restrict__ P, int64_t n, int D, int Dp, double* __restrict__ L,
                             int32_t* __restrict__ bad, const int32_t* __restrict__ inst_of,
-                            const int32_t* __restrict__ iD) {
+                            const int32_t* __restrict__ iD, int tk) {
   const int64_t total = n * Dp;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = t / Dp;
@@ -63,10 +67,21 @@ __global__ void k_log_table(const PT* __restrict__ P, int64_t n, int D, int Dp, 
     double out = 0.0;
     if (i < (inst_of ? iD[inst_of[j]] : D)) {
       const double v = (double)P[j * D + i];
-      if (!(v > 0.0) || isinf(v)) {
-        atomicOr(bad, 1);
+      if (tk == TK_LOG) {
+        if (!(v > 0.0) || isinf(v))
+          atomicOr(bad, 1);
+        else
+          out = crlog(v);
+      } else if (tk == TK_SQRT) {
+        if (!(v >= 0.0) || isinf(v))
+          atomicOr(bad, 1);
+        else
+          out = sqrt(v);
       } else {
-        out = crlog(v);
+        if (!isfinite(v))
+          atomicOr(bad, 1);
+        else
+          out = v;
       }
     }
     L[t] = out;
@@ -80,7 +95,7 @@ __global__ void k_log_table(const PT* __restrict__ P, int64_t n, int D, int Dp, 
 // In a batched group x, y, n and seed are those of x's instance (indices
 // local to it, stored offset by its first point).
 // ---------------------------------------------------------------------------
-template <typename PT>
+template <typename PT, int CK>
 __global__ __launch_bounds__(256) void k_init_graph(const PT* __restrict__ P, const double* __restrict__ L,
                                                     int64_t n, int D, int Dp, int K, uint64_t seed,
                                                     uint32_t* __restrict__ F, double* __restrict__ keys,
@@ -125,7 +140,8 @@ __global__ __launch_bounds__(256) void k_init_graph(const PT* __restrict__ P, co
   uint64_t kb = KEY_SENTINEL;
   uint32_t id = IDMASK;
   if (lane < K) {
-    kb = key_bits(canonical_key(P + x * D, L + x * Dp, L + (int64_t)mine * Dp, D));
+    const PT* pw = P + (CK == CK_REV ? (int64_t)mine : x) * D;
+    kb = key_bits(canonical_key<PT, CK>(pw, L + x * Dp, L + (int64_t)mine * Dp, D));
     id = mine;
   }
   wave_sort(kb, id);
@@ -406,7 +422,7 @@ __device__ __forceinline__ void hub_count(const JoinArgs& a, int64_t v, int64_t 
 // Pairs whose two edges were both present one round earlier are skipped
 // (their candidate cannot enter, see the receiver kernel).
 // ---------------------------------------------------------------------------
-template <typename PT>
+template <typename PT, int CK>
 __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
   extern __shared__ double s_cand[];  // (K+1) rows of Ds doubles
   __shared__ uint32_t s_fv[2 * WAVE];
@@ -485,7 +501,17 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
         if (a.skip && !isnew) continue;
         const double* lc = s_cand + ci * Ds;
         double acc = 0.0;
-        for (int i = 0; i < D; ++i) acc = fma((double)pr[i], lr[i] - lc[i], acc);
+        if constexpr (CK == CK_KL) {
+          for (int i = 0; i < D; ++i) acc = fma((double)pr[i], lr[i] - lc[i], acc);
+        } else if constexpr (CK == CK_REV) {
+          const PT* pc = P + (ci < K ? (int64_t)(s_fv[ci] & IDMASK) : v) * D;
+          for (int i = 0; i < D; ++i) acc = fma((double)pc[i], lc[i] - lr[i], acc);
+        } else {
+          for (int i = 0; i < D; ++i) {
+            const double t = lr[i] - lc[i];
+            acc = fma(t, t, acc);
+          }
+        }
         a.seg[pos] = acc + 0.0;
         ++my_perf;
       }
@@ -504,25 +530,40 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
 // loads, so the fold is two FP64 VALU operations per coordinate with no
 // vector memory traffic.  Same output as k_hub_lds.
 // Canonical fold of one receiver (registers, zero beyond D) against one
-// wave-uniform candidate log row read with scalar loads.
-template <int MAXD>
+// wave-uniform candidate row (feature row lc, point row pc) read with scalar
+// loads.  Candidate entries past D belong to the next row (or the tail
+// padding): the KL kind multiplies them by the receiver's zeros, the other
+// kinds mask them, so every extra term adds an exact zero.
+template <int MAXD, int CK, typename PT>
 __device__ __forceinline__ double hub_fold(const double (&pr)[MAXD], const double (&lr)[MAXD],
-                                           const double* __restrict__ lc) {
+                                           const PT* __restrict__ pc, const double* __restrict__ lc, int D) {
   double acc = 0.0;
 #pragma unroll
   for (int i0 = 0; i0 < MAXD; i0 += 16) {
-    double cv16[16];
+    double cv16[16], w16[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-      if (i0 + i < MAXD) cv16[i] = lc[i0 + i];
+      if (i0 + i < MAXD) {
+        cv16[i] = lc[i0 + i];
+        if constexpr (CK == CK_REV) w16[i] = (double)pc[i0 + i];
+      }
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-      if (i0 + i < MAXD) acc = fma(pr[i0 + i], lr[i0 + i] - cv16[i], acc);
+      if (i0 + i < MAXD) {
+        if constexpr (CK == CK_KL) {
+          acc = fma(pr[i0 + i], lr[i0 + i] - cv16[i], acc);
+        } else if constexpr (CK == CK_REV) {
+          acc = fma(i0 + i < D ? w16[i] : 0.0, cv16[i] - lr[i0 + i], acc);
+        } else {
+          const double t = lr[i0 + i] - (i0 + i < D ? cv16[i] : 0.0);
+          acc = fma(t, t, acc);
+        }
+      }
   }
   return acc + 0.0;
 }
 
-template <int MAXD, typename PT>
+template <int MAXD, typename PT, int CK>
 __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __restrict__ L,
                                                  const PT* __restrict__ P) {
   constexpr int CH = 16;  // candidates per LDS tile
@@ -598,7 +639,7 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
           if (__ballot(nd) == 0) continue;
           const uint32_t craw = (uint32_t)__shfl((int)fv, ci, WAVE);
           const int64_t cidx = (int64_t)__builtin_amdgcn_readfirstlane(craw & IDMASK);
-          s_keys[wv][lane][cj] = hub_fold<MAXD>(pr, lr, L + cidx * Dp);  // scalar loads
+          s_keys[wv][lane][cj] = hub_fold<MAXD, CK>(pr, lr, P + cidx * D, L + cidx * Dp, D);  // scalar loads
           my_perf += nd ? 1 : 0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -617,7 +658,7 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
       }
       // slot K: the hub itself, a co-friend candidate of each of its friends
       if (__ballot(need_v)) {
-        const double key = hub_fold<MAXD>(pr, lr, L + v * Dp);
+        const double key = hub_fold<MAXD, CK>(pr, lr, P + v * D, L + v * Dp, D);
         if (need_v) {
           a.seg[b1] = key;
           ++my_perf;
@@ -1484,8 +1525,6 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
         lk = key_bits(kx[lane]);
         li = s_fx[lane] & IDMASK;
       }
-      const PT* px = P + x * D;
-      const double* lx = a.L + x * Dp;
       for (int i0 = wave * WAVE; i0 < ncand; i0 += NT) {
         const int i = i0 + lane;
         const bool valid = i < ncand;
@@ -1496,7 +1535,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
           if (SEG)
             kb = key_bits(ckey[i]);
           else
-            kb = key_bits(canonical_key(px, lx, a.L + (int64_t)z * Dp, D));
+            kb = key_bits(key_of_kind<PT>(a.ck, P, x, z, a.L, D, Dp));
         }
         my_perf += (!SEG && valid) ? 1 : 0;
         const uint64_t kk = shfl_u64(lk, K - 1);
@@ -1637,23 +1676,35 @@ hipError_t launch_log_table(const Ctx& c, int32_t* bad) {
   const int g = grid_for(total, 256, 65536);
   if (c.dtype == 0)
     hipLaunchKernelGGL(k_log_table<float>, dim3(g), dim3(256), 0, c.stream, (const float*)c.P, c.n, c.D, c.Dp,
-                       c.L, bad, c.inst_of, c.iD);
+                       c.L, bad, c.inst_of, c.iD, c.tk);
   else
     hipLaunchKernelGGL(k_log_table<double>, dim3(g), dim3(256), 0, c.stream, (const double*)c.P, c.n, c.D, c.Dp,
-                       c.L, bad, c.inst_of, c.iD);
+                       c.L, bad, c.inst_of, c.iD, c.tk);
   return hipGetLastError();
 }
 
-hipError_t launch_init_graph(const Ctx& c) {
+template <typename PT, int CK>
+static void launch_init_t(const Ctx& c) {
   const int g = (int)((c.n + 3) / 4);
-  uint32_t* F = c.F[c.cur];
-  double* keys = c.keys[c.cur];
-  if (c.dtype == 0)
-    hipLaunchKernelGGL(k_init_graph<float>, dim3(g), dim3(256), 0, c.stream, (const float*)c.P, c.L, c.n, c.D,
-                       c.Dp, c.K, c.seed, F, keys, c.inst_of, c.ioff, c.iseed);
+  hipLaunchKernelGGL((k_init_graph<PT, CK>), dim3(g), dim3(256), 0, c.stream, (const PT*)c.P, c.L, c.n, c.D,
+                     c.Dp, c.K, c.seed, c.F[c.cur], c.keys[c.cur], c.inst_of, c.ioff, c.iseed);
+}
+
+template <typename PT>
+static void launch_init_kind(const Ctx& c) {
+  if (c.ck == CK_REV)
+    launch_init_t<PT, CK_REV>(c);
+  else if (c.ck == CK_SQ)
+    launch_init_t<PT, CK_SQ>(c);
   else
-    hipLaunchKernelGGL(k_init_graph<double>, dim3(g), dim3(256), 0, c.stream, (const double*)c.P, c.L, c.n, c.D,
-                       c.Dp, c.K, c.seed, F, keys, c.inst_of, c.ioff, c.iseed);
+    launch_init_t<PT, CK_KL>(c);
+}
+
+hipError_t launch_init_graph(const Ctx& c) {
+  if (c.dtype == 0)
+    launch_init_kind<float>(c);
+  else
+    launch_init_kind<double>(c);
   return hipGetLastError();
 }
 
@@ -1747,9 +1798,9 @@ static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
   return launch_recv_class<0, PT, MODE>(c, a, 7);
 }
 
-template <int MAXD, typename PT>
+template <int MAXD, typename PT, int CK>
 static hipError_t launch_hub_reg(const Ctx& c, const JoinArgs& a) {
-  auto kern = k_hub_reg<MAXD, PT>;
+  auto kern = k_hub_reg<MAXD, PT, CK>;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu * 4);
@@ -1757,23 +1808,31 @@ static hipError_t launch_hub_reg(const Ctx& c, const JoinArgs& a) {
   return hipGetLastError();
 }
 
-template <typename PT>
+template <typename PT, int CK>
 static hipError_t launch_hub(const Ctx& c, const JoinArgs& a) {
-  if (c.D <= 8) return launch_hub_reg<8, PT>(c, a);
-  if (c.D <= 12) return launch_hub_reg<12, PT>(c, a);
-  if (c.D <= 16) return launch_hub_reg<16, PT>(c, a);
-  if (c.D <= 24) return launch_hub_reg<24, PT>(c, a);
-  if (c.D <= 32) return launch_hub_reg<32, PT>(c, a);
-  if (c.D <= 40) return launch_hub_reg<40, PT>(c, a);
-  if (c.D <= 52) return launch_hub_reg<52, PT>(c, a);
-  if (c.D <= HUB_MAXD) return launch_hub_reg<HUB_MAXD, PT>(c, a);
+  if (c.D <= 8) return launch_hub_reg<8, PT, CK>(c, a);
+  if (c.D <= 12) return launch_hub_reg<12, PT, CK>(c, a);
+  if (c.D <= 16) return launch_hub_reg<16, PT, CK>(c, a);
+  if (c.D <= 24) return launch_hub_reg<24, PT, CK>(c, a);
+  if (c.D <= 32) return launch_hub_reg<32, PT, CK>(c, a);
+  if (c.D <= 40) return launch_hub_reg<40, PT, CK>(c, a);
+  if (c.D <= 52) return launch_hub_reg<52, PT, CK>(c, a);
+  if (c.D <= HUB_MAXD) return launch_hub_reg<HUB_MAXD, PT, CK>(c, a);
   const size_t lds = (size_t)(c.K + 1) * c.Ds * sizeof(double);
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hub_lds<PT>, 256, lds) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hub_lds<PT, CK>, 256, lds) != hipSuccess ||
+      per_cu < 1)
     per_cu = 1;
   const int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu * 2);
-  hipLaunchKernelGGL(k_hub_lds<PT>, dim3(grid), dim3(256), lds, c.stream, a);
+  hipLaunchKernelGGL((k_hub_lds<PT, CK>), dim3(grid), dim3(256), lds, c.stream, a);
   return hipGetLastError();
+}
+
+template <typename PT>
+static hipError_t launch_hub_kind(const Ctx& c, const JoinArgs& a) {
+  if (c.ck == CK_REV) return launch_hub<PT, CK_REV>(c, a);
+  if (c.ck == CK_SQ) return launch_hub<PT, CK_SQ>(c, a);
+  return launch_hub<PT, CK_KL>(c, a);
 }
 
 template <int DK, typename H>
@@ -1818,6 +1877,7 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   a.Dp = c.Dp;
   a.Ds = c.Ds;
   a.K = c.K;
+  a.ck = c.ck;
   a.F = c.F[c.cur];
   a.keys = c.keys[c.cur];
   a.rowptr = c.rowptr;
@@ -1854,7 +1914,7 @@ hipError_t launch_join_hub(const Ctx& c, int64_t* stats) {
   const JoinArgs a = join_args(c, stats);
   if (c.use_hub && (c.mixed ? (!c.seg32 || !c.Ph || !c.Lh || !c.S) : !c.seg)) return hipErrorInvalidValue;
   if (c.mixed) return launch_hub_mfma(c, a);
-  if (c.use_hub) return c.dtype == 0 ? launch_hub<float>(c, a) : launch_hub<double>(c, a);
+  if (c.use_hub) return c.dtype == 0 ? launch_hub_kind<float>(c, a) : launch_hub_kind<double>(c, a);
   return hipSuccess;
 }
 

@@ -44,10 +44,10 @@ def test_params_struct_layout_matches_header():
     assert ctypes.sizeof(knnd.knnd_round_stats) == 72
     p = knnd.default_params()
     assert (p.precision, p.dtype, p.fcr_samples, p.max_rounds, p.flags) == (0, 0, 0, 100, 0)
-    assert (p.stop_rule, p.reserved, p.delta) == (knnd.KNND_STOP_FCR, 0, 0.0)
+    assert (p.stop_rule, p.comparator, p.delta) == (knnd.KNND_STOP_FCR, knnd.KNND_CMP_KL, 0.0)
 
 
-@pytest.mark.parametrize("kw", [dict(stop_rule=3), dict(stop_rule=-1), dict(reserved=1),
+@pytest.mark.parametrize("kw", [dict(stop_rule=3), dict(stop_rule=-1), dict(comparator=4), dict(comparator=-1),
                                 dict(stop_rule=2, delta=-0.5), dict(stop_rule=2, delta=float("nan")),
                                 dict(stop_rule=2, delta=float("inf")), dict(precision=3)])
 def test_bad_params_are_argument_errors_before_device_work(kw):

@@ -44,14 +44,15 @@ def assert_same_graph(gi, gk, oi, ok, what):
     assert kb.size == 0, f"{what}: keys differ in {kb.size} rows, first x={kb[:5].tolist()}"
 
 
-def full_compare(P, d, K, seed, M=0, flags=0, max_rounds=100, precision=0, stop_rule=0, delta=0.0):
+def full_compare(P, d, K, seed, M=0, flags=0, max_rounds=100, precision=0, stop_rule=0, delta=0.0,
+                 cmp=0):
     say(f"full build n={P.shape[0]} d={d} K={K} seed={seed} {P.dtype} M={M} flags={flags} "
-        f"precision={precision} stop_rule={stop_rule} delta={delta}")
+        f"precision={precision} stop_rule={stop_rule} delta={delta} cmp={cmp}")
     prm = knnd.default_params(fcr_samples=M, flags=flags, max_rounds=max_rounds,
-                              precision=precision, stop_rule=stop_rule, delta=delta)
+                              precision=precision, stop_rule=stop_rule, delta=delta, comparator=cmp)
     g = knnd.knnd_build_ex(P, d, K, seed, prm)
     o = oracle.build_graph(P, d, K, seed, M=M, max_rounds=max_rounds, stop_rule=stop_rule,
-                           delta=delta)
+                           delta=delta, cmp=cmp)
     assert g["status"] == o.status
     assert g["rounds"] == o.rounds, (g["rounds"], o.rounds)
     for r in range(o.rounds + 1):
@@ -108,18 +109,18 @@ def test_initial_graph_bit_exact(n, d, K, dtype):
 # ---------------------------------------------------------------------------
 # a1..a5: one round from the oracle's own snapshot
 # ---------------------------------------------------------------------------
-def one_round(P, d, K, seed, F0=None, k0=None, flags=0, precision=0):
+def one_round(P, d, K, seed, F0=None, k0=None, flags=0, precision=0, cmp=0):
     P64 = oracle.widen(P)
-    L = oracle.log_table(P64)
+    L = oracle.log_table(P64) if cmp in (0, 1) else np.zeros_like(P64)
     if F0 is None:
-        F0, k0 = oracle.initial_graph(P64, L, K, seed)
-    say(f"one round n={P.shape[0]} d={d} K={K} flags={flags} precision={precision}")
-    prm = knnd.default_params(flags=flags, precision=precision)
+        F0, k0 = oracle.initial_graph(P64, L, K, seed, cmp=cmp)
+    say(f"one round n={P.shape[0]} d={d} K={K} flags={flags} precision={precision} cmp={cmp}")
+    prm = knnd.default_params(flags=flags, precision=precision, comparator=cmp)
     with knnd.Context(P, d, K, seed, prm) as c:
         c.set_graph(F0, k0, 0)
         st = c.round()
         gi, gk = c.get_graph()
-    oi, ok, upd, ev = oracle.round_step(P64, L, F0, k0)
+    oi, ok, upd, ev = oracle.round_step(P64, L, F0, k0, cmp=cmp)
     assert_same_graph(gi, gk, oi, ok, "round 1")
     assert (st["updates"], st["evals_alg"]) == (upd, ev)
     assert st["fcr_hits"] == oracle.fcr(oi, seed, 1, min(P.shape[0], 10000))
@@ -473,8 +474,8 @@ def test_exact_knn_device_pointers_and_errors():
 # Batched instances (knnd_build_batched): each instance must come out exactly
 # as the oracle's descent of that instance alone.
 # ---------------------------------------------------------------------------
-def _compare_instance(g, P, d, K, seed, what, stop_rule=0, delta=0.0):
-    o = oracle.build_graph(P, d, K, seed, stop_rule=stop_rule, delta=delta)
+def _compare_instance(g, P, d, K, seed, what, stop_rule=0, delta=0.0, cmp=0):
+    o = oracle.build_graph(P, d, K, seed, stop_rule=stop_rule, delta=delta, cmp=cmp)
     assert g["status"] == o.status, what
     assert g["rounds"] == o.rounds, (what, g["rounds"], o.rounds)
     for r in range(o.rounds + 1):
@@ -588,3 +589,120 @@ def test_paper_tables_statistics_on_gpu():
         assert acc[(K, 10)] > acc[(K, 40)] and acc[(K, 20)] > acc[(K, 60)]
     for c in (10, 20, 40, 60):
         assert acc[(64, c)] > acc[(16, c)]
+
+
+# ---------------------------------------------------------------------------
+# Other comparators (Section 2.1: any family of per-point total orders):
+# reverse KL, Hellinger and Euclidean keys, bit for bit against the oracle.
+# ---------------------------------------------------------------------------
+CMPS = [knnd.KNND_CMP_KL_REVERSE, knnd.KNND_CMP_HELLINGER, knnd.KNND_CMP_L2]
+CMP_IDS = ["reverse_kl", "hellinger", "l2"]
+
+
+def _gauss(seed, n, D, dtype=np.float32):
+    """Seeded standard normal points (any sign): inputs for the Euclidean comparator."""
+    return np.random.default_rng(seed).standard_normal((n, D)).astype(dtype)
+
+
+def test_feature_tables_bit_exact():
+    # square roots (Hellinger) over many binades, zeros and subnormals; the
+    # identity table (Euclidean) on values of any sign
+    rng = np.random.default_rng(3)
+    vals = np.concatenate([np.array([0.0, 1.0, 4.0, 2.0, 0.5, 5e-324, 1e-310, 2.0 ** -1022, 1e300,
+                                     np.nextafter(1.0, 2.0), np.nextafter(1.0, 0.0)]),
+                           np.ldexp(rng.uniform(0.5, 1.0, 20000), rng.integers(-1074, 1000, 20000)),
+                           rng.uniform(0.0, 1.0, 4000)])
+    D = 8
+    vals = vals[: (vals.size // D) * D].reshape(-1, D)
+    say(f"sqrt table of {vals.size} values")
+    prm = knnd.default_params(comparator=knnd.KNND_CMP_HELLINGER)
+    with knnd.Context(vals, D - 1, 2, 1, prm) as c:
+        L = c.log_table()
+    assert np.array_equal(bits(L), bits(np.sqrt(vals)))
+    G = _gauss(4, 500, D, np.float64)
+    prm = knnd.default_params(comparator=knnd.KNND_CMP_L2)
+    with knnd.Context(G, D - 1, 2, 1, prm) as c:
+        L = c.log_table()
+    assert np.array_equal(bits(L), bits(G))
+
+
+@pytest.mark.parametrize("cmp", CMPS, ids=CMP_IDS)
+@pytest.mark.parametrize("n,d,K,dtype", [(2000, 5, 10, np.float64), (5000, 10, 20, np.float32),
+                                         (65, 3, 64, np.float32)])
+def test_comparator_initial_graph_bit_exact(n, d, K, dtype, cmp):
+    P = synth.dirichlet(600 + n, n, d, dtype)
+    seed = 910 + n
+    prm = knnd.default_params(comparator=cmp)
+    with knnd.Context(P, d, K, seed, prm) as c:
+        c.init_graph()
+        gi, gk = c.get_graph()
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    oi, ok = oracle.initial_graph(P64, L, K, seed, cmp=cmp)
+    assert_same_graph(gi, gk, oi, ok, "initial graph")
+
+
+@pytest.mark.parametrize("form", FORMS[:3], ids=FORM_IDS[:3])
+@pytest.mark.parametrize("cmp", CMPS, ids=CMP_IDS)
+@pytest.mark.parametrize("n,d,K", [(3001, 20, 30), (1000, 6, 16), (700, 70, 8), (200, 1, 2)])
+def test_comparator_one_round_bit_exact(n, d, K, cmp, form):
+    P = synth.dirichlet(700 + n + d, n, d, np.float32)
+    one_round(P, d, K, 33 + n, flags=form[0], precision=form[1], cmp=cmp)
+
+
+@pytest.mark.parametrize("form", FORMS[:3], ids=FORM_IDS[:3])
+@pytest.mark.parametrize("cmp", CMPS, ids=CMP_IDS)
+@pytest.mark.parametrize("n,d,K,ds,seed", [(3001, 20, 30, 5, 7), (20000, 10, 20, 6, 8),
+                                           (2500, 80, 12, 10, 4)])
+def test_comparator_full(n, d, K, ds, seed, cmp, form):
+    P = synth.dirichlet(ds, n, d, np.float32)
+    g, o = full_compare(P, d, K, seed, flags=form[0], precision=form[1], cmp=cmp)
+    assert g["stats"][1]["rescues"] == 0  # no mixed form for these keys
+
+
+@pytest.mark.parametrize("form", FORMS[:2], ids=FORM_IDS[:2])
+def test_euclidean_on_points_of_any_sign(form):
+    G = _gauss(5, 6000, 12)
+    full_compare(G, 11, 16, 17, flags=form[0], cmp=knnd.KNND_CMP_L2,
+                 stop_rule=knnd.KNND_STOP_FIXED_POINT)
+
+
+def test_comparator_domains():
+    P = synth.dirichlet(8, 300, 4, np.float32)
+    P[7, 2] = 0.0
+    for cmp, want in [(knnd.KNND_CMP_KL_REVERSE, knnd.KNND_ERR_DOMAIN), (knnd.KNND_CMP_HELLINGER, knnd.KNND_OK),
+                      (knnd.KNND_CMP_L2, knnd.KNND_OK)]:
+        prm = knnd.default_params(comparator=cmp)
+        if want == knnd.KNND_OK:
+            assert knnd.knnd_build_ex(P, 4, 8, 1, prm)["status"] == knnd.KNND_OK
+        else:
+            with pytest.raises(knnd.KnndError) as e:
+                knnd.knnd_build_ex(P, 4, 8, 1, prm)
+            assert e.value.status == want
+    P[9, 1] = -0.25
+    with pytest.raises(knnd.KnndError) as e:
+        knnd.knnd_build_ex(P, 4, 8, 1, knnd.default_params(comparator=knnd.KNND_CMP_HELLINGER))
+    assert e.value.status == knnd.KNND_ERR_DOMAIN
+
+
+@pytest.mark.parametrize("cmp", CMPS, ids=CMP_IDS)
+def test_batched_comparators_vs_oracle(cmp):
+    inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX]
+    say(f"batched: comparator {cmp}")
+    st, outs = knnd.knnd_build_batched(inst, knnd.default_params(comparator=cmp))
+    assert st == knnd.KNND_OK
+    for (P, d, K, s), g in zip(inst, outs):
+        _compare_instance(g, P, d, K, s, f"instance n={P.shape[0]} d={d} K={K}", cmp=cmp)
+
+
+@pytest.mark.parametrize("cmp", CMPS, ids=CMP_IDS)
+@pytest.mark.parametrize("n,d,K,dtype", [(5000, 9, 16, np.float32), (3001, 20, 30, np.float64),
+                                         (1500, 100, 8, np.float32)])
+def test_comparator_exact_knn_matches_oracle(n, d, K, dtype, cmp):
+    P = synth.dirichlet(800 + n, n, d, dtype)
+    qs = synth.subsample(77, n, 300).astype(np.int32)
+    say(f"exact knn n={n} d={d} K={K} cmp={cmp}")
+    ei, ek = knnd.knnd_exact_knn(P, d, K, qs, comparator=cmp)
+    P64 = oracle.widen(P)
+    oi, ok = oracle.bruteforce(P64, oracle.log_table(P64), K, qs.astype(np.int64), cmp=cmp)
+    assert_same_graph(ei, ek, oi, ok, "exact knn")
