@@ -44,7 +44,7 @@ void free_ctx(Ctx& c) {
                   c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.gckey, c.bcand, c.bckey,
                   c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32,
                   c.inst_of, c.ioff, c.iseed, c.iM, c.iD, c.iactive, c.istats, c.vcnt,
-                  c.sl_n, c.sl_id, c.sl_key};
+                  c.sl_n, c.sl_id, c.sl_key, c.csr_T, c.csr_bcount, c.csr_bfill, c.csr_bbase};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c.hstats) (void)hipHostFree(c.hstats);
@@ -129,6 +129,16 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   if (e == hipSuccess) e = dalloc(&c.col, nK);
   if (e == hipSuccess) e = dalloc(&c.colslot, nK);
   if (e == hipSuccess) e = dalloc(&c.tilesum, (size_t)ntiles + 1);
+  // bucketed CSR: targets per bucket the smallest power of two >= 256 giving
+  // at most CSR_MAXB buckets
+  c.csr_shift = 8;
+  while (c.csr_shift < 13 && ((n + ((int64_t)1 << c.csr_shift) - 1) >> c.csr_shift) > knnd::CSR_MAXB) ++c.csr_shift;
+  if (((n + ((int64_t)1 << c.csr_shift) - 1) >> c.csr_shift) <= knnd::CSR_MAXB && nK < ((size_t)1 << 31)) {
+    if (e == hipSuccess) e = dalloc(&c.csr_T, nK);
+    if (e == hipSuccess) e = dalloc(&c.csr_bcount, (size_t)knnd::CSR_MAXB);
+    if (e == hipSuccess) e = dalloc(&c.csr_bfill, (size_t)knnd::CSR_MAXB);
+    if (e == hipSuccess) e = dalloc(&c.csr_bbase, (size_t)knnd::CSR_MAXB + 1);
+  }
   if (e == hipSuccess) e = dalloc(&c.class_count, (size_t)knnd::NCLASS);
   if (e == hipSuccess) e = dalloc(&c.class_list, (size_t)knnd::NCLASS * n);
   if (e == hipSuccess) e = dalloc(&c.gtab, (size_t)c.gblocks * c.gstride);

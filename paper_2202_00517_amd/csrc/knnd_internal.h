@@ -18,6 +18,10 @@ constexpr int HUB_MAXD = 64;     // register hub kernel up to this many coordina
 constexpr uint32_t IDMASK_HOST = 0x3FFFFFFFu;  // point indices are below this
 constexpr uint32_t CLASS_CAP_MIN = 512;
 constexpr int SHORT_LIST = 128;  // candidate lists up to this long are merged by k_merge
+// Bucketed reverse-neighbour build: at most CSR_MAXB buckets of 256..CSR_MAXTB
+// consecutive targets (n <= CSR_MAXB * CSR_MAXTB); larger n uses per-edge atomics.
+constexpr int CSR_MAXB = 4096;
+constexpr int CSR_MAXTB = 8192;
 
 // Key fold kinds and feature table kinds of the comparators (knnd_comparator):
 // KL -> (CK_KL, TK_LOG), reverse KL -> (CK_REV, TK_LOG), Hellinger ->
@@ -78,6 +82,12 @@ struct Ctx {
   uint32_t* sl_id = nullptr;   // [n][SHORT_LIST]
   double* sl_key = nullptr;    // [n][SHORT_LIST] (exact hub form only)
   int64_t* tilesum = nullptr;
+  // bucketed CSR build (null when n is too large for it)
+  uint64_t* csr_T = nullptr;       // [nK] edges partitioned by target bucket
+  int64_t* csr_bcount = nullptr;   // [CSR_MAXB] edges per bucket
+  int64_t* csr_bfill = nullptr;    // [CSR_MAXB] reservation cursors
+  int64_t* csr_bbase = nullptr;    // [CSR_MAXB + 1] first edge of each bucket
+  int csr_shift = 8;               // log2 of the targets per bucket
   int32_t* class_count = nullptr;  // [NCLASS]
   int32_t* class_list = nullptr;   // [NCLASS][n]
   uint32_t* gtab = nullptr;        // [gblocks][gstride]

@@ -17,6 +17,7 @@
 namespace knnd {
 
 constexpr int SEL_BINS = 1024;  // histogram bins of the threshold selection
+constexpr int CSR_CHUNK = 65536;  // edges per block of the partition passes (rounded to a multiple of K)
 constexpr int SEL_SURV = 256;   // survivors handled by the fast selection path
 
 // ---------------------------------------------------------------------------
@@ -329,6 +330,119 @@ __global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, con
     col[pos] = (uint32_t)x | (raw & NEWBIT);
     colslot[pos] = (uint8_t)(e - x * K);
   }
+}
+
+// ---------------------------------------------------------------------------
+// The same reverse-neighbour CSR by a two-level counting sort, without one
+// device-wide atomic per edge: edges are partitioned by target bucket (tb
+// consecutive targets) with LDS histograms and one global reservation per
+// (block, bucket), then each bucket's edges are counted and placed per
+// target in LDS.  A partitioned edge is packed as x (bits 0-29), its slot j
+// in F[x] (30-35), the new-flag (36) and the target's offset in its bucket
+// (40-52).  Within a segment the order of co-friends is arbitrary (as with
+// the atomic scatter); nothing depends on it.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_part_count(const uint32_t* __restrict__ F, int64_t nK, int chunk,
+                                                     int shift, int nb, unsigned long long* __restrict__ bcount) {
+  __shared__ int32_t h[CSR_MAXB];
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) h[t] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * chunk;
+  const int64_t e1 = min(e0 + chunk, nK);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&h[(F[e] & IDMASK) >> shift], 1);
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb; t += blockDim.x)
+    if (h[t]) atomicAdd(&bcount[t], (unsigned long long)h[t]);
+}
+
+// Exclusive scan of m int64 counts (one block), the total at out[m]; the
+// fill counters are cleared for the scatter pass.
+__global__ __launch_bounds__(256) void k_exscan_small(const unsigned long long* __restrict__ in, int64_t m,
+                                                      int64_t* __restrict__ out,
+                                                      unsigned long long* __restrict__ fill) {
+  __shared__ int64_t sh[4];
+  int64_t carry = 0;
+  for (int64_t b = 0; b < m; b += 256) {
+    const int64_t i = b + threadIdx.x;
+    const int64_t v = i < m ? (int64_t)in[i] : 0;
+    int64_t total;
+    const int64_t ex = block_exscan(v, sh, total);
+    if (i < m) {
+      out[i] = carry + ex;
+      fill[i] = 0;
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[m] = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restrict__ F, int64_t nK, int K,
+                                                       int chunk, int shift, int nb,
+                                                       const int64_t* __restrict__ bbase,
+                                                       unsigned long long* __restrict__ bfill,
+                                                       uint64_t* __restrict__ T) {
+  __shared__ int32_t h[CSR_MAXB];
+  __shared__ int64_t base[CSR_MAXB];
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) h[t] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * chunk;  // chunk is a multiple of K
+  const int64_t e1 = min(e0 + chunk, nK);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&h[(F[e] & IDMASK) >> shift], 1);
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+    if (h[t]) base[t] = bbase[t] + (int64_t)atomicAdd(&bfill[t], (unsigned long long)h[t]);
+    h[t] = 0;
+  }
+  __syncthreads();
+  const int64_t x0 = e0 / K;
+  const uint32_t tmask = (1u << shift) - 1;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const uint32_t raw = F[e];
+    const uint32_t v = raw & IDMASK;
+    const int b = (int)(v >> shift);
+    const int q = atomicAdd(&h[b], 1);
+    const uint32_t r = (uint32_t)(e - e0);
+    const uint32_t xr = r / (uint32_t)K;
+    const uint64_t x = (uint64_t)(x0 + xr);
+    const uint64_t j = r - xr * (uint32_t)K;
+    T[base[b] + q] = x | (j << 30) | ((uint64_t)(raw >> 31) << 36) | ((uint64_t)(v & tmask) << 40);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bucket_csr(const uint64_t* __restrict__ T, const int64_t* __restrict__ bbase,
+                                                    int64_t n, int shift, int nb, int64_t* __restrict__ rowptr,
+                                                    uint32_t* __restrict__ col, uint8_t* __restrict__ colslot) {
+  __shared__ int32_t cnt[CSR_MAXTB];
+  __shared__ int64_t sh[4];
+  const int b = blockIdx.x;
+  const int tb = 1 << shift;
+  const int64_t lo = bbase[b], hi = bbase[b + 1];
+  const int64_t v0 = (int64_t)b << shift;
+  for (int t = threadIdx.x; t < tb; t += 256) cnt[t] = 0;
+  __syncthreads();
+  for (int64_t p = lo + threadIdx.x; p < hi; p += 256) atomicAdd(&cnt[(int)(T[p] >> 40) & (tb - 1)], 1);
+  __syncthreads();
+  // exclusive scan: thread i owns targets [i*per, (i+1)*per)
+  const int per = tb / 256;
+  int64_t mine = 0;
+  for (int k = 0; k < per; ++k) mine += cnt[threadIdx.x * per + k];
+  int64_t total;
+  int64_t run = block_exscan(mine, sh, total);
+  for (int k = 0; k < per; ++k) {
+    const int t = threadIdx.x * per + k;
+    const int c = cnt[t];
+    if (v0 + t < n) rowptr[v0 + t] = lo + run;
+    cnt[t] = (int32_t)run;  // becomes the fill cursor of target t
+    run += c;
+  }
+  __syncthreads();
+  for (int64_t p = lo + threadIdx.x; p < hi; p += 256) {
+    const uint64_t u = T[p];
+    const int q = atomicAdd(&cnt[(int)(u >> 40) & (tb - 1)], 1);
+    col[lo + q] = (uint32_t)(u & IDMASK) | ((uint32_t)(u >> 36) & 1u) << 31;
+    colslot[lo + q] = (uint8_t)((u >> 30) & 63u);
+  }
+  if (b == nb - 1 && threadIdx.x == 0) rowptr[n] = hi;
 }
 
 // ---------------------------------------------------------------------------
@@ -1748,6 +1862,21 @@ static void launch_scan(const Ctx& c, int64_t a, int64_t b, int64_t* out) {
 
 hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
   const int64_t nK = c.n * c.K;
+  if (c.csr_T) {
+    const int nb = (int)((c.n + ((int64_t)1 << c.csr_shift) - 1) >> c.csr_shift);
+    const int chunk = (CSR_CHUNK / c.K) * c.K;
+    const unsigned blocks = (unsigned)((nK + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_zero_i64, dim3(grid_for(nb, 256, 64)), dim3(256), 0, c.stream, c.csr_bcount, (int64_t)nb);
+    hipLaunchKernelGGL(k_part_count, dim3(blocks), dim3(1024), 0, c.stream, F, nK, chunk, c.csr_shift, nb,
+                       (unsigned long long*)c.csr_bcount);
+    hipLaunchKernelGGL(k_exscan_small, dim3(1), dim3(256), 0, c.stream, (const unsigned long long*)c.csr_bcount,
+                       (int64_t)nb, c.csr_bbase, (unsigned long long*)c.csr_bfill);
+    hipLaunchKernelGGL(k_part_scatter, dim3(blocks), dim3(1024), 0, c.stream, F, nK, c.K, chunk, c.csr_shift, nb,
+                       c.csr_bbase, (unsigned long long*)c.csr_bfill, c.csr_T);
+    hipLaunchKernelGGL(k_bucket_csr, dim3((unsigned)nb), dim3(256), 0, c.stream, c.csr_T, c.csr_bbase, c.n,
+                       c.csr_shift, nb, c.rowptr, c.col, c.colslot);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.deg, c.n);
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.fill, c.n);
   hipLaunchKernelGGL(k_degree, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.deg);

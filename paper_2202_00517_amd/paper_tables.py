@@ -15,7 +15,12 @@ statistical FCR test, Dong et al.'s delta-proportion rule at two deltas, and
 the fixed point, each with its rounds, time to graph, evaluations and
 accuracy.
 
-    python -m paper_2202_00517_amd.paper_tables [--table 3|4|stop|all] [--json out.json]
+`--table cmp` runs the same workload under each comparator the library
+offers (Section 2.1: any per-point total order): rounds, time to graph,
+evaluations per second and accuracy against the exact search under the same
+comparator.
+
+    python -m paper_2202_00517_amd.paper_tables [--table 3|4|stop|cmp|all] [--json out.json]
 """
 import argparse
 import json
@@ -40,19 +45,19 @@ def _sample(seed, n, m):
     return synth.subsample(seed, n, m).astype(np.int32)
 
 
-def accuracy(idx, P, d, K, queries, kl_bound, torch):
+def accuracy(idx, P, d, K, queries, kl_bound, torch, comparator=0):
     """Mean share of the exact K nearest neighbours that the lists hold."""
     true_idx, _ = knnd.knnd_exact_knn(P, d, K, torch.from_numpy(queries).to(P.device),
-                                      tau=kl_bound, with_kl=False)
+                                      tau=kl_bound, with_kl=False, comparator=comparator)
     got = idx[torch.from_numpy(queries).to(P.device).long()].cpu().numpy()
     tru = true_idx.cpu().numpy()
     return float(np.mean([len(set(a.tolist()) & set(b.tolist())) / K for a, b in zip(got, tru)]))
 
 
-def run_row(n, coords, K, data_seed, seed, torch, precision, stop_rule=0, delta=0.0):
+def run_row(n, coords, K, data_seed, seed, torch, precision, stop_rule=0, delta=0.0, comparator=0):
     d = coords - 1
     P = torch.from_numpy(synth.dirichlet(data_seed, n, d, np.float32)).cuda()
-    prm = knnd.default_params(precision=precision, stop_rule=stop_rule, delta=delta)
+    prm = knnd.default_params(precision=precision, stop_rule=stop_rule, delta=delta, comparator=comparator)
     t = time.perf_counter()
     out = knnd.knnd_build_ex(P, d, K, seed, prm)
     torch.cuda.synchronize()
@@ -64,12 +69,13 @@ def run_row(n, coords, K, data_seed, seed, torch, precision, stop_rule=0, delta=
            "fcc": st[-1]["fcr_hits"] / M, "first_round_ms": round(st[1]["ms"], 2),
            "last_round_ms": round(st[-1]["ms"], 2), "time_to_graph_ms": round(1e3 * wall, 1),
            "evals_alg": int(sum(s["evals_alg"] for s in st)), "last_updates": int(st[-1]["updates"]),
-           "status": out["status"]}
+           "status": out["status"], "device_ms": round(sum(s["ms"] for s in st), 1)}
+    row["evals_per_s"] = row["evals_alg"] / (row["device_ms"] * 1e-3)
     idx, kl = out["idx"], out["kl"]
     for name, m in (("accuracy_6", 6), ("accuracy_2000", 2000)):
         q = _sample(seed + m, n, m)
         bound = kl[torch.from_numpy(q).to(P.device).long(), K - 1]
-        row[name] = round(accuracy(idx, P, d, K, q, bound, torch), 4)
+        row[name] = round(accuracy(idx, P, d, K, q, bound, torch, comparator), 4)
     del P, out
     torch.cuda.empty_cache()
     return row
@@ -113,6 +119,37 @@ def stop_rules(torch, precision, n=1000000, coords=21, K=30):
     return rows
 
 
+COMPARATORS = [("KL D(x||y)", knnd.KNND_CMP_KL), ("reverse KL D(y||x)", knnd.KNND_CMP_KL_REVERSE),
+               ("Hellinger", knnd.KNND_CMP_HELLINGER), ("Euclidean", knnd.KNND_CMP_L2)]
+
+
+def comparators(torch, n=1000000, coords=21, K=30):
+    """Every comparator in the FP64 form, and KL also in the requested mixed form."""
+    rows = []
+    for name, cmp in COMPARATORS:
+        for prec in ([knnd.KNND_PREC_FP64, knnd.KNND_PREC_MIXED_BF16] if cmp == knnd.KNND_CMP_KL
+                     else [knnd.KNND_PREC_FP64]):
+            r = run_row(n, coords, K, 5100, 5200, torch, prec, comparator=cmp)
+            r["comparator"] = name
+            r["precision"] = "split BF16 mixed" if prec else "FP64"
+            print(json.dumps(r), flush=True)
+            rows.append(r)
+    return rows
+
+
+def markdown_cmp(rows):
+    if not rows:
+        return ""
+    r0 = rows[0]
+    lines = [f"Comparators (n = {r0['n']:.0e}, {r0['coordinates']} coordinates, K = {r0['K']}):", "",
+             "| comparator | form | rounds | evaluations | device ms | evals/s | time to graph ms | accuracy 2000 pts |",
+             "|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {r['comparator']} | {r['precision']} | {r['rounds']} | {r['evals_alg']:.3e} | "
+                     f"{r['device_ms']} | {r['evals_per_s']:.3e} | {r['time_to_graph_ms']} | {r['accuracy_2000']:.4f} |")
+    return "\n".join(lines)
+
+
 def markdown_stop(rows):
     if not rows:
         return ""
@@ -151,7 +188,7 @@ def markdown(t3, t4):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--table", default="all", choices=["3", "4", "stop", "all"])
+    ap.add_argument("--table", default="all", choices=["3", "4", "stop", "cmp", "all"])
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "plain"])
     ap.add_argument("--json", default=None)
     args = ap.parse_args()
@@ -161,11 +198,13 @@ def main():
     t3 = table3(torch, prec) if args.table in ("3", "all") else []
     t4 = table4(torch, prec) if args.table in ("4", "all") else []
     sr = stop_rules(torch, prec) if args.table in ("stop", "all") else []
+    cr = comparators(torch) if args.table in ("cmp", "all") else []
     print(markdown(t3, t4), flush=True)
     print(markdown_stop(sr), flush=True)
+    print(markdown_cmp(cr), flush=True)
     if args.json:
         with open(args.json, "w") as f:
-            json.dump({"table3": t3, "table4": t4, "stop_rules": sr}, f, indent=1)
+            json.dump({"table3": t3, "table4": t4, "stop_rules": sr, "comparators": cr}, f, indent=1)
 
 
 if __name__ == "__main__":
