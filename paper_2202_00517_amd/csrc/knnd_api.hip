@@ -144,7 +144,7 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   if (e == hipSuccess) e = dalloc(&c.gtab, (size_t)c.gblocks * c.gstride);
   if (e == hipSuccess) e = dalloc(&c.gcand, (size_t)c.gblocks * (c.gstride / 2));
   if (e == hipSuccess) e = dalloc(&c.gckey, (size_t)c.gblocks * (c.gstride / 2));
-  c.bblocks = 2 * c.num_cu;
+  c.bblocks = 4 * c.num_cu;
   if (e == hipSuccess) e = dalloc(&c.bcand, (size_t)c.bblocks * knnd::BIG_CAND);
   if (e == hipSuccess) e = dalloc(&c.bckey, (size_t)c.bblocks * knnd::BIG_CAND);
   if (e == hipSuccess) e = dalloc(&c.dstats, (size_t)knnd::STAT_N);

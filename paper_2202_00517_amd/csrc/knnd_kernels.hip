@@ -1192,10 +1192,11 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
 
 // Occupancy targets: the tables of up to 2048 slots leave LDS for four blocks
 // per CU (receivers there have at most 1023 occurrences: four per thread in
-// flight cover them), the 4096-slot class for three.
+// flight cover them), the 4096- and 8192-slot classes for three (the latter
+// keeps its candidate list in global memory to fit).
 template <int CAP>
 constexpr int recv_waves_per_eu() {
-  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? 3 : 1);
+  return (CAP > 0 && CAP <= 2048) ? 4 : ((CAP == 4096 || CAP == 8192) ? 3 : 1);
 }
 
 template <int CAP, typename PT, int MODE, int NW>
@@ -1206,8 +1207,8 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   constexpr bool MIX = MODE == 2;  // cross terms from MFMA, exact keys only where needed
   constexpr int NT = NW * 64;
   constexpr bool GLOB = (CAP == 0);
-  constexpr bool BIG = (CAP > 8192);  // table in LDS, candidate list in global memory
-  constexpr bool GUARD = BIG;
+  constexpr bool BIG = (CAP >= 8192);  // table in LDS, candidate list in global memory
+  constexpr bool GUARD = CAP > 8192;   // optimistically sized table (see k_bin)
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
   constexpr int U = (GLOB || CAP <= 2048) ? 4 : 8;  // occurrences per thread in flight
@@ -1908,7 +1909,7 @@ static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
       per_cu = 1;
     }
     int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
-    if (CAP > 8192) grid = std::min(grid, c.bblocks);  // one global candidate region per block
+    if (CAP >= 8192) grid = std::min(grid, c.bblocks);  // one global candidate region per block
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.class_list, c.class_count, cls);
     return hipGetLastError();
   }
