@@ -459,8 +459,10 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
                                              int32_t* __restrict__ counts, int32_t* __restrict__ lists,
                                              const int32_t* __restrict__ inst_of,
                                              const int32_t* __restrict__ iactive) {
+  __shared__ int s_wcnt[NCLASS][4];
+  __shared__ int s_base[NCLASS];
   const int lane = lane_id();
-  // uniform trip count so that every lane takes part in the ballots
+  // uniform trip count so that every lane takes part in the ballots and barriers
   for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = x0 + threadIdx.x;
     int cls = -1;
@@ -485,14 +487,28 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
           cls = NCLASS - 1;
       }
     }
+    // one reservation per class and block: waves publish their counts, one
+    // thread per class reserves the block's range
+    const int wave = threadIdx.x >> 6;
+    uint64_t mk[NCLASS];
+#pragma unroll
     for (int k = 0; k < NCLASS; ++k) {
-      const uint64_t m = __ballot(cls == k);
-      if (!m) continue;
-      int base = 0;
-      if (lane == 0) base = atomicAdd(&counts[k], (int)__popcll(m));
-      base = __shfl(base, 0, WAVE);
-      if (cls == k) lists[(int64_t)k * n + base + (int)rank_in(m)] = (int32_t)x;
+      mk[k] = __ballot(cls == k);
+      if (lane == 0) s_wcnt[k][wave] = (int)__popcll(mk[k]);
     }
+    __syncthreads();
+    if (threadIdx.x < NCLASS) {
+      const int k = threadIdx.x;
+      const int tot = s_wcnt[k][0] + s_wcnt[k][1] + s_wcnt[k][2] + s_wcnt[k][3];
+      s_base[k] = tot ? atomicAdd(&counts[k], tot) : 0;
+    }
+    __syncthreads();
+    if (cls >= 0) {
+      int off = s_base[cls];
+      for (int w = 0; w < wave; ++w) off += s_wcnt[cls][w];
+      lists[(int64_t)cls * n + off + (int)rank_in(mk[cls])] = (int32_t)x;
+    }
+    __syncthreads();
   }
 }
 
@@ -1192,11 +1208,12 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
 
 // Occupancy targets: the tables of up to 2048 slots leave LDS for four blocks
 // per CU (receivers there have at most 1023 occurrences: four per thread in
-// flight cover them), the 4096- and 8192-slot classes for three (the latter
-// keeps its candidate list in global memory to fit).
+// flight cover them), the 4096-slot class for three, the 8192-slot class
+// (candidate list in global memory) for four with four occurrences per
+// thread in flight.
 template <int CAP>
 constexpr int recv_waves_per_eu() {
-  return (CAP > 0 && CAP <= 2048) ? 4 : ((CAP == 4096 || CAP == 8192) ? 3 : 1);
+  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? 3 : (CAP == 8192 ? 4 : 1));
 }
 
 template <int CAP, typename PT, int MODE, int NW>
@@ -1211,7 +1228,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   constexpr bool GUARD = CAP > 8192;   // optimistically sized table (see k_bin)
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
-  constexpr int U = (GLOB || CAP <= 2048) ? 4 : 8;  // occurrences per thread in flight
+  constexpr int U = (GLOB || CAP <= 2048 || CAP == 8192) ? 4 : 8;  // occurrences per thread in flight
   // a guarded class overshoots LIMIT by at most one batch (U per thread)
   static_assert(!BIG || LIMIT + U * NT <= BIG_CAND, "candidate list of the big classes too small");
   // occurrence counter: T < 2^32 in the LDS classes (their binning bounds
