@@ -42,8 +42,9 @@
  * or on scheduling.
  *
  * Threading: calls on distinct contexts/outputs may run concurrently.
- * Nothing is retained between calls except inside a knnd_ctx.  No C++
- * exception crosses this ABI.  On error, outputs are unspecified.
+ * Nothing is retained between calls except inside a knnd_ctx and the device
+ * memory cache (knnd_release_cache).  No C++ exception crosses this ABI.  On
+ * error, outputs are unspecified.
  */
 #ifndef KNND_H
 #define KNND_H
@@ -170,6 +171,16 @@ typedef struct {
 /* Fill *p with the defaults (FP64, F32 points, M = min(n,10000), 100 rounds,
    KNND_STOP_FCR, delta 0, KNND_CMP_KL, flags 0). */
 void knnd_default_params(knnd_params* p);
+
+/*
+ * Device memory.  Scratch blocks a finished call or a destroyed context
+ * gives back are kept in a per-process cache (per device, by rounded size,
+ * at most 64 GiB; the oldest are freed first) and reused by later calls, so
+ * that repeated calls skip hipMalloc and hipFree.  knnd_release_cache()
+ * returns every cached block to the device (blocks in use by live contexts
+ * stay).  Thread-safe; returns KNND_OK.
+ */
+int knnd_release_cache(void);
 
 /* Human-readable name of a knnd_status value (static storage). */
 const char* knnd_status_string(int status);

@@ -33,7 +33,7 @@ EXPORTED = [
     "knnd_default_params", "knnd_status_string", "knnd_abi_version", "knnd_build",
     "knnd_build_ex", "knnd_ctx_create", "knnd_ctx_init_graph", "knnd_ctx_set_graph",
     "knnd_ctx_round", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
-    "knnd_ctx_destroy", "knnd_build_batched", "knnd_exact_knn",
+    "knnd_ctx_destroy", "knnd_build_batched", "knnd_exact_knn", "knnd_release_cache",
 ]
 
 
@@ -105,6 +105,7 @@ def lib():
         "knnd_ctx_destroy": (ctypes.c_int, [vp]),
         "knnd_build_batched": (ctypes.c_int, [P(knnd_instance), i32, P(knnd_params), i32, vp]),
         "knnd_exact_knn": (ctypes.c_int, [vp, i64, i32, i32, i32, i32, vp, i64, vp, i32, vp, vp, vp]),
+        "knnd_release_cache": (ctypes.c_int, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -119,6 +120,11 @@ def lib():
 
 def status_string(status):
     return lib().knnd_status_string(status).decode()
+
+
+def release_cache():
+    """Return the library's cached device memory to the device."""
+    return lib().knnd_release_cache()
 
 
 def default_params(**kw):

@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -20,6 +22,108 @@
 struct knnd_ctx {
   knnd::Ctx c;
 };
+
+// ---------------------------------------------------------------------------
+// Device memory cache.  A descent uses a few gigabytes of scratch at n = 1e6,
+// and hipMalloc / hipFree of it cost several milliseconds per call; blocks a
+// finished call gives back are kept (per device, by rounded size) and handed
+// to later calls.  At most POOL_MAX_CACHED bytes stay cached (the oldest go
+// first); knnd_release_cache() returns all of them.  Thread-safe.
+// ---------------------------------------------------------------------------
+namespace knnd {
+namespace {
+struct PoolBlock {
+  void* p;
+  size_t bytes;
+  int dev;
+};
+std::mutex g_pool_mu;
+std::vector<PoolBlock> g_cached;
+std::unordered_map<void*, PoolBlock> g_live;
+size_t g_cached_bytes = 0;
+constexpr size_t POOL_MAX_CACHED = (size_t)64 << 30;
+
+// Sizes are rounded up (to 256 bytes, above 1 MiB to an eighth of their
+// power of two) so that calls of slightly different sizes share blocks.
+size_t pool_round(size_t b) {
+  if (b <= ((size_t)1 << 20)) return (b + 255) & ~(size_t)255;
+  size_t p = (size_t)1 << 20;
+  while (p < b) p <<= 1;
+  const size_t q = p / 8;
+  return (b + q - 1) / q * q;
+}
+
+void free_block(const PoolBlock& b) {
+  int cur = 0;
+  const bool other = hipGetDevice(&cur) == hipSuccess && cur != b.dev;
+  if (other) (void)hipSetDevice(b.dev);
+  (void)hipFree(b.p);
+  if (other) (void)hipSetDevice(cur);
+}
+}  // namespace
+
+hipError_t pool_malloc(void** out, size_t bytes) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const size_t rb = pool_round(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (size_t i = 0; i < g_cached.size(); ++i) {
+      if (g_cached[i].dev == dev && g_cached[i].bytes == rb) {
+        const PoolBlock b = g_cached[i];
+        g_cached.erase(g_cached.begin() + (std::ptrdiff_t)i);
+        g_cached_bytes -= rb;
+        g_live.emplace(b.p, b);
+        *out = b.p;
+        return hipSuccess;
+      }
+    }
+  }
+  void* p = nullptr;
+  e = hipMalloc(&p, rb);
+  if (e == hipErrorOutOfMemory) {  // give the cached blocks back and try once more
+    (void)hipGetLastError();
+    pool_release();
+    e = hipMalloc(&p, rb);
+  }
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_live.emplace(p, PoolBlock{p, rb, dev});
+  *out = p;
+  return hipSuccess;
+}
+
+void pool_free(void* p) {
+  if (!p) return;
+  std::vector<PoolBlock> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;  // (every library block comes from pool_malloc)
+    g_cached.push_back(it->second);
+    g_cached_bytes += it->second.bytes;
+    g_live.erase(it);
+    while (g_cached_bytes > POOL_MAX_CACHED && !g_cached.empty()) {
+      drop.push_back(g_cached.front());
+      g_cached_bytes -= g_cached.front().bytes;
+      g_cached.erase(g_cached.begin());
+    }
+  }
+  for (const PoolBlock& b : drop) free_block(b);
+}
+
+void pool_release() {
+  std::vector<PoolBlock> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    drop.swap(g_cached);
+    g_cached_bytes = 0;
+  }
+  for (const PoolBlock& b : drop) free_block(b);
+}
+}  // namespace knnd
 
 namespace {
 
@@ -35,7 +139,7 @@ int map_err(hipError_t e) { return e == hipErrorOutOfMemory ? KNND_ERR_NOMEM : K
 
 template <class T>
 hipError_t dalloc(T** p, size_t count) {
-  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T) + 16);
+  return knnd::pmalloc(p, count * sizeof(T) + 16);
 }
 
 void free_ctx(Ctx& c) {
@@ -45,8 +149,9 @@ void free_ctx(Ctx& c) {
                   c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32,
                   c.inst_of, c.ioff, c.iseed, c.iM, c.iD, c.iactive, c.istats, c.vcnt,
                   c.sl_n, c.sl_id, c.sl_key, c.csr_T, c.csr_bcount, c.csr_bfill, c.csr_bbase};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+  // the blocks go back to the cache: the context's work must have finished
+  (void)hipStreamSynchronize(c.stream);
+  for (void* b : bufs) knnd::pool_free(b);
   if (c.hstats) (void)hipHostFree(c.hstats);
   if (c.histats) (void)hipHostFree(c.histats);
   if (c.ev0) (void)hipEventDestroy(c.ev0);
@@ -117,7 +222,7 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   c.gblocks = 32;
   c.gstride = next_pow2(2 * n) < 1024 ? 1024 : next_pow2(2 * n);
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = hipMalloc(&c.P, ((size_t)n * c.D + knnd::HUB_MAXD) * esz);
+  if (e == hipSuccess) e = knnd::pmalloc(&c.P, ((size_t)n * c.D + knnd::HUB_MAXD) * esz);
   if (e == hipSuccess) e = dalloc(&c.L, (size_t)n * c.Dp + knnd::HUB_MAXD);
   for (int b = 0; b < 2; ++b) {
     if (e == hipSuccess) e = dalloc(&c.F[b], nK);
@@ -165,8 +270,8 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   if (c.mixed) {
     c.dk = c.D <= 32 ? 32 : 64;
     // rows of 2 dk 16-bit values: dk high parts, then dk low parts
-    if (e == hipSuccess) e = hipMalloc(&c.Ph, (size_t)n * c.dk * 4 + 64);
-    if (e == hipSuccess) e = hipMalloc(&c.Lh, (size_t)n * c.dk * 4 + 64);
+    if (e == hipSuccess) e = knnd::pmalloc(&c.Ph, (size_t)n * c.dk * 4 + 64);
+    if (e == hipSuccess) e = knnd::pmalloc(&c.Lh, (size_t)n * c.dk * 4 + 64);
     if (e == hipSuccess) e = dalloc(&c.S, (size_t)n);
     if (e == hipSuccess && dalloc(&c.seg32, nK * (size_t)(2 * K + 1)) != hipSuccess) {
       (void)hipGetLastError();
@@ -252,12 +357,13 @@ int prepare_mixed(Ctx& c, size_t nK) {
   if (!(pmax <= 1.0) || !(lmax <= range)) {
     // fall back to the exact hub form
     c.mixed = false;
-    (void)hipFree(c.seg32);
+    (void)hipStreamSynchronize(c.stream);
+    knnd::pool_free(c.seg32);
     c.seg32 = nullptr;
     if (dalloc(&c.seg, nK * (size_t)(2 * c.K + 1)) != hipSuccess ||
         dalloc(&c.sl_key, (size_t)c.n * knnd::SHORT_LIST) != hipSuccess) {
       (void)hipGetLastError();
-      (void)hipFree(c.seg);
+      knnd::pool_free(c.seg);
       c.seg = nullptr;
       c.use_hub = false;  // pull form: needs neither
     }
@@ -390,7 +496,8 @@ struct Group {
 };
 
 void free_group(Group& g) {
-  if (g.staging) (void)hipFree(g.staging);
+  (void)hipStreamSynchronize(g.c.stream);
+  knnd::pool_free(g.staging);
   g.staging = nullptr;
   free_ctx(g.c);
 }
@@ -458,7 +565,7 @@ int create_group(Group& g, const knnd_instance* inst, const knnd_params& prm, in
   if (!on_device) {
     size_t most = 0;
     for (int j = 0; j < nb; ++j) most = std::max(most, (size_t)inst[g.members[j]].n * (inst[g.members[j]].d + 1));
-    KNND_HIP(hipMalloc(&stage, most * esz));
+    KNND_HIP(knnd::pool_malloc(&stage, most * esz));
   }
   int rc = KNND_OK;
   for (int j = 0; j < nb && rc == KNND_OK; ++j) {
@@ -477,7 +584,7 @@ int create_group(Group& g, const knnd_instance* inst, const knnd_params& prm, in
   }
   if (stage) {
     const hipError_t e3 = hipStreamSynchronize(c.stream);
-    (void)hipFree(stage);
+    knnd::pool_free(stage);
     if (rc == KNND_OK && e3 != hipSuccess) rc = map_err(e3);
   }
   if (rc != KNND_OK) return rc;
@@ -648,6 +755,11 @@ const char* knnd_status_string(int s) {
 }
 
 int knnd_abi_version(void) { return KNND_ABI_VERSION; }
+
+int knnd_release_cache(void) {
+  knnd::pool_release();
+  return KNND_OK;
+}
 
 int knnd_ctx_create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,
                     int32_t on_device, void* stream, knnd_ctx** out) {

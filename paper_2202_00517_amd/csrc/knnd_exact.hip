@@ -300,10 +300,11 @@ struct XBufs {
   int32_t* idx = nullptr;
   double* kl = nullptr;
   int32_t* flag = nullptr;
+  hipStream_t st = nullptr;
   ~XBufs() {
     void* b[] = {P, L, q, tau, tk, ti, ck, ci, cnt, sel, idx, kl, flag};
-    for (void* p : b)
-      if (p) (void)hipFree(p);
+    (void)hipStreamSynchronize(st);  // the blocks go back to the cache
+    for (void* p : b) knnd::pool_free(p);
   }
 };
 
@@ -316,19 +317,20 @@ int exact_knn(const void* points, int64_t n, int32_t d, int32_t K, int tk, const
   const hipMemcpyKind h2d = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   const hipMemcpyKind d2h = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   XBufs b;
-  KNND_XHIP(hipMalloc(&b.P, ((size_t)n * D + HUB_MAXD) * esz));
-  KNND_XHIP(hipMalloc(&b.L, ((size_t)n * Dp + HUB_MAXD) * 8));
-  KNND_XHIP(hipMalloc(&b.q, (size_t)nq * 4));
-  KNND_XHIP(hipMalloc(&b.tk, (size_t)nq * 8));
-  KNND_XHIP(hipMalloc(&b.ti, (size_t)nq * 4));
-  KNND_XHIP(hipMalloc(&b.ck, (size_t)nq * XCAP * 8));
-  KNND_XHIP(hipMalloc(&b.ci, (size_t)nq * XCAP * 4));
-  KNND_XHIP(hipMalloc(&b.cnt, (size_t)nq * 4));
-  KNND_XHIP(hipMalloc(&b.sel, (size_t)nq * 4));
-  KNND_XHIP(hipMalloc(&b.flag, 16));
+  b.st = st;
+  KNND_XHIP(knnd::pmalloc(&b.P, ((size_t)n * D + HUB_MAXD) * esz));
+  KNND_XHIP(knnd::pmalloc(&b.L, ((size_t)n * Dp + HUB_MAXD) * 8));
+  KNND_XHIP(knnd::pmalloc(&b.q, (size_t)nq * 4));
+  KNND_XHIP(knnd::pmalloc(&b.tk, (size_t)nq * 8));
+  KNND_XHIP(knnd::pmalloc(&b.ti, (size_t)nq * 4));
+  KNND_XHIP(knnd::pmalloc(&b.ck, (size_t)nq * XCAP * 8));
+  KNND_XHIP(knnd::pmalloc(&b.ci, (size_t)nq * XCAP * 4));
+  KNND_XHIP(knnd::pmalloc(&b.cnt, (size_t)nq * 4));
+  KNND_XHIP(knnd::pmalloc(&b.sel, (size_t)nq * 4));
+  KNND_XHIP(knnd::pmalloc(&b.flag, 16));
   if (!on_device) {
-    KNND_XHIP(hipMalloc(&b.idx, (size_t)nq * K * 4));
-    if (out_kl) KNND_XHIP(hipMalloc(&b.kl, (size_t)nq * K * 8));
+    KNND_XHIP(knnd::pmalloc(&b.idx, (size_t)nq * K * 4));
+    if (out_kl) KNND_XHIP(knnd::pmalloc(&b.kl, (size_t)nq * K * 8));
   }
   int32_t* didx = on_device ? out_idx : b.idx;
   double* dkl = on_device ? out_kl : b.kl;
@@ -361,7 +363,7 @@ int exact_knn(const void* points, int64_t n, int32_t d, int32_t K, int tk, const
 
   const unsigned qblocks = (unsigned)((nq + XQ - 1) / XQ);
   if (tau) {
-    KNND_XHIP(hipMalloc(&b.tau, (size_t)nq * 8));
+    KNND_XHIP(knnd::pmalloc(&b.tau, (size_t)nq * 8));
     KNND_XHIP(hipMemcpyAsync(b.tau, tau, (size_t)nq * 8, h2d, st));
     hipLaunchKernelGGL(k_bound_from_keys, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, b.tau, nq, b.tk,
                        b.ti);

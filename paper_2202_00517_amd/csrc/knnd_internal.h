@@ -155,6 +155,18 @@ struct JoinArgs {
   double* sl_key;
 };
 
+// Device memory of the library comes from a per-process cache of freed
+// blocks (see knnd_release_cache): pool_malloc and pool_free stand in for
+// hipMalloc and hipFree.  A block goes back to the cache only after the work
+// using it has finished (callers synchronise its stream first).
+hipError_t pool_malloc(void** p, size_t bytes);
+void pool_free(void* p);
+void pool_release();
+template <class T>
+hipError_t pmalloc(T** p, size_t bytes) {
+  return pool_malloc(reinterpret_cast<void**>(p), bytes);
+}
+
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_log_table(const Ctx& c, int32_t* bad);
 hipError_t launch_init_graph(const Ctx& c);

@@ -706,3 +706,27 @@ def test_comparator_exact_knn_matches_oracle(n, d, K, dtype, cmp):
     P64 = oracle.widen(P)
     oi, ok = oracle.bruteforce(P64, oracle.log_table(P64), K, qs.astype(np.int64), cmp=cmp)
     assert_same_graph(ei, ek, oi, ok, "exact knn")
+
+
+# ---------------------------------------------------------------------------
+# Device memory cache: reused blocks hold stale data from earlier calls;
+# results must not depend on it.
+# ---------------------------------------------------------------------------
+def test_memory_cache_reuse_and_release():
+    P = synth.dirichlet(31, 20000, 10, np.float32)
+    Q = synth.dirichlet(32, 20000, 10, np.float32)
+    prm = knnd.default_params(precision=knnd.KNND_PREC_MIXED_BF16)
+    say("cache: build P, build Q (reusing P's blocks), release, build P again")
+    a = knnd.knnd_build_ex(P, 10, 20, 5, prm)
+    b = knnd.knnd_build_ex(Q, 10, 20, 5, prm)
+    assert knnd.release_cache() == knnd.KNND_OK
+    c = knnd.knnd_build_ex(P, 10, 20, 5, prm)
+    o = oracle.build_graph(Q, 10, 20, 5)
+    assert_same_graph(b["idx"], b["kl"], o.idx, o.keys, "second build")
+    assert np.array_equal(a["idx"], c["idx"]) and np.array_equal(bits(a["kl"]), bits(c["kl"]))
+    # a smaller build then a larger one on reused blocks
+    d = knnd.knnd_build_ex(P[:5000], 10, 20, 5, prm)
+    e = knnd.knnd_build_ex(P, 10, 20, 5, prm)
+    o = oracle.build_graph(P[:5000], 10, 20, 5)
+    assert_same_graph(d["idx"], d["kl"], o.idx, o.keys, "small build")
+    assert np.array_equal(a["idx"], e["idx"])
