@@ -260,7 +260,7 @@ int knnd_build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int
 
 /*
  * Exact K nearest neighbours of query points by exhaustive comparison (the
- * problem of Section 2.3 solved directly; the accuracy measure of Section 4.3
+ * problem of Section 2.3 solved directly; the accuracy measure of Section 4.4
  * compares a descent's lists with these).  For query point q every other
  * point p is ranked by the same canonical key k(q, p) of the comparator
  * (knnd_comparator; KNND_CMP_KL: D(q||p)) and (key, index) order as the

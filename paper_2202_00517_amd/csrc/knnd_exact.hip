@@ -1,6 +1,6 @@
 // Exact K nearest neighbours of query points by exhaustive comparison: the
 // problem statement itself (Section 2.3), used to measure the descent's
-// accuracy (Section 4.3: the share of true nearest neighbours found).
+// accuracy (Section 4.4: the share of true nearest neighbours found).
 //
 // For each query q every other point p gets its canonical key k(q, p) under
 // the comparator (the same FP64 fold as the descent; D(q||p) for KL) and the
