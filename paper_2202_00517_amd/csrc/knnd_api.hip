@@ -206,6 +206,8 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   c.Dp = (c.D + 1) & ~1;
   c.Ds = c.D | 1;  // odd LDS row stride (in doubles) for conflict-free column reads
   c.K = K;
+  c.Ks = 8;
+  while (c.Ks < K) c.Ks <<= 1;
   c.seed = seed;
   c.dtype = prm.dtype;
   c.precision = prm.precision;
@@ -225,7 +227,7 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   if (e == hipSuccess) e = knnd::pmalloc(&c.P, ((size_t)n * c.D + knnd::HUB_MAXD) * esz);
   if (e == hipSuccess) e = dalloc(&c.L, (size_t)n * c.Dp + knnd::HUB_MAXD);
   for (int b = 0; b < 2; ++b) {
-    if (e == hipSuccess) e = dalloc(&c.F[b], nK);
+    if (e == hipSuccess) e = dalloc(&c.F[b], (size_t)n * c.Ks);
     if (e == hipSuccess) e = dalloc(&c.keys[b], nK);
   }
   if (e == hipSuccess) e = dalloc(&c.deg, (size_t)n);
@@ -262,7 +264,7 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   if (e == hipSuccess) e = hipEventCreate(&c.evh);
   if (e != hipSuccess) return map_err(e);
   // Hub form: candidate rows of a hub must fit in LDS, and the key slots
-  // (K(2K+1) per point) must fit in memory; otherwise the pull form.  The
+  // (K(K+Ks+1) per point) must fit in memory; otherwise the pull form.  The
   // mixed-precision form needs the hub form, D <= 64 (MFMA K dimension) and
   // the KL comparator (its error bound is derived for that key).
   c.use_hub = !(c.flags & KNND_FLAG_PULL) && (size_t)(K + 1) * c.Ds * sizeof(double) <= 64 * 1024;
@@ -273,13 +275,13 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
     if (e == hipSuccess) e = knnd::pmalloc(&c.Ph, (size_t)n * c.dk * 4 + 64);
     if (e == hipSuccess) e = knnd::pmalloc(&c.Lh, (size_t)n * c.dk * 4 + 64);
     if (e == hipSuccess) e = dalloc(&c.S, (size_t)n);
-    if (e == hipSuccess && dalloc(&c.seg32, nK * (size_t)(2 * K + 1)) != hipSuccess) {
+    if (e == hipSuccess && dalloc(&c.seg32, nK * (size_t)(K + c.Ks + 1)) != hipSuccess) {
       (void)hipGetLastError();
       c.mixed = false;
     }
     if (e != hipSuccess) return map_err(e);
   }
-  if (c.use_hub && !c.mixed && dalloc(&c.seg, nK * (size_t)(2 * K + 1)) != hipSuccess) {
+  if (c.use_hub && !c.mixed && dalloc(&c.seg, nK * (size_t)(K + c.Ks + 1)) != hipSuccess) {
     (void)hipGetLastError();
     c.seg = nullptr;
     c.use_hub = false;
@@ -360,7 +362,7 @@ int prepare_mixed(Ctx& c, size_t nK) {
     (void)hipStreamSynchronize(c.stream);
     knnd::pool_free(c.seg32);
     c.seg32 = nullptr;
-    if (dalloc(&c.seg, nK * (size_t)(2 * c.K + 1)) != hipSuccess ||
+    if (dalloc(&c.seg, nK * (size_t)(c.K + c.Ks + 1)) != hipSuccess ||
         dalloc(&c.sl_key, (size_t)c.n * knnd::SHORT_LIST) != hipSuccess) {
       (void)hipGetLastError();
       knnd::pool_free(c.seg);

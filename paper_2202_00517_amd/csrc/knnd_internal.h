@@ -59,7 +59,10 @@ struct Ctx {
   // device buffers
   void* P = nullptr;          // [n][D] points (copy owned by the context)
   double* L = nullptr;        // [n][Dp] feature table (log x for the KL comparators)
+  // F rows have stride Ks, the power of two >= max(K, 8): a row never
+  // straddles more cache lines than its size needs
   uint32_t* F[2] = {nullptr, nullptr};
+  int Ks = 0;
   double* keys[2] = {nullptr, nullptr};
   int cur = 0;                // F[cur], keys[cur] hold the current snapshot
   int32_t* deg = nullptr;     // [n]
@@ -67,14 +70,14 @@ struct Ctx {
   int64_t* rowptr = nullptr;  // [n+1]
   uint32_t* col = nullptr;    // [nK]
   uint8_t* colslot = nullptr; // [nK] slot of the edge in its source's list
-  double* seg = nullptr;      // [nK(2K+1)] candidate keys by snapshot edge (hub form)
+  double* seg = nullptr;      // [nK(K+Ks+1)] candidate keys by snapshot edge (hub form)
   // mixed precision
   bool mixed = false;
   int dk = 0;                 // D padded to 32 or 64 (MFMA K dimension)
   void* Ph = nullptr;         // [n][2 dk] x split in 16-bit high and low parts (rows: dk high, dk low)
   void* Lh = nullptr;         // [n][2 dk] the same split of L
   double* S = nullptr;        // [n] sum_i x_i log x_i
-  float* seg32 = nullptr;     // [nK(2K+1)] cross terms C~ by snapshot edge
+  float* seg32 = nullptr;     // [nK(K+Ks+1)] cross terms C~ by snapshot edge
   double eps_relq = 0.0, eps_abs = 0.0;  // mixed-form error bound: e_rel / (1 - e_rel) and e_abs
   bool use_hub = false;
   // short candidate lists handed from the receiver kernel to k_merge (hub form)
@@ -130,7 +133,9 @@ struct JoinArgs {
   const int64_t* rowptr;
   const uint32_t* col;
   const uint8_t* colslot;
-  int64_t nKK;  // n*K*K: offset of the FC part of seg (DI part at 2nKK)
+  int64_t nKK;     // n*K*K: offset of the FC part of seg
+  int64_t di_off;  // n*K*(K+Ks): offset of the DI part of seg
+  int Ks;          // row stride of F (and of the FC blocks of seg)
   const float* seg32;
   const double* S;
   double eps_relq, eps_abs;

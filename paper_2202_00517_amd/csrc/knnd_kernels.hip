@@ -31,20 +31,23 @@ __global__ void k_zero_i64(int64_t* p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
 }
-// out = F without flag bits
-__global__ void k_strip(const uint32_t* __restrict__ F, int64_t cnt, int32_t* __restrict__ out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = (int32_t)(F[i] & IDMASK);
+// out [n][K] = F (rows of stride Ks) without flag bits
+__global__ void k_strip(const uint32_t* __restrict__ F, int64_t cnt, int K, int Ks, int32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = i / K;
+    out[i] = (int32_t)(F[x * Ks + (i - x * K)] & IDMASK);
+  }
 }
 // F = idx | NEWBIT (an externally supplied snapshot: every edge counts as
 // new).  An index outside [0, n) is replaced by 0 and counted in *bad.
-__global__ void k_load_idx(const int32_t* __restrict__ idx, int64_t cnt, int64_t n, uint32_t* __restrict__ F,
-                           int32_t* __restrict__ bad) {
+__global__ void k_load_idx(const int32_t* __restrict__ idx, int64_t cnt, int64_t n, int K, int Ks,
+                           uint32_t* __restrict__ F, int32_t* __restrict__ bad) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = idx[i];
     const bool ok = v >= 0 && (int64_t)v < n;
     if (!ok) atomicOr(bad, 1);
-    F[i] = ((uint32_t)(ok ? v : 0)) | NEWBIT;
+    const int64_t x = i / K;
+    F[x * Ks + (i - x * K)] = ((uint32_t)(ok ? v : 0)) | NEWBIT;
   }
 }
 
@@ -98,7 +101,7 @@ __global__ void k_log_table(const PT* __restrict__ P, int64_t n, int D, int Dp, 
 // ---------------------------------------------------------------------------
 template <typename PT, int CK>
 __global__ __launch_bounds__(256) void k_init_graph(const PT* __restrict__ P, const double* __restrict__ L,
-                                                    int64_t n, int D, int Dp, int K, uint64_t seed,
+                                                    int64_t n, int D, int Dp, int K, int Ks, uint64_t seed,
                                                     uint32_t* __restrict__ F, double* __restrict__ keys,
                                                     const int32_t* __restrict__ inst_of,
                                                     const int64_t* __restrict__ ioff,
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(256) void k_init_graph(const PT* __restrict__ P, co
   }
   wave_sort(kb, id);
   if (lane < K) {
-    F[x * K + lane] = id | NEWBIT;
+    F[x * Ks + lane] = id | NEWBIT;
     keys[x * K + lane] = bits_key(kb);
   }
 }
@@ -155,7 +158,7 @@ __global__ __launch_bounds__(256) void k_init_graph(const PT* __restrict__ P, co
 // ---------------------------------------------------------------------------
 // a6: friend clustering rate sample (Section 3.3), one thread per sample.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fcr(const uint32_t* __restrict__ F, int64_t n, int K, uint64_t seed,
+__global__ __launch_bounds__(256) void k_fcr(const uint32_t* __restrict__ F, int64_t n, int K, int Ks, uint64_t seed,
                                              int64_t round, int64_t M, int64_t* __restrict__ hits) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   bool hit = false;
@@ -164,10 +167,10 @@ __global__ __launch_bounds__(256) void k_fcr(const uint32_t* __restrict__ F, int
     const int av = (int)bound(hash4(seed, 3, (uint64_t)round, (uint64_t)s), (uint64_t)K);
     const int bp = (int)bound(hash4(seed, 4, (uint64_t)round, (uint64_t)s), (uint64_t)(K - 1));
     const int bv = bp + (bp >= av ? 1 : 0);
-    const uint32_t y = F[x * K + av] & IDMASK;
-    const uint32_t z = F[x * K + bv] & IDMASK;
+    const uint32_t y = F[x * Ks + av] & IDMASK;
+    const uint32_t z = F[x * Ks + bv] & IDMASK;
     for (int j = 0; j < K; ++j)
-      hit |= ((F[(int64_t)z * K + j] & IDMASK) == y) || ((F[(int64_t)y * K + j] & IDMASK) == z);
+      hit |= ((F[(int64_t)z * Ks + j] & IDMASK) == y) || ((F[(int64_t)y * Ks + j] & IDMASK) == z);
   }
   const uint64_t m = __ballot(hit);
   if (lane_id() == 0 && m) atomicAdd((unsigned long long*)hits, (unsigned long long)__popcll(m));
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(256) void k_fcr(const uint32_t* __restrict__ F, int
 
 // The same sample for every active instance of a batched group (grid y =
 // instance), in the instance's own indices and seed.
-__global__ __launch_bounds__(256) void k_fcr_batched(const uint32_t* __restrict__ F, int K,
+__global__ __launch_bounds__(256) void k_fcr_batched(const uint32_t* __restrict__ F, int K, int Ks,
                                                      const int64_t* __restrict__ ioff,
                                                      const uint64_t* __restrict__ iseed,
                                                      const int64_t* __restrict__ iM,
@@ -192,10 +195,10 @@ __global__ __launch_bounds__(256) void k_fcr_batched(const uint32_t* __restrict_
     const int av = (int)bound(hash4(seed, 3, (uint64_t)round, (uint64_t)s), (uint64_t)K);
     const int bp = (int)bound(hash4(seed, 4, (uint64_t)round, (uint64_t)s), (uint64_t)(K - 1));
     const int bv = bp + (bp >= av ? 1 : 0);
-    const uint32_t y = F[x * K + av] & IDMASK;
-    const uint32_t z = F[x * K + bv] & IDMASK;
+    const uint32_t y = F[x * Ks + av] & IDMASK;
+    const uint32_t z = F[x * Ks + bv] & IDMASK;
     for (int j = 0; j < K; ++j)
-      hit |= ((F[(int64_t)z * K + j] & IDMASK) == y) || ((F[(int64_t)y * K + j] & IDMASK) == z);
+      hit |= ((F[(int64_t)z * Ks + j] & IDMASK) == y) || ((F[(int64_t)y * Ks + j] & IDMASK) == z);
   }
   const uint64_t m = __ballot(hit);
   if (lane_id() == 0 && m)
@@ -236,9 +239,12 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const int32_t* __restrict_
 }
 
 // Rows [off, off + nb) of the lists, as indices local to their instance.
-__global__ void k_emit(const uint32_t* __restrict__ F, int64_t off, int64_t cnt, int K, int32_t* __restrict__ out) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cnt; t += (int64_t)gridDim.x * blockDim.x)
-    out[t] = (int32_t)((int64_t)(F[off * K + t] & IDMASK) - off);
+__global__ void k_emit(const uint32_t* __restrict__ F, int64_t off, int64_t cnt, int K, int Ks,
+                       int32_t* __restrict__ out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cnt; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t xl = t / K;
+    out[t] = (int32_t)((int64_t)(F[(off + xl) * Ks + (t - xl * K)] & IDMASK) - off);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -246,9 +252,11 @@ __global__ void k_emit(const uint32_t* __restrict__ F, int64_t off, int64_t cnt,
 // scatter.  The order inside a co-friend list is arbitrary (the round's result
 // does not depend on it).
 // ---------------------------------------------------------------------------
-__global__ void k_degree(const uint32_t* __restrict__ F, int64_t nK, int32_t* __restrict__ deg) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&deg[F[e] & IDMASK], 1);
+__global__ void k_degree(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks, int32_t* __restrict__ deg) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = e / K;
+    atomicAdd(&deg[F[x * Ks + (e - x * K)] & IDMASK], 1);
+  }
 }
 
 constexpr int SCAN_ITEMS = 8;
@@ -319,14 +327,15 @@ __global__ void k_scan_add(int64_t* __restrict__ rowptr, int64_t n, const int64_
 
 // Edge e = x*K + j (x -> v = F[x][j]) lands at position q of coF(v):
 // col[rowptr[v] + q] = x | new-flag, colslot[...] = j.
-__global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, const int64_t* __restrict__ rowptr,
-                          int32_t* __restrict__ fill, uint32_t* __restrict__ col, uint8_t* __restrict__ colslot) {
+__global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks,
+                          const int64_t* __restrict__ rowptr, int32_t* __restrict__ fill, uint32_t* __restrict__ col,
+                          uint8_t* __restrict__ colslot) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t raw = F[e];
+    const int64_t x = e / K;
+    const uint32_t raw = F[x * Ks + (e - x * K)];
     const uint32_t v = raw & IDMASK;
     const int q = atomicAdd(&fill[v], 1);
     const int64_t pos = rowptr[v] + q;
-    const int64_t x = e / K;
     col[pos] = (uint32_t)x | (raw & NEWBIT);
     colslot[pos] = (uint8_t)(e - x * K);
   }
@@ -342,14 +351,25 @@ __global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, con
 // (40-52).  Within a segment the order of co-friends is arbitrary (as with
 // the atomic scatter); nothing depends on it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_part_count(const uint32_t* __restrict__ F, int64_t nK, int chunk,
-                                                     int shift, int nb, unsigned long long* __restrict__ bcount) {
+// Edge e = x*K + j of a chunk (chunk is a multiple of K) is F[x*Ks + j].
+__device__ __forceinline__ uint32_t edge_raw(const uint32_t* __restrict__ F, int64_t e0, int64_t x0, int64_t e,
+                                             int K, int Ks) {
+  const uint32_t r = (uint32_t)(e - e0);
+  const uint32_t xr = r / (uint32_t)K;
+  return F[(x0 + xr) * Ks + (r - xr * (uint32_t)K)];
+}
+
+__global__ __launch_bounds__(1024) void k_part_count(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks,
+                                                     int chunk, int shift, int nb,
+                                                     unsigned long long* __restrict__ bcount) {
   __shared__ int32_t h[CSR_MAXB];
   for (int t = threadIdx.x; t < nb; t += blockDim.x) h[t] = 0;
   __syncthreads();
   const int64_t e0 = (int64_t)blockIdx.x * chunk;
   const int64_t e1 = min(e0 + chunk, nK);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&h[(F[e] & IDMASK) >> shift], 1);
+  const int64_t x0 = e0 / K;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+    atomicAdd(&h[(edge_raw(F, e0, x0, e, K, Ks) & IDMASK) >> shift], 1);
   __syncthreads();
   for (int t = threadIdx.x; t < nb; t += blockDim.x)
     if (h[t]) atomicAdd(&bcount[t], (unsigned long long)h[t]);
@@ -376,7 +396,7 @@ __global__ __launch_bounds__(256) void k_exscan_small(const unsigned long long* 
   if (threadIdx.x == 0) out[m] = carry;
 }
 
-__global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restrict__ F, int64_t nK, int K,
+__global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks,
                                                        int chunk, int shift, int nb,
                                                        const int64_t* __restrict__ bbase,
                                                        unsigned long long* __restrict__ bfill,
@@ -387,17 +407,18 @@ __global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restric
   __syncthreads();
   const int64_t e0 = (int64_t)blockIdx.x * chunk;  // chunk is a multiple of K
   const int64_t e1 = min(e0 + chunk, nK);
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&h[(F[e] & IDMASK) >> shift], 1);
+  const int64_t x0 = e0 / K;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+    atomicAdd(&h[(edge_raw(F, e0, x0, e, K, Ks) & IDMASK) >> shift], 1);
   __syncthreads();
   for (int t = threadIdx.x; t < nb; t += blockDim.x) {
     if (h[t]) base[t] = bbase[t] + (int64_t)atomicAdd(&bfill[t], (unsigned long long)h[t]);
     h[t] = 0;
   }
   __syncthreads();
-  const int64_t x0 = e0 / K;
   const uint32_t tmask = (1u << shift) - 1;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const uint32_t raw = F[e];
+    const uint32_t raw = edge_raw(F, e0, x0, e, K, Ks);
     const uint32_t v = raw & IDMASK;
     const int b = (int)(v >> shift);
     const int q = atomicAdd(&h[b], 1);
@@ -581,7 +602,7 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
     const int cv = (int)(a.rowptr[v + 1] - rp);
     bool anynew = !a.skip;
     if (tid < K) {
-      const uint32_t e = a.F[v * K + tid];
+      const uint32_t e = a.F[v * a.Ks + tid];
       s_fv[tid] = e;
       anynew |= (e & NEWBIT) != 0;
     }
@@ -611,8 +632,8 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
         r = e & IDMASK;
         rnew = e & NEWBIT;
         excl = sp;
-        b0 = a.nKK + (v * K + sp) * K;  // FC
-        b1 = 2 * a.nKK + v * K + sp;    // DI
+        b0 = a.nKK + (v * K + sp) * a.Ks;  // FC
+        b1 = a.di_off + v * K + sp;        // DI
       }
       const PT* pr = P + r * D;
       const double* lr = a.L + r * Dp;
@@ -710,7 +731,7 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
     const int64_t pf0 = my_perf;
     const int64_t rp = a.rowptr[v];
     const int cv = (int)(a.rowptr[v + 1] - rp);
-    const uint32_t fv = lane < K ? a.F[v * K + lane] : 0u;  // lane j holds F(v)[j]
+    const uint32_t fv = lane < K ? a.F[v * a.Ks + lane] : 0u;  // lane j holds F(v)[j]
     const uint64_t cand_new = __ballot((fv & NEWBIT) != 0);
     const int nR = cv + K;
     for (int k0 = 0; k0 < nR; k0 += WAVE) {
@@ -732,8 +753,8 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
           r = fsp & IDMASK;
           rnew = fsp & NEWBIT;
           excl = sp;
-          b0 = a.nKK + (v * K + sp) * K;  // FC
-          b1 = 2 * a.nKK + v * K + sp;    // DI
+          b0 = a.nKK + (v * K + sp) * a.Ks;  // FC
+          b1 = a.di_off + v * K + sp;        // DI
         }
       }
       // which of this receiver's K+1 candidate slots need a key (bit ci)
@@ -888,7 +909,7 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
     const int64_t pf0 = my_perf;
     const int64_t rp = a.rowptr[v];
     const int cv = (int)(a.rowptr[v + 1] - rp);
-    const uint32_t fv = lane < K ? a.F[v * K + lane] : 0u;
+    const uint32_t fv = lane < K ? a.F[v * a.Ks + lane] : 0u;
     const uint64_t cand_new = __ballot((fv & NEWBIT) != 0);
     const int nR = cv + K;
     // candidate fragments, hi and lo parts (registers for the whole hub)
@@ -928,8 +949,8 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
           r = fsp & IDMASK;
           rnew = fsp & NEWBIT;
           excl = sp;
-          b0 = a.nKK + (v * K + sp) * K;  // FC
-          b1 = 2 * a.nKK + v * K + sp;    // DI
+          b0 = a.nKK + (v * K + sp) * a.Ks;  // FC
+          b1 = a.di_off + v * K + sp;        // DI
         }
       }
       const bool want = on && (!a.skip || rnew != 0 || cand_new != 0);
@@ -1188,7 +1209,7 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
       id = old_raw & IDMASK;
       key = a.keys[x * K + lane];
     }
-    a.Fn[x * K + lane] = id;
+    a.Fn[x * a.Ks + lane] = id;
     a.keysn[x * K + lane] = key;
   }
   const uint64_t um = __ballot(lane < K && !bad && (li & NEWBIT));
@@ -1327,7 +1348,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       s_csl[tid] = a.colslot[rp + tid];
     }
     if (tid < K) {
-      const uint32_t raw = a.F[x * K + tid];
+      const uint32_t raw = a.F[x * a.Ks + tid];
       s_fx[tid] = raw;
       s_kx[tid] = a.keys[x * K + tid];
       tab_insert(tab, mask, raw & IDMASK, EXCLBIT);
@@ -1386,11 +1407,11 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
         const uint32_t srcw = rg[u] == 2 ? fw[u] : cw[u];
         const int64_t v = srcw & IDMASK;
         const IT t = t0 + tid + NT * u;
-        zr[u] = a.F[rg[u] >= 2 ? v * K + ss[u] : 0];
+        zr[u] = a.F[rg[u] >= 2 ? v * a.Ks + ss[u] : 0];
         if (SEG) {
-          const int64_t kp = rg[u] == 1   ? 2 * a.nKK + v * K + sl[u]
+          const int64_t kp = rg[u] == 1   ? a.di_off + v * K + sl[u]
                              : rg[u] == 2 ? x * KK + (int64_t)(t - (IT)c)
-                             : rg[u] == 3 ? a.nKK + (v * K + sl[u]) * K + ss[u]
+                             : rg[u] == 3 ? a.nKK + (v * K + sl[u]) * a.Ks + ss[u]
                                           : 0;
           kr[u] = MIX ? (KT)a.seg32[kp] : (KT)a.seg[kp];
         }
@@ -1751,7 +1772,7 @@ __global__ __launch_bounds__(256) void k_merge(JoinArgs a) {
     if (inactive(a, x)) continue;  // whole wave
     const int nc = a.sl_n[x];
     if (nc < 0) continue;           // merged by the receiver kernel
-    const uint32_t old = lane < K ? a.F[x * K + lane] : 0u;
+    const uint32_t old = lane < K ? a.F[x * a.Ks + lane] : 0u;
     uint64_t lk = lane < K ? key_bits(a.keys[x * K + lane]) : KEY_SENTINEL;
     uint32_t li = lane < K ? (old & IDMASK) : IDMASK;
     for (int b0 = 0; b0 < nc; b0 += WAVE) {
@@ -1819,7 +1840,7 @@ template <typename PT, int CK>
 static void launch_init_t(const Ctx& c) {
   const int g = (int)((c.n + 3) / 4);
   hipLaunchKernelGGL((k_init_graph<PT, CK>), dim3(g), dim3(256), 0, c.stream, (const PT*)c.P, c.L, c.n, c.D,
-                     c.Dp, c.K, c.seed, c.F[c.cur], c.keys[c.cur], c.inst_of, c.ioff, c.iseed);
+                     c.Dp, c.K, c.Ks, c.seed, c.F[c.cur], c.keys[c.cur], c.inst_of, c.ioff, c.iseed);
 }
 
 template <typename PT>
@@ -1844,12 +1865,12 @@ hipError_t launch_init_graph(const Ctx& c) {
 hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits) {
   if (c.nb > 0) {
     const int gx = grid_for(c.Mmax, 256, 1 << 30);
-    hipLaunchKernelGGL(k_fcr_batched, dim3(gx, c.nb), dim3(256), 0, c.stream, F, c.K, c.ioff, c.iseed, c.iM,
+    hipLaunchKernelGGL(k_fcr_batched, dim3(gx, c.nb), dim3(256), 0, c.stream, F, c.K, c.Ks, c.ioff, c.iseed, c.iM,
                        c.iactive, round, c.istats);
     return hipGetLastError();
   }
   const int g = grid_for(c.M, 256, 1 << 30);
-  hipLaunchKernelGGL(k_fcr, dim3(g), dim3(256), 0, c.stream, F, c.n, c.K, c.seed, round, c.M, hits);
+  hipLaunchKernelGGL(k_fcr, dim3(g), dim3(256), 0, c.stream, F, c.n, c.K, c.Ks, c.seed, round, c.M, hits);
   return hipGetLastError();
 }
 
@@ -1861,7 +1882,7 @@ hipError_t launch_batch_reduce(const Ctx& c) {
 hipError_t launch_emit(const Ctx& c, int64_t off, int64_t n_b, int32_t* out_idx) {
   const int64_t cnt = n_b * c.K;
   hipLaunchKernelGGL(k_emit, dim3(grid_for(cnt, 256, 4096)), dim3(256), 0, c.stream, c.F[c.cur], off, cnt, c.K,
-                     out_idx);
+                     c.Ks, out_idx);
   return hipGetLastError();
 }
 
@@ -1885,11 +1906,11 @@ hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
     const int chunk = (CSR_CHUNK / c.K) * c.K;
     const unsigned blocks = (unsigned)((nK + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_zero_i64, dim3(grid_for(nb, 256, 64)), dim3(256), 0, c.stream, c.csr_bcount, (int64_t)nb);
-    hipLaunchKernelGGL(k_part_count, dim3(blocks), dim3(1024), 0, c.stream, F, nK, chunk, c.csr_shift, nb,
+    hipLaunchKernelGGL(k_part_count, dim3(blocks), dim3(1024), 0, c.stream, F, nK, c.K, c.Ks, chunk, c.csr_shift, nb,
                        (unsigned long long*)c.csr_bcount);
     hipLaunchKernelGGL(k_exscan_small, dim3(1), dim3(256), 0, c.stream, (const unsigned long long*)c.csr_bcount,
                        (int64_t)nb, c.csr_bbase, (unsigned long long*)c.csr_bfill);
-    hipLaunchKernelGGL(k_part_scatter, dim3(blocks), dim3(1024), 0, c.stream, F, nK, c.K, chunk, c.csr_shift, nb,
+    hipLaunchKernelGGL(k_part_scatter, dim3(blocks), dim3(1024), 0, c.stream, F, nK, c.K, c.Ks, chunk, c.csr_shift, nb,
                        c.csr_bbase, (unsigned long long*)c.csr_bfill, c.csr_T);
     hipLaunchKernelGGL(k_bucket_csr, dim3((unsigned)nb), dim3(256), 0, c.stream, c.csr_T, c.csr_bbase, c.n,
                        c.csr_shift, nb, c.rowptr, c.col, c.colslot);
@@ -1897,10 +1918,10 @@ hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
   }
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.deg, c.n);
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.fill, c.n);
-  hipLaunchKernelGGL(k_degree, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.deg);
+  hipLaunchKernelGGL(k_degree, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.Ks, c.deg);
   launch_scan(c, 1, 0, c.rowptr);
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.rowptr,
-                     c.fill, c.col, c.colslot);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.Ks,
+                     c.rowptr, c.fill, c.col, c.colslot);
   return hipGetLastError();
 }
 
@@ -2031,6 +2052,8 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   a.col = c.col;
   a.colslot = c.colslot;
   a.nKK = c.n * (int64_t)c.K * c.K;
+  a.Ks = c.Ks;
+  a.di_off = a.nKK + c.n * (int64_t)c.K * c.Ks;
   a.seg = c.seg;
   a.Fn = c.F[c.cur ^ 1];
   a.keysn = c.keys[c.cur ^ 1];
@@ -2094,13 +2117,14 @@ hipError_t launch_join_recv(const Ctx& c, int64_t* stats) {
 
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out) {
   const int64_t cnt = c.n * c.K;
-  hipLaunchKernelGGL(k_strip, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, F, cnt, out);
+  hipLaunchKernelGGL(k_strip, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, F, cnt, c.K, c.Ks, out);
   return hipGetLastError();
 }
 
 hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad) {
   const int64_t cnt = c.n * c.K;
-  hipLaunchKernelGGL(k_load_idx, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, idx, cnt, c.n, F, bad);
+  hipLaunchKernelGGL(k_load_idx, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, idx, cnt, c.n, c.K, c.Ks,
+                     F, bad);
   return hipGetLastError();
 }
 
