@@ -148,7 +148,7 @@ void free_ctx(Ctx& c) {
                   c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.gckey, c.bcand, c.bckey,
                   c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32,
                   c.inst_of, c.ioff, c.iseed, c.iM, c.iD, c.iactive, c.istats, c.vcnt,
-                  c.sl_n, c.sl_id, c.sl_key, c.csr_T, c.csr_bcount, c.csr_bfill, c.csr_bbase};
+                  c.sl_n, c.sl_id, c.sl_key, c.csr_T, c.csr_bcount, c.csr_bfill, c.csr_bbase, c.Pw};
   // the blocks go back to the cache: the context's work must have finished
   (void)hipStreamSynchronize(c.stream);
   for (void* b : bufs) knnd::pool_free(b);
@@ -286,6 +286,10 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
     c.seg = nullptr;
     c.use_hub = false;
   }
+  if (c.use_hub && c.ck == knnd::CK_REV && c.dtype == KNND_F32) {
+    e = dalloc(&c.Pw, (size_t)n * c.D + knnd::HUB_MAXD);
+    if (e != hipSuccess) return map_err(e);
+  }
   if (c.use_hub) {
     const size_t sl = (size_t)n * knnd::SHORT_LIST;
     e = dalloc(&c.sl_n, (size_t)n);
@@ -307,6 +311,7 @@ int finish_create(Ctx& c) {
   KNND_HIP(hipMemsetAsync(c.L + (size_t)c.n * c.Dp, 0, knnd::HUB_MAXD * sizeof(double), c.stream));
   KNND_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int32_t), c.stream));
   KNND_HIP(knnd::launch_log_table(c, c.dflag));
+  if (c.Pw) KNND_HIP(knnd::launch_widen(c));
   int32_t bad = 0;
   KNND_HIP(hipMemcpyAsync(&bad, c.dflag, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
   KNND_HIP(hipStreamSynchronize(c.stream));

@@ -58,6 +58,8 @@ struct Ctx {
 
   // device buffers
   void* P = nullptr;          // [n][D] points (copy owned by the context)
+  double* Pw = nullptr;       // FP64 copy of FP32 points, reverse-KL hub form only (the fold weighs by
+                              // the candidate's coordinates, read per candidate)
   double* L = nullptr;        // [n][Dp] feature table (log x for the KL comparators)
   // F rows have stride Ks, the power of two >= max(K, 8): a row never
   // straddles more cache lines than its size needs
@@ -174,6 +176,7 @@ hipError_t pmalloc(T** p, size_t bytes) {
 
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_log_table(const Ctx& c, int32_t* bad);
+hipError_t launch_widen(const Ctx& c);
 hipError_t launch_init_graph(const Ctx& c);
 hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits);
 hipError_t launch_csr(const Ctx& c, const uint32_t* F);

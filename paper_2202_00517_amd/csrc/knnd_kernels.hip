@@ -23,6 +23,12 @@ constexpr int SEL_SURV = 256;   // survivors handled by the fast selection path
 // ---------------------------------------------------------------------------
 // Small utility kernels
 // ---------------------------------------------------------------------------
+// out = (double)in, element by element
+__global__ void k_widen(const float* __restrict__ in, int64_t cnt, double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (double)in[i];
+}
+
 __global__ void k_zero_i32(int32_t* p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
@@ -716,7 +722,7 @@ __device__ __forceinline__ double hub_fold(const double (&pr)[MAXD], const doubl
 
 template <int MAXD, typename PT, int CK>
 __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __restrict__ L,
-                                                 const PT* __restrict__ P) {
+                                                 const PT* __restrict__ P, const double* __restrict__ Pd) {
   constexpr int CH = 16;  // candidates per LDS tile
   __shared__ double s_keys[4][WAVE][CH + 1];
   __shared__ int64_t s_b0[4][WAVE];
@@ -790,7 +796,7 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
           if (__ballot(nd) == 0) continue;
           const uint32_t craw = (uint32_t)__shfl((int)fv, ci, WAVE);
           const int64_t cidx = (int64_t)__builtin_amdgcn_readfirstlane(craw & IDMASK);
-          s_keys[wv][lane][cj] = hub_fold<MAXD, CK>(pr, lr, P + cidx * D, L + cidx * Dp, D);  // scalar loads
+          s_keys[wv][lane][cj] = hub_fold<MAXD, CK>(pr, lr, Pd + cidx * D, L + cidx * Dp, D);  // scalar loads
           my_perf += nd ? 1 : 0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -809,7 +815,7 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
       }
       // slot K: the hub itself, a co-friend candidate of each of its friends
       if (__ballot(need_v)) {
-        const double key = hub_fold<MAXD, CK>(pr, lr, P + v * D, L + v * Dp, D);
+        const double key = hub_fold<MAXD, CK>(pr, lr, Pd + v * D, L + v * Dp, D);
         if (need_v) {
           a.seg[b1] = key;
           ++my_perf;
@@ -1824,6 +1830,12 @@ hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_widen(const Ctx& c) {
+  const int64_t cnt = c.n * c.D + HUB_MAXD;  // rows and the zeroed tail padding
+  hipLaunchKernelGGL(k_widen, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, (const float*)c.P, cnt, c.Pw);
+  return hipGetLastError();
+}
+
 hipError_t launch_log_table(const Ctx& c, int32_t* bad) {
   const int64_t total = c.n * c.Dp;
   const int g = grid_for(total, 256, 65536);
@@ -1972,7 +1984,9 @@ static hipError_t launch_hub_reg(const Ctx& c, const JoinArgs& a) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
   const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu * 4);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.L, (const PT*)c.P);
+  // candidate point rows as FP64 (read only by the reverse-KL fold)
+  const double* Pd = c.Pw ? c.Pw : reinterpret_cast<const double*>(c.P);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.L, (const PT*)c.P, Pd);
   return hipGetLastError();
 }
 
