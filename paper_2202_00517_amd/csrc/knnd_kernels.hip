@@ -898,12 +898,12 @@ __global__ void k_prep_mixed(const PT* __restrict__ P, const double* __restrict_
 // cross term is accumulated as lo*hi + hi*lo + hi*hi (the lo*lo term is left
 // to the error bound).  C~ goes to the same edge-indexed slots as the FP64
 // keys of the exact hub form, as FP32.
-template <int DK, typename H>
+template <int DK, typename H, int MAXCT>
 __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restrict__ Ph, const H* __restrict__ Lh,
                                                   float* __restrict__ seg32) {
   using V8 = typename Mfma<H>::v8;
   constexpr int KS = DK / 32;  // MFMA k-steps
-  constexpr int MAXCT = 5;     // candidate tiles: K+1 <= 80
+  // MAXCT: candidate tiles held in registers, >= ceil((K+1)/16)
   const int K = a.K, K1 = a.K + 1;
   const int nct = (K1 + 15) / 16;
   const int lane = lane_id();
@@ -1341,9 +1341,12 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       s_tau = key_bits(a.keys[x * K + K - 1]);
     }
     __syncthreads();
-    if (MIX && tid < D) {  // (read only after the syncs of phases B and C)
-      s_xr[tid] = (double)P[x * D + tid];
-      s_lr[tid] = a.L[x * Dp + tid];
+    // x's row and logs for the rescue: loaded now, written to LDS after the
+    // enumeration (their latency overlaps phases B and C)
+    double xr_pre = 0.0, lr_pre = 0.0;
+    if (MIX && tid < D) {
+      xr_pre = (double)P[x * D + tid];
+      lr_pre = a.L[x * Dp + tid];
     }
     // B: excluded entries; a co-friend list of at most NT entries is staged
     // in LDS (its loads overlap those of x's own list), so that enumerating
@@ -1502,6 +1505,10 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       continue;
     }
     my_evals += item_evals;
+    if (MIX && tid < D) {  // (read only after the barriers of the selection below)
+      s_xr[tid] = xr_pre;
+      s_lr[tid] = lr_pre;
+    }
     // (s_ncand exceeds the list capacity only after a reported internal error)
     const int ncand = (int)min((int64_t)s_ncand, ccap);
     const double* kx = s_kx;  // the old list's keys
@@ -2019,7 +2026,7 @@ static hipError_t launch_hub_kind(const Ctx& c, const JoinArgs& a) {
 
 template <int DK, typename H>
 static hipError_t launch_hub_mfma_t(const Ctx& c, const JoinArgs& a) {
-  auto kern = k_hub_mfma<DK, H>;
+  auto kern = (a.K + 1 <= 32) ? k_hub_mfma<DK, H, 2> : ((a.K + 1 <= 48) ? k_hub_mfma<DK, H, 3> : k_hub_mfma<DK, H, 5>);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) {
     (void)hipGetLastError();
