@@ -145,6 +145,40 @@ def cpu_baseline(P, d, K, seed, receivers, threads):
                       f"{threads} threads; log table and start graph not timed)"}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_timing(configs):
+    """The CPU oracle (unchanged) timed on whole descents of the given
+    configurations: per-round seconds and evaluations per second."""
+    import oracle
+    import synth
+    threads = min(16, os.cpu_count() or 1)  # the host share of one GPU
+    out = {"kind": "oracle", "cpu": cpu_model(), "host_threads": threads, "runs": []}
+    for cfgi in configs:
+        cf = synth.CONFIGS[cfgi]
+        P = synth.dirichlet(cf["data_seed"], cf["n"], cf["d"], cf["dtype"])
+        for t in ([threads, 1] if cfgi == 1 else [threads]):
+            log(f"oracle: configuration {cfgi} (n={cf['n']}, d={cf['d']}, K={cf['K']}), {t} threads")
+            t0 = time.perf_counter()
+            r = oracle.build_graph(P, cf["d"], cf["K"], cf["seed"], threads=t)
+            secs = time.perf_counter() - t0
+            out["runs"].append({"config": cfgi, "n": cf["n"], "d": cf["d"], "K": cf["K"], "threads": t,
+                                "rounds": r.rounds, "seconds": round(secs, 3),
+                                "round_seconds": [round(float(s), 3) for s in r.seconds],
+                                "evals_alg": int(r.evals.sum()),
+                                "evals_per_s": float(r.evals.sum()) / secs})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,9 +194,16 @@ def main():
     ap.add_argument("--cpu-receivers", type=int, default=400_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device (reference run for HBM counters)")
+    ap.add_argument("--oracle-timing", default=None, metavar="CONFIGS",
+                    help="only time the CPU oracle's whole descent on these configurations "
+                         "(comma-separated numbers, e.g. 1,2), with all host threads and, for "
+                         "configuration 1, with one thread")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.oracle_timing:
+        oracle_timing([int(c) for c in args.oracle_timing.split(",")])
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -228,6 +269,17 @@ def main():
                  "speedup_mixed_over_plain": pel / elapsed,
                  "identical_graph": bool(same)}
 
+    # end to end: host points in, host lists out (H2D of the points, the
+    # descent, D2H of the lists), the same call the step makes otherwise
+    prm_e2e = knnd.default_params(precision=prec)
+    e2e = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        knnd.knnd_build_ex(P, d, K, seed, prm_e2e, with_kl=False)
+        e2e.append(1e3 * (time.perf_counter() - ts))
+    e2e_ms = sorted(e2e)[1]
+
     # roofline of the dominant kernel: the receiver pass (k_recv, one launch
     # per table-size class, then k_merge; steps a2-a5 on the receiver side), timed with HIP
     # events on the library's stream around its launches in every timed round
@@ -265,6 +317,7 @@ def main():
                                f"n={n}, K={K}, seed={seed}, whole descent to the stop test",
                    "n": n, "d": d, "K": K, "precision": args.precision},
         "time_to_graph_ms": ms_per_step,
+        "end_to_end_ms": round(e2e_ms, 2),
         "rounds": last["rounds"],
         "evals_alg": evals[0],
         "median_ms_per_step": steps_ms[len(steps_ms) // 2],
