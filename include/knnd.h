@@ -94,6 +94,10 @@ typedef enum {
 #define KNND_FLAG_PULL 0x2      /* join in pull form (each receiver gathers its
                                    candidates' log rows) instead of hub form
                                    (same result) */
+#define KNND_FLAG_ATOMIC_CSR 0x4 /* build the reverse-neighbour lists with one
+                                   device-wide atomic per edge (the form used
+                                   above 2^25 points) instead of the bucketed
+                                   counting sort (same result) */
 
 /*
  * Comparators (Section 2.1: any family of per-point total orders; Section 1.3

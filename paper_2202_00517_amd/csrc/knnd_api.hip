@@ -240,7 +240,8 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   // at most CSR_MAXB buckets
   c.csr_shift = 8;
   while (c.csr_shift < 13 && ((n + ((int64_t)1 << c.csr_shift) - 1) >> c.csr_shift) > knnd::CSR_MAXB) ++c.csr_shift;
-  if (((n + ((int64_t)1 << c.csr_shift) - 1) >> c.csr_shift) <= knnd::CSR_MAXB && nK < ((size_t)1 << 31)) {
+  if (((n + ((int64_t)1 << c.csr_shift) - 1) >> c.csr_shift) <= knnd::CSR_MAXB && nK < ((size_t)1 << 31) &&
+      !(prm.flags & KNND_FLAG_ATOMIC_CSR)) {
     if (e == hipSuccess) e = dalloc(&c.csr_T, nK);
     if (e == hipSuccess) e = dalloc(&c.csr_bcount, (size_t)knnd::CSR_MAXB);
     if (e == hipSuccess) e = dalloc(&c.csr_bfill, (size_t)knnd::CSR_MAXB);

@@ -1263,7 +1263,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   // T = c (K+1) + K^2 < 2^22)
   using IT = typename std::conditional<GLOB, int64_t, uint32_t>::type;
   using KT = typename std::conditional<MIX, float, double>::type;  // what a key slot holds
-  __shared__ uint32_t s_tab[GLOB ? 1 : CAP];
+  __shared__ __align__(16) uint32_t s_tab[GLOB ? 1 : CAP];
   __shared__ uint32_t s_cid[CC];
   __shared__ double s_ckey[SEG ? CC : 1];
   __shared__ uint32_t s_fx[WAVE];
@@ -1329,7 +1329,12 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
     const double Sx = MIX ? a.S[x] : 0.0;  // sum_i x_i log x_i
 
     // A: clear
-    for (uint32_t s = tid; s < cap; s += NT) tab[s] = EMPTY;
+    if (GLOB) {
+      for (uint32_t s = tid; s < cap; s += NT) tab[s] = EMPTY;
+    } else {
+      const uint4 e4 = {EMPTY, EMPTY, EMPTY, EMPTY};
+      for (uint32_t s = 4 * tid; s < cap; s += 4 * NT) *reinterpret_cast<uint4*>(tab + s) = e4;
+    }
     const int64_t pf_item0 = my_perf;
     if (tid == 0) {
       s_ncand = 0;

@@ -244,6 +244,13 @@ def test_stop_rule_round_cap_warns():
     assert g["status"] == knnd.KNND_WARN_MAX_ROUNDS and g["rounds"] == 4
 
 
+@pytest.mark.parametrize("n,d,K,seed", [(20000, 10, 20, 8), (3001, 20, 30, 7)])
+def test_atomic_reverse_neighbour_build(n, d, K, seed):
+    # the per-edge atomic CSR build (used above 2^25 points) gives the same descent
+    P = synth.dirichlet(6, n, d, np.float32)
+    full_compare(P, d, K, seed, flags=knnd.KNND_FLAG_ATOMIC_CSR, precision=knnd.KNND_PREC_MIXED_BF16)
+
+
 def test_round_cap_and_fcr_sample_size():
     P = synth.dirichlet(9, 4000, 8, np.float32)
     full_compare(P, 8, 12, seed=3, max_rounds=2)
