@@ -156,22 +156,22 @@ def cpu_model():
     return "unknown"
 
 
-def oracle_timing(configs):
-    """The CPU oracle (unchanged) timed on whole descents of the given
-    configurations: per-round seconds and evaluations per second."""
+def oracle_timing(names):
+    """The CPU oracle (unchanged) timed on whole descents of the named
+    workloads: per-round seconds and evaluations per second."""
     import oracle
     import synth
     threads = min(16, os.cpu_count() or 1)  # the host share of one GPU
     out = {"kind": "oracle", "cpu": cpu_model(), "host_threads": threads, "runs": []}
-    for cfgi in configs:
-        cf = synth.CONFIGS[cfgi]
+    for name in names:
+        cf = synth.WORKLOADS[name]
         P = synth.dirichlet(cf["data_seed"], cf["n"], cf["d"], cf["dtype"])
-        for t in ([threads, 1] if cfgi == 1 else [threads]):
-            log(f"oracle: configuration {cfgi} (n={cf['n']}, d={cf['d']}, K={cf['K']}), {t} threads")
+        for t in ([threads, 1] if cf["n"] <= 10000 else [threads]):
+            log(f"oracle: {name}, {t} threads")
             t0 = time.perf_counter()
             r = oracle.build_graph(P, cf["d"], cf["K"], cf["seed"], threads=t)
             secs = time.perf_counter() - t0
-            out["runs"].append({"config": cfgi, "n": cf["n"], "d": cf["d"], "K": cf["K"], "threads": t,
+            out["runs"].append({"workload": name, "n": cf["n"], "d": cf["d"], "K": cf["K"], "threads": t,
                                 "rounds": r.rounds, "seconds": round(secs, 3),
                                 "round_seconds": [round(float(s), 3) for s in r.seconds],
                                 "evals_alg": int(r.evals.sum()),
@@ -194,19 +194,19 @@ def main():
     ap.add_argument("--cpu-receivers", type=int, default=400_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device (reference run for HBM counters)")
-    ap.add_argument("--oracle-timing", default=None, metavar="CONFIGS",
-                    help="only time the CPU oracle's whole descent on these configurations "
-                         "(comma-separated numbers, e.g. 1,2), with all host threads and, for "
-                         "configuration 1, with one thread")
+    ap.add_argument("--oracle-timing", default=None, metavar="WORKLOADS",
+                    help="only time the CPU oracle's whole descent on these workloads "
+                         "(comma-separated names, e.g. n2000_d5_k10,n100000_d10_k20), with the "
+                         "host threads and, for n <= 10000, with one thread")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
     if args.oracle_timing:
-        oracle_timing([int(c) for c in args.oracle_timing.split(",")])
+        oracle_timing(args.oracle_timing.split(","))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
@@ -215,7 +215,7 @@ def main():
     import paper_2202_00517_amd as knnd
     import synth
 
-    cfg = dict(synth.CONFIGS[3])
+    cfg = dict(synth.WORKLOADS["n1000000_d20_k30"])
     cfg["n"] = args.n
     n, d, K, seed = cfg["n"], cfg["d"], cfg["K"], cfg["seed"]
     D = d + 1

@@ -65,7 +65,7 @@ typedef enum {
     KNND_ERR_DOMAIN = -2,       /* a coordinate is NaN, infinite or <= 0 */
     KNND_ERR_NOMEM = -3,        /* device allocation failed */
     KNND_ERR_DEVICE = -4,       /* a HIP call failed, or no gfx950 device */
-    KNND_ERR_UNSUPPORTED = -5   /* valid request this build does not implement */
+    KNND_ERR_UNSUPPORTED = -5   /* valid request the library does not implement */
 } knnd_status;
 
 typedef enum { KNND_F32 = 0, KNND_F64 = 1 } knnd_dtype;

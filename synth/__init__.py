@@ -97,12 +97,14 @@ def subsample(seed, n, m):
     return out
 
 
-# The benchmark workloads: (n, d, K, storage dtype, data seed, algorithm seed).
-CONFIGS = {
-    1: dict(n=2000, d=5, K=10, dtype=np.float64, data_seed=1001, seed=2001),
-    2: dict(n=100_000, d=10, K=20, dtype=np.float32, data_seed=1002, seed=2002),
-    3: dict(n=1_000_000, d=20, K=30, dtype=np.float32, data_seed=1003, seed=2003),
-    4: dict(n=200_000, d=50, K=20, dtype=np.float32, data_seed=1004, seed=2004),
+# The benchmark workloads, named by their sizes: (n, d, K, storage dtype, data
+# seed, algorithm seed).
+WORKLOADS = {
+    "n2000_d5_k10": dict(n=2000, d=5, K=10, dtype=np.float64, data_seed=1001, seed=2001),
+    "n100000_d10_k20": dict(n=100_000, d=10, K=20, dtype=np.float32, data_seed=1002, seed=2002),
+    "n1000000_d20_k30": dict(n=1_000_000, d=20, K=30, dtype=np.float32, data_seed=1003, seed=2003),
+    "n200000_d50_k20": dict(n=200_000, d=50, K=20, dtype=np.float32, data_seed=1004, seed=2004),
 }
+BATCH_WORKLOAD = "batch512"  # BATCH_INSTANCES instances drawn from BATCH_BASE_SEED
 BATCH_BASE_SEED = 1005
 BATCH_INSTANCES = 512

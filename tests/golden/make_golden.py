@@ -3,7 +3,7 @@ full-size synthetic workloads, as SHA-256 digests of the final neighbor lists
 (int32, little-endian) and keys (FP64 bits) plus every per-round count.
 
 Calls only oracle/ (and the input generator).  Usage:
-    python tests/golden/make_golden.py c3 c4 c5
+    python tests/golden/make_golden.py n1000000_d20_k30 n200000_d50_k20 batch512
 """
 import hashlib
 import json
@@ -25,14 +25,14 @@ def digest(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def run_single(cfg_id):
-    c = synth.CONFIGS[cfg_id]
+def run_single(name):
+    c = synth.WORKLOADS[name]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
     t = time.time()
     res = oracle.build_graph(P, c["d"], c["K"], c["seed"])
     secs = time.time() - t
     return {
-        "workload": f"config {cfg_id}: n={c['n']} d={c['d']} K={c['K']} "
+        "workload": f"n={c['n']} d={c['d']} K={c['K']} "
                     f"{np.dtype(c['dtype']).name} points, data seed {c['data_seed']}, seed {c['seed']}",
         "status": res.status,
         "rounds": res.rounds,
@@ -62,10 +62,10 @@ def run_batched():
 
 def main(names):
     for name in names:
-        if name == "c5":
+        if name == synth.BATCH_WORKLOAD:
             rec = run_batched()
         else:
-            rec = run_single(int(name[1:]))
+            rec = run_single(name)
         path = os.path.join(HERE, f"oracle_{name}.json")
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)
@@ -73,4 +73,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c1", "c2", "c3", "c4", "c5"])
+    main(sys.argv[1:] or list(synth.WORKLOADS) + [synth.BATCH_WORKLOAD])

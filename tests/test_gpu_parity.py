@@ -80,10 +80,10 @@ def test_log_table_bit_exact():
         L = c.log_table()
     ref = oracle.log_table(vals)
     assert np.array_equal(bits(L), bits(ref))
-    for cfg in (1, 2):
-        cf = synth.CONFIGS[cfg]
+    for cfg in ("n2000_d5_k10", "n100000_d10_k20"):
+        cf = synth.WORKLOADS[cfg]
         P = synth.dirichlet(cf["data_seed"], cf["n"], cf["d"], cf["dtype"])
-        say(f"log table config {cfg}")
+        say(f"log table {cfg}")
         with knnd.Context(P, cf["d"], cf["K"], cf["seed"]) as c:
             L = c.log_table()
         assert np.array_equal(bits(L), bits(oracle.log_table(oracle.widen(P))))
@@ -188,13 +188,13 @@ def test_exact_ties_break_by_index(form):
 # ---------------------------------------------------------------------------
 # whole descent (all rounds, stop test) against the oracle
 # ---------------------------------------------------------------------------
-def test_config1_full():
-    c = synth.CONFIGS[1]
+def test_n2000_d5_k10_full():
+    c = synth.WORKLOADS["n2000_d5_k10"]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
     full_compare(P, c["d"], c["K"], c["seed"])
 
 
-def test_random_small_configs_full():
+def test_random_small_workloads_full():
     rng = np.random.default_rng(2024)
     for i in range(24):
         n = int(rng.integers(30, 5000))
@@ -303,10 +303,10 @@ def _digest(a):
 
 
 def check_against_golden(cfg, precision=0):
-    gold = _golden(f"c{cfg}")
-    c = synth.CONFIGS[cfg]
+    gold = _golden(cfg)
+    c = synth.WORKLOADS[cfg]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
-    say(f"config {cfg} full size vs stored oracle digests, precision {precision}")
+    say(f"{cfg} full size vs stored oracle digests, precision {precision}")
     g = knnd.knnd_build_ex(P, c["d"], c["K"], c["seed"], knnd.default_params(precision=precision))
     assert g["status"] == gold["status"]
     assert g["rounds"] == gold["rounds"]
@@ -318,19 +318,19 @@ def check_against_golden(cfg, precision=0):
     return g, P
 
 
-def test_config2_full_size():
-    check_against_golden(2)
+def test_n100000_d10_k20_full_size():
+    check_against_golden("n100000_d10_k20")
 
 
 @pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
-def test_config2_live_oracle(form):
-    c = synth.CONFIGS[2]
+def test_n100000_d10_k20_live_oracle(form):
+    c = synth.WORKLOADS["n100000_d10_k20"]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
     g, _ = full_compare(P, c["d"], c["K"], c["seed"], flags=form[0], precision=form[1])
     resc = sum(s["rescues"] for s in g["stats"])
     if form[1] != knnd.KNND_PREC_FP64:
         alg = sum(s["evals_alg"] for s in g["stats"])
-        say(f"config 2 {FORM_IDS[FORMS.index(form)]}: rescued {resc} of {alg} evaluations "
+        say(f"n=100000 d=10 K=20 {FORM_IDS[FORMS.index(form)]}: rescued {resc} of {alg} evaluations "
             f"({100.0 * resc / alg:.2f}%)")
         assert 0 < resc < alg
     else:
@@ -361,23 +361,23 @@ def test_mixed_tiny_coordinates(prec):
     assert sum(s["rescues"] for s in g["stats"]) > 0
 
 
-def test_config3_mixed_bf16_full_size():
-    g, _ = check_against_golden(3, knnd.KNND_PREC_MIXED_BF16)
+def test_n1000000_d20_k30_mixed_bf16_full_size():
+    g, _ = check_against_golden("n1000000_d20_k30", knnd.KNND_PREC_MIXED_BF16)
     resc = sum(s["rescues"] for s in g["stats"])
     alg = sum(s["evals_alg"] for s in g["stats"])
-    say(f"config 3 bf16: rescued {resc} of {alg} evaluations ({100.0 * resc / alg:.2f}%)")
+    say(f"n=1e6 d=20 K=30 bf16: rescued {resc} of {alg} evaluations ({100.0 * resc / alg:.2f}%)")
 
 
-def test_config4_mixed_fp16_full_size():
-    g, _ = check_against_golden(4, knnd.KNND_PREC_MIXED_FP16)
+def test_n200000_d50_k20_mixed_fp16_full_size():
+    g, _ = check_against_golden("n200000_d50_k20", knnd.KNND_PREC_MIXED_FP16)
     resc = sum(s["rescues"] for s in g["stats"])
     alg = sum(s["evals_alg"] for s in g["stats"])
-    say(f"config 4 fp16: rescued {resc} of {alg} evaluations ({100.0 * resc / alg:.2f}%)")
+    say(f"n=200000 d=50 K=20 fp16: rescued {resc} of {alg} evaluations ({100.0 * resc / alg:.2f}%)")
 
 
-def test_config3_full_size():
-    g, P = check_against_golden(3)
-    c = synth.CONFIGS[3]
+def test_n1000000_d20_k30_full_size():
+    g, P = check_against_golden("n1000000_d20_k30")
+    c = synth.WORKLOADS["n1000000_d20_k30"]
     # sampled rows recomputed key by key with the oracle's key function
     P64 = oracle.widen(P)
     L = oracle.log_table(P64)
@@ -387,38 +387,38 @@ def test_config3_full_size():
             assert g["kl"][x, j] == oracle.key(P64, L, int(x), int(g["idx"][x, j]))
 
 
-def test_config3_round1_sampled_receivers():
+def test_n1000000_d20_k30_round1_sampled_receivers():
     # Round 1 at full size from the oracle's own initial graph, on 2000 receivers.
-    c = synth.CONFIGS[3]
+    c = synth.WORKLOADS["n1000000_d20_k30"]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
     P64 = oracle.widen(P)
     L = oracle.log_table(P64)
     F0, k0 = oracle.initial_graph(P64, L, c["K"], c["seed"])
-    say("config 3 round 1 from the oracle snapshot")
+    say("n=1e6 d=20 K=30 round 1 from the oracle snapshot")
     with knnd.Context(P, c["d"], c["K"], c["seed"]) as ctx:
         st0 = ctx.init_graph()
         gi, gk = ctx.get_graph()
-        assert_same_graph(gi, gk, F0, k0, "config 3 initial graph")
+        assert_same_graph(gi, gk, F0, k0, "n=1e6 d=20 K=30 initial graph")
         st1 = ctx.round()
         gi, gk = ctx.get_graph()
     xs = synth.subsample(7, c["n"], 2000)
     oi, ok, _, _ = oracle.round_subset(P64, L, F0, k0, xs)
-    assert_same_graph(gi[xs], gk[xs], oi, ok, "config 3 round 1 sample")
-    gold = _golden("c3")
+    assert_same_graph(gi[xs], gk[xs], oi, ok, "n=1e6 d=20 K=30 round 1 sample")
+    gold = _golden("n1000000_d20_k30")
     assert st0["fcr_hits"] == gold["fcr_hits"][0]
     assert (st1["updates"], st1["evals_alg"], st1["fcr_hits"]) == \
         (gold["updates"][1], gold["evals_alg"][1], gold["fcr_hits"][1])
 
 
-def test_config4_full_size_and_recall():
-    g, P = check_against_golden(4)
-    c = synth.CONFIGS[4]
+def test_n200000_d50_k20_full_size_and_recall():
+    g, P = check_against_golden("n200000_d50_k20")
+    c = synth.WORKLOADS["n200000_d50_k20"]
     P64 = oracle.widen(P)
     L = oracle.log_table(P64)
     qs = synth.subsample(c["seed"], c["n"], 2000)
     bf, bk = oracle.bruteforce(P64, L, c["K"], qs)
     rec = np.mean([len(set(g["idx"][q].tolist()) & set(b.tolist())) / c["K"] for q, b in zip(qs, bf)])
-    say(f"config 4 recall@{c['K']} on 2000 queries: {rec:.4f}")
+    say(f"n=200000 d=50 K=20 recall@{c['K']} on 2000 queries: {rec:.4f}")
     assert 0.0 < rec <= 1.0
     # the library's exhaustive search, bounded by the descent's K-th keys
     ei, ek = knnd.knnd_exact_knn(P, c["d"], c["K"], qs.astype(np.int32), tau=g["kl"][qs, -1])
@@ -550,13 +550,13 @@ def test_batched_round_cap_stops_every_instance():
 
 
 @pytest.mark.parametrize("prec", [knnd.KNND_PREC_FP64, knnd.KNND_PREC_MIXED_BF16], ids=["plain", "bf16"])
-def test_config5_batched_full_size(prec):
-    gold = _golden("c5")["instances"]
+def test_512_instances_batched_full_size(prec):
+    gold = _golden(synth.BATCH_WORKLOAD)["instances"]
     inst = []
     for b in range(synth.BATCH_INSTANCES):
         n, d, K, ds, s = synth.instance(synth.BATCH_BASE_SEED, b)
         inst.append((synth.dirichlet(ds, n, d, np.float32), d, K, s))
-    say(f"config 5: {len(inst)} instances vs stored oracle digests, precision {prec}")
+    say(f"512 instances: {len(inst)} instances vs stored oracle digests, precision {prec}")
     st, outs = knnd.knnd_build_batched(inst, knnd.default_params(precision=prec))
     assert st == knnd.KNND_OK
     for b, (g, o) in enumerate(zip(outs, gold)):
