@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_exact_bound(const PT* __restrict__ P, c
     uint64_t lk;
     uint32_t li;
     block_smallest(mk[j], mi[j], sk, si, lk, li);
-    if (threadIdx.x == K - 1 && qb + j < nq) {  // lane K-1 of wave 0
+    if ((int)threadIdx.x == K - 1 && qb + j < nq) {  // lane K-1 of wave 0
       tk[qb + j] = lk;
       ti[qb + j] = li;
     }

@@ -727,7 +727,7 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
   __shared__ double s_keys[4][WAVE][CH + 1];
   __shared__ int64_t s_b0[4][WAVE];
   __shared__ uint64_t s_need[4][WAVE];
-  const int K = a.K, K1 = a.K + 1, D = a.D, Dp = a.Dp;
+  const int K = a.K, D = a.D, Dp = a.Dp;
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
   const int64_t nwaves = (int64_t)gridDim.x * 4;
