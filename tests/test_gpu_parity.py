@@ -737,3 +737,23 @@ def test_memory_cache_reuse_and_release():
     o = oracle.build_graph(P[:5000], 10, 20, 5)
     assert_same_graph(d["idx"], d["kl"], o.idx, o.keys, "small build")
     assert np.array_equal(a["idx"], e["idx"])
+
+
+# ---------------------------------------------------------------------------
+# Dimension boundaries: the MFMA operand width (32 or 64 coordinates; above 64
+# the exact hub form runs) and the LDS limit of the hub form ((K+1) rows of
+# D doubles over 64 KB: the pull form runs).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", MIXED, ids=["bf16", "fp16"])
+@pytest.mark.parametrize("d", [31, 32, 63, 64])
+def test_mixed_at_operand_width_boundaries(d, prec):
+    P = synth.dirichlet(900 + d, 3000, d, np.float32)
+    g, _ = full_compare(P, d, 16, 41 + d, precision=prec)
+    if d + 1 > 64:
+        assert sum(s["rescues"] for s in g["stats"]) == 0  # exact hub form
+
+
+def test_high_dimension_runs_the_pull_form():
+    d, K = 200, 40  # (K+1) * 201 * 8 bytes > 64 KB
+    P = synth.dirichlet(905, 1500, d, np.float32)
+    full_compare(P, d, K, 43, precision=knnd.KNND_PREC_MIXED_BF16)
