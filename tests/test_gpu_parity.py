@@ -757,3 +757,15 @@ def test_high_dimension_runs_the_pull_form():
     d, K = 200, 40  # (K+1) * 201 * 8 bytes > 64 KB
     P = synth.dirichlet(905, 1500, d, np.float32)
     full_compare(P, d, K, 43, precision=knnd.KNND_PREC_MIXED_BF16)
+
+
+@pytest.mark.parametrize("prec", MIXED, ids=["bf16", "fp16"])
+def test_mixed_near_duplicates_resolved_by_rescue(prec):
+    # clusters of near-duplicates: keys inside a cluster differ far below the
+    # 16-bit operands' resolution, so only the FP64 rescue orders them
+    base = synth.dirichlet(910, 400, 9, np.float64)
+    rng = np.random.default_rng(911)
+    P = np.repeat(base, 8, axis=0) * (1.0 + 1e-7 * rng.standard_normal((3200, 10)))
+    P = (P / P.sum(axis=1, keepdims=True)).astype(np.float32)
+    g, _ = full_compare(P, 9, 12, 47, precision=prec)
+    assert sum(s["rescues"] for s in g["stats"]) > 0
