@@ -17,7 +17,8 @@
 namespace knnd {
 
 constexpr int SEL_BINS = 1024;  // histogram bins of the threshold selection
-constexpr int CSR_CHUNK = 65536;  // edges per block of the partition passes (rounded to a multiple of K)
+constexpr int CSR_CHUNK = 65536;
+constexpr int SMALL_NW_CAP = 1024;  // receiver classes up to this table size run two waves per receiver  // edges per block of the partition passes (rounded to a multiple of K)
 constexpr int SEL_SURV = 256;   // survivors handled by the fast selection path
 
 // ---------------------------------------------------------------------------
@@ -1964,15 +1965,17 @@ static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
                        c.class_count, cls);
     return hipGetLastError();
   } else {
-    auto kern = k_recv<CAP, PT, MODE, 4>;
+    // small tables: two waves per receiver, twice the receivers in flight
+    constexpr int NWC = CAP <= SMALL_NW_CAP ? 2 : 4;
+    auto kern = k_recv<CAP, PT, MODE, NWC>;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NWC * 64, 0) != hipSuccess || per_cu < 1) {
       (void)hipGetLastError();
       per_cu = 1;
     }
     int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
     if (CAP >= 8192) grid = std::min(grid, c.bblocks);  // one global candidate region per block
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.class_list, c.class_count, cls);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NWC * 64), 0, c.stream, a, c.class_list, c.class_count, cls);
     return hipGetLastError();
   }
 }
