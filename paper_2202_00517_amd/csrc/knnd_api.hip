@@ -27,8 +27,10 @@ struct knnd_ctx {
 // Device memory cache.  A descent uses a few gigabytes of scratch at n = 1e6,
 // and hipMalloc / hipFree of it cost several milliseconds per call; blocks a
 // finished call gives back are kept (per device, by rounded size) and handed
-// to later calls.  At most POOL_MAX_CACHED bytes stay cached (the oldest go
-// first); knnd_release_cache() returns all of them.  Thread-safe.
+// to later calls.  At most half of the first device's memory stays cached
+// (the oldest go first: a cap below what alternating workloads use together
+// frees and reallocates blocks on every call); knnd_release_cache() returns
+// all of them.  Thread-safe.
 // ---------------------------------------------------------------------------
 namespace knnd {
 namespace {
@@ -41,7 +43,7 @@ std::mutex g_pool_mu;
 std::vector<PoolBlock> g_cached;
 std::unordered_map<void*, PoolBlock> g_live;
 size_t g_cached_bytes = 0;
-constexpr size_t POOL_MAX_CACHED = (size_t)64 << 30;
+size_t g_cap = 0;  // set on the first allocation (under g_pool_mu)
 
 // Sizes are rounded up (to 256 bytes, above 1 MiB to an eighth of their
 // power of two) so that calls of slightly different sizes share blocks.
@@ -70,6 +72,10 @@ hipError_t pool_malloc(void** out, size_t bytes) {
   const size_t rb = pool_round(bytes);
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_cap == 0) {
+      size_t total = 0;
+      g_cap = (hipDeviceTotalMem(&total, dev) == hipSuccess && total > 0) ? total / 2 : ((size_t)64 << 30);
+    }
     for (size_t i = 0; i < g_cached.size(); ++i) {
       if (g_cached[i].dev == dev && g_cached[i].bytes == rb) {
         const PoolBlock b = g_cached[i];
@@ -105,7 +111,7 @@ void pool_free(void* p) {
     g_cached.push_back(it->second);
     g_cached_bytes += it->second.bytes;
     g_live.erase(it);
-    while (g_cached_bytes > POOL_MAX_CACHED && !g_cached.empty()) {
+    while (g_cached_bytes > g_cap && !g_cached.empty()) {
       drop.push_back(g_cached.front());
       g_cached_bytes -= g_cached.front().bytes;
       g_cached.erase(g_cached.begin());
@@ -221,8 +227,12 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
   const size_t nK = (size_t)n * K;
   const int64_t ntiles = (n + 2047) / 2048;
-  c.gblocks = 32;
   c.gstride = next_pow2(2 * n) < 1024 ? 1024 : next_pow2(2 * n);
+  // blocks of the global-memory receiver class, each with its own table,
+  // candidate list and keys (10 bytes per table slot): as many as 4 GiB
+  // holds, between 32 and 128 (more than 32 cut its tail of few, very large
+  // receivers; more than 128 gained nothing at 10^6 points)
+  c.gblocks = (int)std::min<int64_t>(128, std::max<int64_t>(32, ((int64_t)4 << 30) / (10 * c.gstride)));
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = knnd::pmalloc(&c.P, ((size_t)n * c.D + knnd::HUB_MAXD) * esz);
   if (e == hipSuccess) e = dalloc(&c.L, (size_t)n * c.Dp + knnd::HUB_MAXD);
