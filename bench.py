@@ -95,6 +95,36 @@ def batched_leg(knnd, synth, torch, steps):
             "max_rounds": max(o["rounds"] for o in outs)}
 
 
+def share_leg(knnd, Pd, d, K, seed, precision, shares=8, reps=3):
+    """One GPU's share of a descent split by receivers over `shares` GPUs:
+    round 2 (from the graph a full round 1 left) restricted to the first
+    1/shares of the receivers, against the same round over all of them.  The
+    share still builds the reverse lists of the whole graph and runs every
+    hub, as each GPU would after an all-gather of the lists.  Device time of
+    the round from the library's HIP events; median of `reps`."""
+    n = Pd.shape[0]
+    prm = knnd.default_params(precision=precision)
+    cnt = (n + shares - 1) // shares
+    full, part = [], []
+    for _ in range(reps):
+        for out in (full, part):
+            with knnd.Context(Pd, d, K, seed, prm) as c:
+                c.init_graph()
+                c.round()
+                out.append(c.round() if out is full else c.round_share(0, cnt))
+
+    def med(rows, key):
+        v = sorted(r[key] for r in rows)
+        return round(v[len(v) // 2], 3)
+
+    return {"receivers": f"first 1/{shares} ({cnt} of {n}), round 2",
+            "round_ms_full": med(full, "ms"), "round_ms_share": med(part, "ms"),
+            "share_over_full": round(med(part, "ms") / med(full, "ms"), 4),
+            "hub_ms_full": med(full, "ms_hub"), "hub_ms_share": med(part, "ms_hub"),
+            "recv_ms_full": med(full, "ms_recv"), "recv_ms_share": med(part, "ms_recv"),
+            "evals_alg_full": full[0]["evals_alg"], "evals_alg_share": part[0]["evals_alg"]}
+
+
 def copy_calibration():
     """A plain device copy of 1 GiB: the reference for scaling FETCH_SIZE and
     WRITE_SIZE (run under rocprofv3 --pmc)."""
@@ -192,6 +222,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-instances comparison")
     ap.add_argument("--cpu-receivers", type=int, default=400_000)
+    ap.add_argument("--no-share", action="store_true",
+                    help="skip the one-GPU-share round (1/8 of the receivers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device (reference run for HBM counters)")
     ap.add_argument("--oracle-timing", default=None, metavar="WORKLOADS",
@@ -328,6 +360,9 @@ def main():
     }
     if plain is not None:
         line["plain"] = plain
+    if not args.no_share:
+        log("one GPU's share: round 2 over 1/8 of the receivers vs all of them")
+        line["share"] = share_leg(knnd, Pd, d, K, seed, prec)
     if not args.no_batched:
         log("batched instances: one batched call vs one by one")
         line["batched"] = batched_leg(knnd, synth, torch, args.steps)

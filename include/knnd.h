@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define KNND_ABI_VERSION 4
+#define KNND_ABI_VERSION 5
 
 typedef enum {
     KNND_OK = 0,
@@ -313,6 +313,21 @@ int knnd_ctx_set_graph(knnd_ctx* c, const int32_t* idx, const double* kl, int32_
 /* One synchronous round (Sections 3.1, 4.2) and its FCR sample (Section 3.3).
  * Fills st (host) and synchronises the context's stream. */
 int knnd_ctx_round(knnd_ctx* c, knnd_round_stats* st);
+
+/* One round for a share of the receivers.  Each vertex's new list is a task
+ * of its own that reads only the round-start graph, which is what lets the
+ * paper spread the vertices over processors (Section 4.2); a GPU's share of
+ * a descent split over several GPUs is such a range.  The lists of points
+ * first .. first+count-1 are recomputed exactly as knnd_ctx_round would;
+ * every other list is carried over unchanged.  The next round skips no
+ * candidate pair (an edge present a round earlier no longer means that the
+ * pairs through it were evaluated then), so later rounds stay exact.  The hub
+ * kernel computes only the keys those receivers read.  st counts the
+ * share's evaluations, updates and rescues; fcr_hits is taken on the whole
+ * graph after the round.  Returns KNND_ERR_ARG when the context has no graph
+ * yet, first < 0, count < 1 or first + count > n.  Synchronises the
+ * context's stream. */
+int knnd_ctx_round_share(knnd_ctx* c, int64_t first, int64_t count, knnd_round_stats* st);
 
 /* Copy the current lists out: idx [n][K] int32, kl optional [n][K] FP64 (kind). */
 int knnd_ctx_get_graph(knnd_ctx* c, int32_t* idx, double* kl, int32_t on_device);

@@ -33,12 +33,12 @@ KNND_CMP_KL, KNND_CMP_KL_REVERSE, KNND_CMP_HELLINGER, KNND_CMP_L2 = 0, 1, 2, 3
 EXPORTED = [
     "knnd_default_params", "knnd_status_string", "knnd_abi_version", "knnd_build",
     "knnd_build_ex", "knnd_ctx_create", "knnd_ctx_init_graph", "knnd_ctx_set_graph",
-    "knnd_ctx_round", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
+    "knnd_ctx_round", "knnd_ctx_round_share", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
     "knnd_ctx_destroy", "knnd_build_batched", "knnd_exact_knn", "knnd_release_cache",
 ]
 
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class knnd_params(ctypes.Structure):
@@ -100,6 +100,7 @@ def lib():
         "knnd_ctx_init_graph": (ctypes.c_int, [vp, P(knnd_round_stats)]),
         "knnd_ctx_set_graph": (ctypes.c_int, [vp, vp, vp, i32, i32]),
         "knnd_ctx_round": (ctypes.c_int, [vp, P(knnd_round_stats)]),
+        "knnd_ctx_round_share": (ctypes.c_int, [vp, i64, i64, P(knnd_round_stats)]),
         "knnd_ctx_get_graph": (ctypes.c_int, [vp, vp, vp, i32]),
         "knnd_ctx_get_log_table": (ctypes.c_int, [vp, vp, i32]),
         "knnd_ctx_rounds": (ctypes.c_int, [vp]),
@@ -329,6 +330,16 @@ class Context:
         st = lib().knnd_ctx_round(self.h, ctypes.byref(s))
         if st != KNND_OK:
             raise KnndError(st, "knnd_ctx_round")
+        return s.as_dict()
+
+    def round_share(self, first, count):
+        """One round in which only the lists of points first .. first+count-1
+        are recomputed; every other list is carried over, and the next round
+        skips no candidate pair."""
+        s = knnd_round_stats()
+        st = lib().knnd_ctx_round_share(self.h, int(first), int(count), ctypes.byref(s))
+        if st != KNND_OK:
+            raise KnndError(st, "knnd_ctx_round_share")
         return s.as_dict()
 
     def get_graph(self, with_kl=True):

@@ -207,6 +207,8 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   c.num_cu = prop.multiProcessorCount;
   c.stream = reinterpret_cast<hipStream_t>(stream);
   c.n = n;
+  c.own0 = 0;
+  c.own1 = n;
   c.d = d;
   c.D = d + 1;
   c.Dp = (c.D + 1) & ~1;
@@ -442,6 +444,7 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   KNND_HIP(hipEventRecord(c.ev0, c.stream));
   KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
   KNND_HIP(knnd::launch_bin(c));
+  if (c.own0 > 0 || c.own1 < c.n) KNND_HIP(knnd::launch_keep_rows(c));
   KNND_HIP(hipEventRecord(c.evj0, c.stream));
   KNND_HIP(knnd::launch_join_hub(c, c.dstats));
   KNND_HIP(hipEventRecord(c.evh, c.stream));
@@ -451,7 +454,19 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   KNND_HIP(hipEventRecord(c.ev1, c.stream));
   c.cur ^= 1;
   c.round += 1;
+  c.no_skip_next = c.own0 > 0 || c.own1 < c.n;
   return read_stats(c, st, true);
+}
+
+// One round in which only the receivers [first, first + count) get new lists.
+int run_round_share(Ctx& c, int64_t first, int64_t count, knnd_round_stats* st) {
+  if (!c.have_graph || first < 0 || count < 1 || first > c.n - count) return KNND_ERR_ARG;
+  c.own0 = first;
+  c.own1 = first + count;
+  const int r = run_round(c, st);
+  c.own0 = 0;
+  c.own1 = c.n;
+  return r;
 }
 
 int get_graph(Ctx& c, int32_t* idx, double* kl, int32_t on_device) {
@@ -825,6 +840,11 @@ int knnd_ctx_set_graph(knnd_ctx* h, const int32_t* idx, const double* kl, int32_
 int knnd_ctx_round(knnd_ctx* h, knnd_round_stats* st) {
   if (!h) return KNND_ERR_ARG;
   return run_round(h->c, st);
+}
+
+int knnd_ctx_round_share(knnd_ctx* h, int64_t first, int64_t count, knnd_round_stats* st) {
+  if (!h) return KNND_ERR_ARG;
+  return run_round_share(h->c, first, count, st);
 }
 
 int knnd_ctx_get_graph(knnd_ctx* h, int32_t* idx, double* kl, int32_t on_device) {

@@ -55,6 +55,14 @@ struct Ctx {
   int max_rounds = 100;
   int round = 0;      // rounds completed
   bool have_graph = false;
+  // receivers whose lists a round updates: [own0, own1) (all of them unless
+  // a round is restricted to one share of the receivers)
+  int64_t own0 = 0, own1 = 0;
+  // the last round updated only a share of the receivers: an edge present a
+  // round earlier no longer means that its pairs were evaluated then (a
+  // receiver outside the share evaluated nothing), so the next round skips
+  // no pair
+  bool no_skip_next = false;
 
   // device buffers
   void* P = nullptr;          // [n][D] points (copy owned by the context)
@@ -160,6 +168,8 @@ struct JoinArgs {
   int32_t* sl_n;
   uint32_t* sl_id;
   double* sl_key;
+  // receivers whose lists this round updates, [own0, own1)
+  int64_t own0, own1;
 };
 
 // Device memory of the library comes from a per-process cache of freed
@@ -185,6 +195,7 @@ hipError_t launch_join_hub(const Ctx& c, int64_t* stats);
 hipError_t launch_join_recv(const Ctx& c, int64_t* stats);
 hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits);
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out);
+hipError_t launch_keep_rows(const Ctx& c);
 hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad);
 // batched groups
 hipError_t launch_batch_reduce(const Ctx& c);

@@ -45,6 +45,21 @@ __global__ void k_strip(const uint32_t* __restrict__ F, int64_t cnt, int K, int 
     out[i] = (int32_t)(F[x * Ks + (i - x * K)] & IDMASK);
   }
 }
+// A round restricted to the receivers [own0, own1) carries every other list
+// over unchanged, its edges marked new (as for a snapshot loaded from
+// outside; the round after a restricted one skips no pair anyway).
+__global__ void k_keep_rows(const uint32_t* __restrict__ F, const double* __restrict__ keys, int64_t n, int K,
+                            int Ks, int64_t own0, int64_t own1, uint32_t* __restrict__ Fn,
+                            double* __restrict__ keysn) {
+  const int64_t cnt = n * K;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = i / K;
+    if (x >= own0 && x < own1) continue;
+    const int64_t j = i - x * K;
+    Fn[x * Ks + j] = (F[x * Ks + j] & IDMASK) | NEWBIT;
+    keysn[i] = keys[i];
+  }
+}
 // F = idx | NEWBIT (an externally supplied snapshot: every edge counts as
 // new).  An index outside [0, n) is replaced by 0 and counted in *bad.
 __global__ void k_load_idx(const int32_t* __restrict__ idx, int64_t cnt, int64_t n, int K, int Ks,
@@ -486,7 +501,8 @@ __device__ __forceinline__ int64_t table_need(int64_t c, int K, int64_t n) {
 __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr, int64_t n, int K,
                                              int32_t* __restrict__ counts, int32_t* __restrict__ lists,
                                              const int32_t* __restrict__ inst_of,
-                                             const int32_t* __restrict__ iactive) {
+                                             const int32_t* __restrict__ iactive, int64_t own0,
+                                             int64_t own1) {
   __shared__ int s_wcnt[NCLASS][4];
   __shared__ int s_base[NCLASS];
   const int lane = lane_id();
@@ -494,8 +510,9 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
   for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = x0 + threadIdx.x;
     int cls = -1;
-    // (receivers of a stopped instance of a batched group are not binned)
-    if (x < n && (!inst_of || iactive[inst_of[x]])) {
+    // (receivers of a stopped instance of a batched group, or outside the
+    // share of receivers this round updates, are not binned)
+    if (x < n && x >= own0 && x < own1 && (!inst_of || iactive[inst_of[x]])) {
       const int64_t c = rowptr[x + 1] - rowptr[x];
       const int64_t need2 = 2 * table_need(c, K, n);
       if (need2 <= (int64_t)(CLASS_CAP_MIN << 4)) {  // exact bound fits a small table
@@ -555,6 +572,8 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* sh /*[4]*/) {
 __device__ __forceinline__ bool inactive(const JoinArgs& a, int64_t v) {
   return a.iactive && !a.iactive[a.inst_of[v]];
 }
+// r is one of the receivers this round updates
+__device__ __forceinline__ bool owned(const JoinArgs& a, int64_t r) { return r >= a.own0 && r < a.own1; }
 __device__ __forceinline__ void hub_count(const JoinArgs& a, int64_t v, int64_t d) {
   if (!a.vcnt) return;
 #pragma unroll
@@ -642,6 +661,7 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
         b0 = a.nKK + (v * K + sp) * a.Ks;  // FC
         b1 = a.di_off + v * K + sp;        // DI
       }
+      if (!owned(a, r)) continue;
       const PT* pr = P + r * D;
       const double* lr = a.L + r * Dp;
       for (int ci = ci0; ci < K1; ci += cstep) {
@@ -743,13 +763,13 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
     const int nR = cv + K;
     for (int k0 = 0; k0 < nR; k0 += WAVE) {
       const int k = k0 + lane;
-      const bool on = k < nR;
+      const bool in = k < nR;
       // all lanes take part in the shuffle (a disabled source lane reads as 0)
       const uint32_t fsp = (uint32_t)__shfl((int)fv, (k >= cv && k < nR) ? k - cv : 0, WAVE);
       int64_t r = 0, b0 = 0, b1 = -1;
       uint32_t rnew = 0;
       int excl = -1;
-      if (on) {
+      if (in) {
         if (k < cv) {
           const uint32_t e = a.col[rp + k];
           r = e & IDMASK;
@@ -764,6 +784,7 @@ __global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __res
           b1 = a.di_off + v * K + sp;        // DI
         }
       }
+      const bool on = in && owned(a, r);
       // which of this receiver's K+1 candidate slots need a key (bit ci)
       uint64_t need = 0;
       if (on) {
@@ -940,9 +961,9 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
     for (int k0 = 0; k0 < nR; k0 += 16) {
       // metadata of row k0 + col (the four lanes sharing col compute the same)
       const int row = k0 + col;
-      const bool on = row < nR;
+      bool on = row < nR;
       const uint32_t fsp = (uint32_t)__shfl((int)fv, (row >= cv && row < nR) ? row - cv : 0, WAVE);
-      int64_t r = 0, b0 = 0, b1 = -1;
+      int64_t r = 0, b0 = -1, b1 = -1;  // b0 < 0: no row to write (out of range or not owned)
       uint32_t rnew = 0;
       int excl = -1;
       if (on) {
@@ -958,6 +979,10 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
           excl = sp;
           b0 = a.nKK + (v * K + sp) * a.Ks;  // FC
           b1 = a.di_off + v * K + sp;        // DI
+        }
+        if (!owned(a, r)) {
+          on = false;
+          b0 = b1 = -1;
         }
       }
       const bool want = on && (!a.skip || rnew != 0 || cand_new != 0);
@@ -992,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
           const int64_t rb1 = (int64_t)shfl_u64((uint64_t)b1, src);
           const int rex = __shfl(excl, src, WAVE);
           const uint32_t rnw = shfl_u32(rnew, src);
-          const bool ron = k0 + src < nR;
+          const bool ron = rb0 >= 0;  // in range and owned
           bool need;
           int64_t pos;
           if (ci < K) {
@@ -1787,7 +1812,7 @@ __global__ __launch_bounds__(256) void k_merge(JoinArgs a) {
   const PT* P = reinterpret_cast<const PT*>(a.P);
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   int64_t my_upd = 0, my_err = 0, my_resc = 0;
-  for (int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); x < a.n; x += nwaves) {
+  for (int64_t x = a.own0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); x < a.own1; x += nwaves) {
     if (inactive(a, x)) continue;  // whole wave
     const int nc = a.sl_n[x];
     if (nc < 0) continue;           // merged by the receiver kernel
@@ -1953,7 +1978,7 @@ hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
 hipError_t launch_bin(const Ctx& c) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c.stream, c.class_count, (int64_t)NCLASS);
   hipLaunchKernelGGL(k_bin, dim3(grid_for(c.n, 256, 8192)), dim3(256), 0, c.stream, c.rowptr, c.n, c.K,
-                     c.class_count, c.class_list, c.inst_of, c.iactive);
+                     c.class_count, c.class_list, c.inst_of, c.iactive, c.own0, c.own1);
   return hipGetLastError();
 }
 
@@ -2087,7 +2112,7 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   a.Fn = c.F[c.cur ^ 1];
   a.keysn = c.keys[c.cur ^ 1];
   a.stats = stats;
-  a.skip = (c.flags & 1) ? 0 : 1;
+  a.skip = ((c.flags & 1) || c.no_skip_next) ? 0 : 1;
   a.gtab = c.gtab;
   a.gcand = c.gcand;
   a.gckey = c.gckey;
@@ -2104,6 +2129,8 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   a.sl_n = c.sl_n;
   a.sl_id = c.sl_id;
   a.sl_key = c.sl_key;
+  a.own0 = c.own0;
+  a.own1 = c.own1;
   return a;
 }
 
@@ -2147,6 +2174,13 @@ hipError_t launch_join_recv(const Ctx& c, int64_t* stats) {
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out) {
   const int64_t cnt = c.n * c.K;
   hipLaunchKernelGGL(k_strip, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, F, cnt, c.K, c.Ks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_keep_rows(const Ctx& c) {
+  const int64_t cnt = c.n * c.K;
+  hipLaunchKernelGGL(k_keep_rows, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, c.F[c.cur],
+                     c.keys[c.cur], c.n, c.K, c.Ks, c.own0, c.own1, c.F[c.cur ^ 1], c.keys[c.cur ^ 1]);
   return hipGetLastError();
 }
 
