@@ -1803,10 +1803,13 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
 // into the old list held in registers.  In the mixed form every listed
 // candidate gets its canonical FP64 key here (the rescue): the list's members
 // passed the lower-bound test, and bounding Theta first would cost more than
-// these few gathers.
+// these few gathers.  x's row and logs are staged in LDS, one slot per wave
+// (fewer registers than holding them per lane: five waves per SIMD).
 // ---------------------------------------------------------------------------
 template <typename PT, bool MIX>
-__global__ __launch_bounds__(256) void k_merge(JoinArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIX ? 5 : 1))) void k_merge(JoinArgs a) {
+  __shared__ double s_xr[MIX ? 4 : 1][MIX ? HUB_MAXD + 16 : 1], s_lr[MIX ? 4 : 1][MIX ? HUB_MAXD + 16 : 1];
+  const int wv = MIX ? (int)(threadIdx.x >> 6) : 0;
   const int lane = lane_id();
   const int K = a.K, D = a.D, Dp = a.Dp;
   const PT* P = reinterpret_cast<const PT*>(a.P);
@@ -1819,11 +1822,20 @@ __global__ __launch_bounds__(256) void k_merge(JoinArgs a) {
     const uint32_t old = lane < K ? a.F[x * a.Ks + lane] : 0u;
     uint64_t lk = lane < K ? key_bits(a.keys[x * K + lane]) : KEY_SENTINEL;
     uint32_t li = lane < K ? (old & IDMASK) : IDMASK;
+    if (MIX && nc > 0) {
+      if (lane < D) {
+        s_xr[wv][lane] = (double)P[x * D + lane];
+        s_lr[wv][lane] = a.L[x * Dp + lane];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     for (int b0 = 0; b0 < nc; b0 += WAVE) {
       const bool ok = b0 + lane < nc;
       const uint32_t z = ok ? a.sl_id[x * SHORT_LIST + b0 + lane] : 0u;
       double key = 0.0;
-      if (ok) key = MIX ? canonical_key(P + x * D, a.L + x * Dp, a.L + (int64_t)z * Dp, D)
+      if (ok) key = MIX ? canonical_key_lds(s_xr[wv], s_lr[wv], a.L + (int64_t)z * Dp, D)
                         : a.sl_key[x * SHORT_LIST + b0 + lane];
       uint64_t bk = ok ? key_bits(key) : KEY_SENTINEL;
       uint32_t bi = ok ? (z | NEWBIT) : IDMASK;
@@ -1831,6 +1843,11 @@ __global__ __launch_bounds__(256) void k_merge(JoinArgs a) {
       wave_merge(lk, li, bk, bi);
     }
     write_row(a, x, K, lane, lk, li, old, my_upd, my_err);
+    if (MIX && nc > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     if (MIX) {
       if (lane == 0) my_resc += nc;
       if (a.vcnt && lane == 0) {
