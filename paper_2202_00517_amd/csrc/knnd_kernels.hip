@@ -741,8 +741,18 @@ __device__ __forceinline__ double hub_fold(const double (&pr)[MAXD], const doubl
   return acc + 0.0;
 }
 
+// Rows of up to 24 coordinates run three waves per SIMD: at 24 the compiler
+// would hold both rows in registers at two waves (195 VGPRs); three waves
+// with a few spilled values take the round's hub pass at 10^6 points from
+// 16.5 to 15.1 ms.  Wider rows spill too much at three.
+template <int MAXD>
+constexpr int hub_reg_waves_per_eu() {
+  return MAXD <= 24 ? 3 : 1;
+}
+
 template <int MAXD, typename PT, int CK>
-__global__ __launch_bounds__(256) void k_hub_reg(JoinArgs a, const double* __restrict__ L,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hub_reg_waves_per_eu<MAXD>())))
+void k_hub_reg(JoinArgs a, const double* __restrict__ L,
                                                  const PT* __restrict__ P, const double* __restrict__ Pd) {
   constexpr int CH = 16;  // candidates per LDS tile
   __shared__ double s_keys[4][WAVE][CH + 1];
