@@ -899,23 +899,30 @@ __global__ void k_prep_mixed(const PT* __restrict__ P, const double* __restrict_
                              int DK, H* __restrict__ Ph, H* __restrict__ Lh, double* __restrict__ S,
                              unsigned long long* __restrict__ maxbits /*[2]: max |x|, max |log x|*/) {
   double pm = 0.0, lm = 0.0;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int i = 0; i < DK; ++i) {
-      double p = 0.0, l = 0.0;
-      if (i < D) {
-        p = (double)P[x * D + i];
-        l = L[x * Dp + i];
-        s = fma(p, l, s);
-        pm = fmax(pm, fabs(p));
-        lm = fmax(lm, fabs(l));
-      }
-      const H ph = (H)p, lh = (H)l;
-      Ph[x * 2 * DK + i] = ph;
-      Ph[x * 2 * DK + DK + i] = (H)(p - (double)ph);
-      Lh[x * 2 * DK + i] = lh;
-      Lh[x * 2 * DK + DK + i] = (H)(l - (double)lh);
+  // the split rows: one thread per (point, coordinate) of the [n][DK] grid,
+  // so that consecutive threads store consecutive elements (DK = 32 or 64)
+  const int sh = DK == 32 ? 5 : 6;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (n << sh); t += stride) {
+    const int64_t x = t >> sh;
+    const int i = (int)(t & (DK - 1));
+    double p = 0.0, l = 0.0;
+    if (i < D) {
+      p = (double)P[x * D + i];
+      l = L[x * Dp + i];
+      pm = fmax(pm, fabs(p));
+      lm = fmax(lm, fabs(l));
     }
+    const H ph = (H)p, lh = (H)l;
+    Ph[x * 2 * DK + i] = ph;
+    Ph[x * 2 * DK + DK + i] = (H)(p - (double)ph);
+    Lh[x * 2 * DK + i] = lh;
+    Lh[x * 2 * DK + DK + i] = (H)(l - (double)lh);
+  }
+  // S(x): the ascending fold, one thread per point
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += stride) {
+    double s = 0.0;
+    for (int i = 0; i < D; ++i) s = fma((double)P[x * D + i], L[x * Dp + i], s);
     S[x] = s;
   }
   // non-negative doubles order like their bit patterns
@@ -2104,7 +2111,7 @@ static hipError_t launch_hub_mfma(const Ctx& c, const JoinArgs& a) {
 
 template <typename PT, typename H>
 static void launch_prep_t(const Ctx& c, unsigned long long* maxbits) {
-  hipLaunchKernelGGL((k_prep_mixed<PT, H>), dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream,
+  hipLaunchKernelGGL((k_prep_mixed<PT, H>), dim3(grid_for(c.n * c.dk, 256, 8192)), dim3(256), 0, c.stream,
                      (const PT*)c.P, c.L, c.n, c.D, c.Dp, c.dk, (H*)c.Ph, (H*)c.Lh, c.S, maxbits);
 }
 
