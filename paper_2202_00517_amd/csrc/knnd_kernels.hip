@@ -1189,14 +1189,14 @@ __device__ __forceinline__ double mix_eps(const JoinArgs& a, double Sx, double k
 // An upper bound T on the K-th smallest of {old keys} u {k~_i + eps_i}: the
 // largest value in the first bins (of a monotone histogram over values <= hi)
 // that together hold at least K values.
-template <int NW>
-__device__ double kth_upper_bound(int K, int ncand, const double* kx, double hi, const double* ckey,
+template <int NW, typename KGet>
+__device__ double kth_upper_bound(int K, int ncand, const double* kx, double hi, KGet ktilde,
                                   const JoinArgs& a, double Sx, int32_t* hist, int* s_bstar, int64_t* s_red,
                                   double* s_dred) {
   constexpr int NT = NW * 64;
   const int tid = threadIdx.x;
   auto ub = [&](int i) {
-    const double kt = ckey[i];
+    const double kt = ktilde(i);
     return kt + mix_eps(a, Sx, kt);
   };
   double lo = kx[0];
@@ -1278,16 +1278,17 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
 
 // Occupancy targets: the tables of up to 2048 slots leave LDS for four blocks
 // per CU (receivers there have at most 1023 occurrences: four per thread in
-// flight cover them), the 4096-slot class for three, the 8192-slot class
+// flight cover them), the 4096-slot class for three (four in the mixed form,
+// whose candidate list holds FP32 cross terms), the 8192-slot class
 // (candidate list in global memory) for four with four occurrences per
 // thread in flight.
-template <int CAP>
+template <int CAP, int MODE>
 constexpr int recv_waves_per_eu() {
-  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? 3 : (CAP == 8192 ? 4 : 1));
+  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? (MODE == 2 ? 4 : 3) : (CAP == 8192 ? 4 : 1));
 }
 
 template <int CAP, typename PT, int MODE, int NW>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(recv_waves_per_eu<CAP>())))
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(recv_waves_per_eu<CAP, MODE>())))
 void k_recv(JoinArgs a, int32_t* __restrict__ lists,
                                                   int32_t* __restrict__ counts, int cls) {
   constexpr bool SEG = MODE >= 1;  // keys (or cross terms) come from the hub kernel
@@ -1298,7 +1299,8 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   constexpr bool GUARD = CAP > 8192;   // optimistically sized table (see k_bin)
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
-  constexpr int U = (GLOB || CAP <= 2048 || CAP == 8192) ? 4 : 8;  // occurrences per thread in flight
+  // occurrences per thread in flight
+  constexpr int U = (GLOB || CAP <= 2048 || CAP == 8192 || (CAP == 4096 && MODE == 2)) ? 4 : 8;
   // a guarded class overshoots LIMIT by at most one batch (U per thread)
   static_assert(!BIG || LIMIT + U * NT <= BIG_CAND, "candidate list of the big classes too small");
   // occurrence counter: T < 2^32 in the LDS classes (their binning bounds
@@ -1306,9 +1308,13 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   // T = c (K+1) + K^2 < 2^22)
   using IT = typename std::conditional<GLOB, int64_t, uint32_t>::type;
   using KT = typename std::conditional<MIX, float, double>::type;  // what a key slot holds
+  // mixed form, LDS classes: the candidate list keeps the FP32 cross term C~
+  // (k~ = S(x) - C~ is formed again where needed), half the LDS of FP64 k~
+  constexpr bool CF = MIX && !GLOB && !BIG;
   __shared__ __align__(16) uint32_t s_tab[GLOB ? 1 : CAP];
   __shared__ uint32_t s_cid[CC];
-  __shared__ double s_ckey[SEG ? CC : 1];
+  __shared__ double s_ckey[(SEG && !CF) ? CC : 1];
+  __shared__ float s_ckf[CF ? CC : 1];
   __shared__ uint32_t s_fx[WAVE];
   __shared__ double s_kx[WAVE];
   __shared__ uint32_t s_col[NT];  // the co-friend list, when it has at most NT entries
@@ -1344,9 +1350,9 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   uint32_t* tab = GLOB ? a.gtab + (int64_t)blockIdx.x * a.gstride : s_tab;
   uint32_t* cid = GLOB ? a.gcand + (int64_t)blockIdx.x * half
                        : (BIG ? a.bcand + (int64_t)blockIdx.x * BIG_CAND : s_cid);
-  double* ckey = SEG ? (GLOB ? a.gckey + (int64_t)blockIdx.x * half
-                             : (BIG ? a.bckey + (int64_t)blockIdx.x * BIG_CAND : s_ckey))
-                     : nullptr;
+  double* ckey = (SEG && !CF) ? (GLOB ? a.gckey + (int64_t)blockIdx.x * half
+                                      : (BIG ? a.bckey + (int64_t)blockIdx.x * BIG_CAND : s_ckey))
+                              : nullptr;
   const int64_t ccap = GLOB ? half : (BIG ? (int64_t)BIG_CAND : (int64_t)CC);  // candidate-list capacity
   const PT* P = reinterpret_cast<const PT*>(a.P);
   const int nitems = counts[cls];
@@ -1525,7 +1531,10 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
           if (!((appm >> u) & 1)) continue;
           if (at < ccap) {
             cid[at] = z[u];
-            if (SEG) ckey[at] = key_of(u);
+            if (CF)
+              s_ckf[at] = (float)kr[u];
+            else if (SEG)
+              ckey[at] = key_of(u);
           } else if (GUARD) {
             s_over = 1;  // list full: the global-memory class redoes this receiver
           } else {
@@ -1560,6 +1569,13 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
     // (s_ncand exceeds the list capacity only after a reported internal error)
     const int ncand = (int)min((int64_t)s_ncand, ccap);
     const double* kx = s_kx;  // the old list's keys
+    // k~ of listed candidate i (mixed form); the listed key otherwise
+    auto ktil = [&](int i) -> double {
+      if constexpr (CF)
+        return Sx - (double)s_ckf[i];
+      else
+        return ckey[i];
+    };
     bool done = false;
     if (SEG) {
       // a short list goes to k_merge (one wave per receiver, no block
@@ -1585,11 +1601,11 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       if (tid == 0) s_ns = all ? ncand : 0;
       if (!all) {
         const double theta =
-            kth_upper_bound<NW>(K, ncand, kx, tau0, ckey, a, Sx, s_hist, &s_bstar, s_red, s_dred);
+            kth_upper_bound<NW>(K, ncand, kx, tau0, ktil, a, Sx, s_hist, &s_bstar, s_red, s_dred);
         if (tid == 0) s_theta = theta;
         // compact the rescue set (its positions in the candidate list)
         for (int i = tid; i < ncand; i += NT) {
-          const double kt = ckey[i];
+          const double kt = ktil(i);
           if (kt - mix_eps(a, Sx, kt) <= theta) {
             const int pos = atomicAdd(&s_ns, 1);
             if (pos < SEL_SURV) s_si[pos] = (uint32_t)i;
@@ -1622,6 +1638,9 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
           }
           write_row(a, x, K, lane, lk, li, lane < K ? s_fx[lane] : 0u, my_upd, my_err);
         }
+      } else if (CF) {
+        // a large rescue set with FP32 cross terms in the list: the final
+        // merge forms each canonical key as it goes (+inf beyond Theta)
       } else {
         // a large rescue set: canonical keys in place, +inf for the rest
         // (bounds compared with the same Theta), then the exact selection
@@ -1636,7 +1655,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       }
     }
 
-    if (!done && SEG && ncand <= 2 * WAVE) {
+    if (!done && SEG && !CF && ncand <= 2 * WAVE) {
       // D (hub form, short list): wave 0 sorts the listed candidates and
       // merges them into the old list
       done = true;
@@ -1652,7 +1671,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
         }
         write_row(a, x, K, lane, lk, li, lane < K ? s_fx[lane] : 0u, my_upd, my_err);
       }
-    } else if (!done && SEG) {
+    } else if (!done && SEG && !CF) {
       // D (hub form): every key is known and every listed candidate has key
       // <= tau0.  Histogram the candidates and the old list over
       // [kmin, tau0] with a monotone binning and find the first bin b* where
@@ -1746,10 +1765,16 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
         uint32_t z = IDMASK;
         if (valid) {
           z = cid[i];
-          if (SEG)
+          if (CF) {  // (only after a large rescue set)
+            const double kt = ktil(i);
+            double exact = INFINITY;
+            if (kt - mix_eps(a, Sx, kt) <= s_theta) exact = canonical_key_lds(s_xr, s_lr, a.L + (int64_t)z * Dp, D);
+            kb = key_bits(exact);
+          } else if (SEG) {
             kb = key_bits(ckey[i]);
-          else
+          } else {
             kb = key_bits(key_of_kind<PT>(a.ck, P, x, z, a.L, D, Dp));
+          }
         }
         my_perf += (!SEG && valid) ? 1 : 0;
         const uint64_t kk = shfl_u64(lk, K - 1);
