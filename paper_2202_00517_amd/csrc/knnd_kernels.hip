@@ -18,7 +18,7 @@ namespace knnd {
 
 constexpr int SEL_BINS = 1024;  // histogram bins of the threshold selection
 constexpr int CSR_CHUNK = 65536;      // edges per block of the partition passes (rounded to a multiple of K)
-constexpr int SMALL_NW_CAP = 1024;  // receiver classes up to this table size run two waves per receiver
+constexpr int SMALL_NW_CAP = 2048;  // receiver classes up to this table size run two waves per receiver
 constexpr int SEL_SURV = 256;   // survivors handled by the fast selection path
 
 // ---------------------------------------------------------------------------
