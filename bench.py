@@ -29,6 +29,7 @@ import numpy as np  # noqa: E402
 
 METRIC = "comparator evals/sec + time-to-graph (n=1e6,d=20,K=30), mixed vs plain"
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_recv_c3.json")
@@ -330,6 +331,13 @@ def main():
            else "k_hub_reg (FP64 keys)", "avg_launch_ms": round(sum(hub_ms) / len(hub_ms), 3),
            "evals_per_launch": int(sum(s["evals_performed"] - s["rescues"] for s in rounds)
                                    / len(rounds))}
+    if mixed:
+        # matrix-core use: one multiply-add per coordinate of each stored cross
+        # term, against the dense BF16 peak (the split form issues three MFMAs
+        # per term over coordinates padded to 32, so issued work is about 4.6x)
+        tflops = hub["evals_per_launch"] * 2 * D / (hub["avg_launch_ms"] * 1e-3) / 1e12
+        hub["mfma"] = {"useful_tflops": round(tflops, 3), "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+                       "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 6)}
     steps_ms = sorted(1e3 * t for _, t in results)
 
     line = {
