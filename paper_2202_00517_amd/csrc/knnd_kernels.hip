@@ -1299,8 +1299,10 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   constexpr bool GUARD = CAP > 8192;   // optimistically sized table (see k_bin)
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
-  // occurrences per thread in flight
-  constexpr int U = (GLOB || CAP <= 2048 || CAP == 8192 || (CAP == 4096 && MODE == 2)) ? 4 : 8;
+  // occurrences per thread in flight (the 16384- and 32768-slot classes are
+  // held to one or two blocks per CU by their tables, which leaves registers
+  // for sixteen)
+  constexpr int U = (GLOB || CAP <= 2048 || CAP == 8192 || (CAP == 4096 && MODE == 2)) ? 4 : (CAP >= 16384 ? 16 : 8);
   // a guarded class overshoots LIMIT by at most one batch (U per thread)
   static_assert(!BIG || LIMIT + U * NT <= BIG_CAND, "candidate list of the big classes too small");
   // occurrence counter: T < 2^32 in the LDS classes (their binning bounds
