@@ -81,6 +81,7 @@ def test_null_pointers_are_argument_errors():
     r = ctypes.c_int32()
     assert lib.knnd_build(None, 10, 3, 2, 1, None, None, 4, ctypes.byref(r)) == knnd.KNND_ERR_ARG
     assert lib.knnd_ctx_round(None, None) == knnd.KNND_ERR_ARG
+    assert lib.knnd_ctx_round_share(None, 0, 1, None) == knnd.KNND_ERR_ARG
     assert lib.knnd_ctx_destroy(None) == knnd.KNND_ERR_ARG
     assert lib.knnd_ctx_rounds(None) == -1
 
