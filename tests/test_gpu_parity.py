@@ -769,3 +769,19 @@ def test_mixed_near_duplicates_resolved_by_rescue(prec):
     P = (P / P.sum(axis=1, keepdims=True)).astype(np.float32)
     g, _ = full_compare(P, 9, 12, 47, precision=prec)
     assert sum(s["rescues"] for s in g["stats"]) > 0
+
+
+@pytest.mark.parametrize("prec", [knnd.KNND_PREC_MIXED_BF16, knnd.KNND_PREC_MIXED_FP16], ids=["bf16", "fp16"])
+def test_mixed_large_rescue_sets(prec):
+    # two clusters of 1200 near-duplicates at K = 30: in round 1 a receiver
+    # lists the hundreds of candidates from its own cluster, whose key
+    # intervals all contain the K-th bound, so its rescue set exceeds the
+    # fast path's 256 and the keys are formed in the block's final merge
+    base = synth.dirichlet(912, 2, 9, np.float64)
+    rng = np.random.default_rng(913)
+    P = np.repeat(base, 1200, axis=0) * (1.0 + 1e-6 * rng.standard_normal((2400, 10)))
+    P = (P / P.sum(axis=1, keepdims=True)).astype(np.float32)
+    g, _ = full_compare(P, 9, 30, 48, precision=prec)
+    # more than 256 rescues per receiver on average in some round: at least
+    # one receiver took the large-rescue path
+    assert max(s["rescues"] for s in g["stats"]) > 256 * 2400
