@@ -154,7 +154,8 @@ void free_ctx(Ctx& c) {
                   c.tilesum, c.class_count, c.class_list, c.gtab, c.gcand, c.gckey, c.bcand, c.bckey,
                   c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32,
                   c.inst_of, c.ioff, c.iseed, c.iM, c.iD, c.iactive, c.istats, c.vcnt,
-                  c.sl_n, c.sl_id, c.sl_key, c.csr_T, c.csr_bcount, c.csr_bfill, c.csr_bbase, c.Pw};
+                  c.sl_n, c.sl_id, c.sl_key, c.csr_T, c.csr_bcount, c.csr_bfill, c.csr_bbase, c.Pw,
+                  c.vchg, c.vev};
   // the blocks go back to the cache: the context's work must have finished
   (void)hipStreamSynchronize(c.stream);
   for (void* b : bufs) knnd::pool_free(b);
@@ -345,7 +346,10 @@ int create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, c
   const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
   KNND_HIP(hipMemcpyAsync(c.P, points, (size_t)n * c.D * esz,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.stream));
-  return finish_create(c);
+  st = finish_create(c);
+  // neighbourhood tracking: hub form only (k_merge carries the lists over)
+  if (st == KNND_OK) c.track_capable = c.use_hub;
+  return st;
 }
 
 // Split 16-bit operand copies and the error-bound constants of the mixed
@@ -435,6 +439,7 @@ int init_graph(Ctx& c, knnd_round_stats* st) {
   KNND_HIP(hipEventRecord(c.ev1, c.stream));
   c.round = 0;
   c.have_graph = true;
+  c.track_ok = false;
   return read_stats(c, st, false);
 }
 
@@ -443,19 +448,42 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
   KNND_HIP(hipEventRecord(c.ev0, c.stream));
   KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
-  KNND_HIP(knnd::launch_bin(c));
-  if (c.own0 > 0 || c.own1 < c.n) KNND_HIP(knnd::launch_keep_rows(c));
+  // receivers whose neighbourhood did not change keep their list and count.
+  // The flags are gathered once the last round changed at most 4% of the
+  // entries, and used once it changed at most 2% (before, nearly every
+  // neighbourhood changes); using them needs the last round's flags of every
+  // receiver and the pair skipping in force
+  const bool full = c.own0 == 0 && c.own1 == c.n;
+  const int64_t nK = c.n * (int64_t)c.K;
+  const bool want = c.track_capable && full && c.last_updates >= 0 && c.last_updates * 25 <= nK;
+  if (want && !c.vchg) {  // first use: 24 bytes per point
+    if (dalloc(&c.vchg, (size_t)c.n) != hipSuccess || dalloc(&c.vev, (size_t)c.n * knnd::VC_N) != hipSuccess ||
+        knnd::launch_zero_i32(c.vchg, c.n, c.stream) != hipSuccess) {
+      (void)hipGetLastError();  // no tracking then: every receiver is evaluated, as without it
+      c.track_capable = false;
+    }
+  }
+  c.tracking = want && c.track_capable && c.vchg && c.vev;
+  const bool carry = c.tracking && c.track_ok && !c.no_skip_next && !(c.flags & KNND_FLAG_NO_SKIP) &&
+                     c.last_updates * 50 <= nK;
+  KNND_HIP(knnd::launch_bin(c, carry));
+  if (!full) KNND_HIP(knnd::launch_keep_rows(c));
   KNND_HIP(hipEventRecord(c.evj0, c.stream));
   KNND_HIP(knnd::launch_join_hub(c, c.dstats));
   KNND_HIP(hipEventRecord(c.evh, c.stream));
   KNND_HIP(knnd::launch_join_recv(c, c.dstats));
   KNND_HIP(hipEventRecord(c.evj1, c.stream));
+  if (c.tracking) KNND_HIP(knnd::launch_track(c));
   KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], c.round + 1, c.dstats + knnd::STAT_HITS));
   KNND_HIP(hipEventRecord(c.ev1, c.stream));
   c.cur ^= 1;
   c.round += 1;
-  c.no_skip_next = c.own0 > 0 || c.own1 < c.n;
-  return read_stats(c, st, true);
+  c.no_skip_next = !full;
+  c.track_ok = c.tracking;
+  c.tracking = false;
+  const int r = read_stats(c, st, true);
+  c.last_updates = r == KNND_OK ? c.hstats[knnd::STAT_UPDATES] : -1;
+  return r;
 }
 
 // One round in which only the receivers [first, first + count) get new lists.
@@ -637,7 +665,7 @@ int group_round(Group& g, int r) {
   } else {
     KNND_HIP(knnd::launch_zero_i32(c.vcnt, c.n * knnd::VC_N, c.stream));
     KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
-    KNND_HIP(knnd::launch_bin(c));
+    KNND_HIP(knnd::launch_bin(c, false));
     KNND_HIP(hipEventRecord(c.evj0, c.stream));
     KNND_HIP(knnd::launch_join_hub(c, c.dstats));
     KNND_HIP(hipEventRecord(c.evh, c.stream));
@@ -834,6 +862,7 @@ int knnd_ctx_set_graph(knnd_ctx* h, const int32_t* idx, const double* kl, int32_
   }
   c.round = round;
   c.have_graph = true;
+  c.track_ok = false;
   return KNND_OK;
 }
 

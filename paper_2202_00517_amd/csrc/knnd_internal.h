@@ -63,6 +63,17 @@ struct Ctx {
   // receiver outside the share evaluated nothing), so the next round skips
   // no pair
   bool no_skip_next = false;
+  // single descents in the hub form: per point, bit 0 = its list gained an
+  // entry in the last round, bit 1 = some list dropped it; and the
+  // evaluation count of its last update.  A receiver whose own flags and
+  // whose friends' and co-friends' bit 0 are clear has the same candidate
+  // set and list as one round earlier (see k_bin).
+  int32_t* vchg = nullptr;
+  int32_t* vev = nullptr;  // [n][VC_N] per-point counters of the last update (VC_EVALS is used)
+  bool track_capable = false; // a single descent in the hub form (arrays allocated on first use)
+  bool tracking = false;      // this round gathers the flags and counts
+  bool track_ok = false;      // the last round updated every receiver with tracking on
+  int64_t last_updates = -1;  // updates of the last round
 
   // device buffers
   void* P = nullptr;          // [n][D] points (copy owned by the context)
@@ -190,12 +201,13 @@ hipError_t launch_widen(const Ctx& c);
 hipError_t launch_init_graph(const Ctx& c);
 hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits);
 hipError_t launch_csr(const Ctx& c, const uint32_t* F);
-hipError_t launch_bin(const Ctx& c);
+hipError_t launch_bin(const Ctx& c, bool carry);
 hipError_t launch_join_hub(const Ctx& c, int64_t* stats);
 hipError_t launch_join_recv(const Ctx& c, int64_t* stats);
 hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits);
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out);
 hipError_t launch_keep_rows(const Ctx& c);
+hipError_t launch_track(const Ctx& c);
 hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad);
 // batched groups
 hipError_t launch_batch_reduce(const Ctx& c);

@@ -45,6 +45,24 @@ __global__ void k_strip(const uint32_t* __restrict__ F, int64_t cnt, int K, int 
     out[i] = (int32_t)(F[x * Ks + (i - x * K)] & IDMASK);
   }
 }
+// Neighbourhood flags of a round (one wave per point): bit 0 of x when its
+// new list holds an entry that entered, bit 1 of every old friend of x that
+// the new list no longer holds (it lost x as a co-friend).
+__global__ __launch_bounds__(256) void k_track(const uint32_t* __restrict__ Fo, const uint32_t* __restrict__ Fn,
+                                               int64_t n, int K, int Ks, int32_t* __restrict__ vchg) {
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); x < n; x += nwaves) {
+    const uint32_t nw = lane < K ? Fn[x * Ks + lane] : 0u;
+    if (__ballot(lane < K && (nw & NEWBIT)) == 0) continue;  // whole wave
+    if (lane == 0) atomicOr(&vchg[x], 1);
+    const uint32_t o = lane < K ? (Fo[x * Ks + lane] & IDMASK) : 0u;
+    bool kept = false;
+    for (int l = 0; l < K; ++l) kept |= (shfl_u32(nw, l) & IDMASK) == o;
+    if (lane < K && !kept) atomicOr(&vchg[o], 2);
+  }
+}
+
 // A round restricted to the receivers [own0, own1) carries every other list
 // over unchanged, its edges marked new (as for a snapshot loaded from
 // outside; the round after a restricted one skips no pair anyway).
@@ -502,17 +520,34 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
                                              int32_t* __restrict__ counts, int32_t* __restrict__ lists,
                                              const int32_t* __restrict__ inst_of,
                                              const int32_t* __restrict__ iactive, int64_t own0,
-                                             int64_t own1) {
+                                             int64_t own1, const uint32_t* __restrict__ F, int Ks,
+                                             const uint32_t* __restrict__ col, const int32_t* __restrict__ vchg,
+                                             const int32_t* __restrict__ vev, int32_t* __restrict__ sl_n,
+                                             int64_t* __restrict__ stats) {
   __shared__ int s_wcnt[NCLASS][4];
   __shared__ int s_base[NCLASS];
   const int lane = lane_id();
+  int64_t carried = 0;  // evaluations of receivers whose neighbourhood did not change
   // uniform trip count so that every lane takes part in the ballots and barriers
   for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = x0 + threadIdx.x;
     int cls = -1;
     // (receivers of a stopped instance of a batched group, or outside the
     // share of receivers this round updates, are not binned)
-    if (x < n && x >= own0 && x < own1 && (!inst_of || iactive[inst_of[x]])) {
+    bool same = false;
+    if (vchg && x < n && x >= own0 && x < own1 && vchg[x] == 0) {
+      // x's list, its friends' and its co-friends' lists are those of the
+      // last round and no list dropped x, so its candidate set is the same,
+      // every candidate lost then and its list stays: no evaluation needed
+      same = true;
+      for (int j = 0; j < K && same; ++j) same = (vchg[F[x * Ks + j] & IDMASK] & 1) == 0;
+      for (int64_t q = rowptr[x]; q < rowptr[x + 1] && same; ++q) same = (vchg[col[q] & IDMASK] & 1) == 0;
+      if (same) {
+        carried += vev[x * VC_N + VC_EVALS];
+        sl_n[x] = 0;  // k_merge carries the list over
+      }
+    }
+    if (!same && x < n && x >= own0 && x < own1 && (!inst_of || iactive[inst_of[x]])) {
       const int64_t c = rowptr[x + 1] - rowptr[x];
       const int64_t need2 = 2 * table_need(c, K, n);
       if (need2 <= (int64_t)(CLASS_CAP_MIN << 4)) {  // exact bound fits a small table
@@ -554,6 +589,11 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
       lists[(int64_t)cls * n + off + (int)rank_in(mk[cls])] = (int32_t)x;
     }
     __syncthreads();
+  }
+  if (vchg) {  // one atomic per wave
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) carried += (int64_t)shfl_xor_u64((uint64_t)carried, o);
+    if (lane == 0 && carried) atomicAdd((unsigned long long*)&stats[STAT_EVALS], (unsigned long long)carried);
   }
 }
 
@@ -1263,6 +1303,7 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
   }
   const uint64_t um = __ballot(lane < K && !bad && (li & NEWBIT));
   const uint64_t bm = __ballot(bad);
+
   if (lane == 0) {
     my_upd += (int64_t)__popcll(um);
     my_err += (int64_t)__popcll(bm);
@@ -2036,10 +2077,13 @@ hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const Ctx& c) {
+hipError_t launch_bin(const Ctx& c, bool carry) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c.stream, c.class_count, (int64_t)NCLASS);
   hipLaunchKernelGGL(k_bin, dim3(grid_for(c.n, 256, 8192)), dim3(256), 0, c.stream, c.rowptr, c.n, c.K,
-                     c.class_count, c.class_list, c.inst_of, c.iactive, c.own0, c.own1);
+                     c.class_count, c.class_list, c.inst_of, c.iactive, c.own0, c.own1, c.F[c.cur], c.Ks, c.col,
+                     carry ? c.vchg : nullptr, c.vev, c.sl_n, c.dstats);
+  // this round's flags are gathered afresh (after the test above has read the last round's)
+  if (c.tracking) hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.vchg, c.n);
   return hipGetLastError();
 }
 
@@ -2192,6 +2236,9 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   a.sl_key = c.sl_key;
   a.own0 = c.own0;
   a.own1 = c.own1;
+  // a single descent that gathers neighbourhood flags keeps the per-point
+  // counters too (their evaluation counts carry over to unchanged receivers)
+  if (!a.vcnt && c.tracking) a.vcnt = c.vev;
   return a;
 }
 
@@ -2235,6 +2282,12 @@ hipError_t launch_join_recv(const Ctx& c, int64_t* stats) {
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out) {
   const int64_t cnt = c.n * c.K;
   hipLaunchKernelGGL(k_strip, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, F, cnt, c.K, c.Ks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_track(const Ctx& c) {
+  hipLaunchKernelGGL(k_track, dim3(grid_for(c.n, 4, 16 * c.num_cu)), dim3(256), 0, c.stream, c.F[c.cur],
+                     c.F[c.cur ^ 1], c.n, c.K, c.Ks, c.vchg);
   return hipGetLastError();
 }
 
