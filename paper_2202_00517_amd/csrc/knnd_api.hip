@@ -449,13 +449,14 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   KNND_HIP(hipEventRecord(c.ev0, c.stream));
   KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
   // receivers whose neighbourhood did not change keep their list and count.
-  // The flags are gathered once the last round changed at most 4% of the
-  // entries, and used once it changed at most 2% (before, nearly every
-  // neighbourhood changes); using them needs the last round's flags of every
-  // receiver and the pair skipping in force
+  // A changed list touches about 2K neighbourhoods, so few are unchanged
+  // until few lists change: the flags are gathered once the last round
+  // changed at most 0.2% of the entries and used once it changed at most
+  // 0.1%; using them needs the last round's flags of every receiver and the
+  // pair skipping in force
   const bool full = c.own0 == 0 && c.own1 == c.n;
   const int64_t nK = c.n * (int64_t)c.K;
-  const bool want = c.track_capable && full && c.last_updates >= 0 && c.last_updates * 25 <= nK;
+  const bool want = c.track_capable && full && c.last_updates >= 0 && c.last_updates * 500 <= nK;
   if (want && !c.vchg) {  // first use: 24 bytes per point
     if (dalloc(&c.vchg, (size_t)c.n) != hipSuccess || dalloc(&c.vev, (size_t)c.n * knnd::VC_N) != hipSuccess ||
         knnd::launch_zero_i32(c.vchg, c.n, c.stream) != hipSuccess) {
@@ -465,7 +466,7 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   }
   c.tracking = want && c.track_capable && c.vchg && c.vev;
   const bool carry = c.tracking && c.track_ok && !c.no_skip_next && !(c.flags & KNND_FLAG_NO_SKIP) &&
-                     c.last_updates * 50 <= nK;
+                     c.last_updates * 1000 <= nK;
   KNND_HIP(knnd::launch_bin(c, carry));
   if (!full) KNND_HIP(knnd::launch_keep_rows(c));
   KNND_HIP(hipEventRecord(c.evj0, c.stream));
