@@ -29,7 +29,8 @@ import numpy as np  # noqa: E402
 
 METRIC = "comparator evals/sec + time-to-graph (n=1e6,d=20,K=30), mixed vs plain"
 HBM_PEAK_GBS = 8000.0
-MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+MFMA_16BIT_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix peak
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_recv_c3.json")
@@ -138,6 +139,49 @@ def copy_calibration():
     log("copied 1 GiB")
 
 
+def eval_bytes(D, mixed):
+    """Algorithmic bytes of one comparator evaluation (steps a2+a3): the
+    gather of the candidate's row, D 16-bit values (mixed) or D FP64 logs
+    (plain), plus its 4-byte id."""
+    return D * (2 if mixed else 8) + 4
+
+
+def eval_flops(D, mixed):
+    """Algorithmic arithmetic of one evaluation's key: D multiply-adds of the
+    cross term on the matrix cores (mixed), or D subtractions and D
+    multiply-adds in FP64 (plain)."""
+    return 2 * D if mixed else 3 * D
+
+
+def kernel_rooflines(rounds, D, mixed):
+    """Per-kernel achieved fractions of the roofline that bounds each, from
+    the per-evaluation units above times the evaluations each round performs
+    (evals_alg minus the count carried over unchanged) and the kernels' HIP
+    event times summed over the timed rounds."""
+    ev = sum(s["evals_alg"] - s.get("evals_carried", 0) for s in rounds)
+    recv_s = sum(s["ms_recv"] for s in rounds) * 1e-3
+    hub_s = sum(s["ms_hub"] for s in rounds) * 1e-3
+    join_s = sum(s["ms_join"] for s in rounds) * 1e-3
+    nr = len(rounds)
+    byt = ev * eval_bytes(D, mixed)
+    fl = ev * eval_flops(D, mixed)
+
+    def hbm(name, secs):
+        a = byt / secs / 1e9
+        return {"kernel": name, "bound": "hbm", "unit": "GB/s", "per_eval": eval_bytes(D, mixed),
+                "achieved": round(a, 2), "peak": HBM_PEAK_GBS, "frac": round(a / HBM_PEAK_GBS, 5),
+                "avg_launch_ms": round(1e3 * secs / nr, 3), "work_per_launch": int(byt / nr)}
+
+    peak = MFMA_16BIT_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+    a = fl / hub_s / 1e12
+    hub = {"kernel": "k_hub_mfma (split 16-bit cross terms on MFMA)" if mixed else "k_hub_reg (FP64 keys)",
+           "bound": "mfma" if mixed else "fp64", "unit": "TFLOP/s", "per_eval": eval_flops(D, mixed),
+           "achieved": round(a, 3), "peak": peak, "frac": round(a / peak, 6),
+           "avg_launch_ms": round(1e3 * hub_s / nr, 3), "work_per_launch": int(fl / nr)}
+    return [hbm("receiver pass: k_recv (every table-size class) + k_merge", recv_s),
+            hbm("join: hub kernel + receiver pass", join_s), hub]
+
+
 def recv_bytes(n, K, D, mixed, rescues, psize=4):
     """Algorithmic HBM bytes of one receiver pass (every size class of
     k_recv, one round), as the kernel's algorithm moves them:
@@ -150,7 +194,9 @@ def recv_bytes(n, K, D, mixed, rescues, psize=4):
                     entries and one key slot (8 B FP64 key; 4 B FP32 cross
                     term in the mixed form)
       mixed form    S(x), x's row and logs per receiver, and the candidate's
-                    FP64 log row per rescue"""
+                    FP64 log row per rescue
+    This is the receiver design's own traffic model (reported as
+    design_bytes), not the per-evaluation unit of the roofline."""
     s = 4 if mixed else 8
     b = n * (K * 24 + 16) + n * K * (10 + s) + 2 * n * K * K * (4 + s)
     if mixed:
@@ -187,13 +233,22 @@ def cpu_model():
     return "unknown"
 
 
-def oracle_timing(names):
+def host_threads():
+    """Threads for the CPU oracle: the host's hardware concurrency, capped at
+    16 (the CPU share that goes with one GPU on a shared host)."""
+    return min(16, os.cpu_count() or 1)
+
+
+def oracle_descents(names):
     """The CPU oracle (unchanged) timed on whole descents of the named
-    workloads: per-round seconds and evaluations per second."""
+    workloads, from points in host memory to final lists: per-round seconds
+    and evaluations per second, with the host's threads and, for n <= 10000,
+    with one thread as well."""
     import oracle
     import synth
-    threads = min(16, os.cpu_count() or 1)  # the host share of one GPU
-    out = {"kind": "oracle", "cpu": cpu_model(), "host_threads": threads, "runs": []}
+    threads = host_threads()
+    out = {"kind": "oracle", "cpu": cpu_model(), "hardware_concurrency": os.cpu_count(),
+           "threads": threads, "runs": []}
     for name in names:
         cf = synth.WORKLOADS[name]
         P = synth.dirichlet(cf["data_seed"], cf["n"], cf["d"], cf["dtype"])
@@ -204,10 +259,74 @@ def oracle_timing(names):
             secs = time.perf_counter() - t0
             out["runs"].append({"workload": name, "n": cf["n"], "d": cf["d"], "K": cf["K"], "threads": t,
                                 "rounds": r.rounds, "seconds": round(secs, 3),
-                                "round_seconds": [round(float(s), 3) for s in r.seconds],
+                                "round_seconds": [round(float(s), 3) for s in r.seconds[1:]],
                                 "evals_alg": int(r.evals.sum()),
                                 "evals_per_s": float(r.evals.sum()) / secs})
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def oracle_timing(names):
+    print(json.dumps(oracle_descents(names)), flush=True)
+
+
+# The other workloads, timed beside the headline one: (name, precision).
+CONFIG_LEGS = [("n2000_d5_k10", "plain"), ("n100000_d10_k20", "plain"),
+               ("n200000_d50_k20", "mixed_fp16"), ("n200000_d50_k20", "plain")]
+RECALL_QUERIES = 2000
+
+
+def config_leg(knnd, torch, name, precision, reps=5):
+    """One workload on the device: time-to-graph (device-resident points,
+    median of `reps` after one warm-up), end-to-end time (host points in, host
+    lists out; median of 3), evaluations per second and the rescue rate.  For
+    the 50-coordinate workload also recall@K against exhaustive search on
+    RECALL_QUERIES sampled points."""
+    import synth
+    cf = synth.WORKLOADS[name]
+    n, d, K, seed = cf["n"], cf["d"], cf["K"], cf["seed"]
+    P = synth.dirichlet(cf["data_seed"], n, d, cf["dtype"])
+    Pd = torch.from_numpy(P).cuda()
+    prec = {"plain": knnd.KNND_PREC_FP64, "mixed_bf16": knnd.KNND_PREC_MIXED_BF16,
+            "mixed_fp16": knnd.KNND_PREC_MIXED_FP16}[precision]
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        return knnd.knnd_build_ex(Pd, d, K, seed, knnd.default_params(precision=prec), stream=stream)
+
+    out = run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        out = run()
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t))
+    e2e = []
+    for _ in range(3):
+        t = time.perf_counter()
+        knnd.knnd_build_ex(P, d, K, seed, knnd.default_params(precision=prec), with_kl=False)
+        e2e.append(1e3 * (time.perf_counter() - t))
+    st = out["stats"][1:]
+    ev = sum(s["evals_alg"] for s in st)
+    evaluated = sum(s["evals_alg"] - s["evals_carried"] for s in st)
+    resc = sum(s["rescues"] for s in st)
+    ms = sorted(times)[reps // 2]
+    rec = {"workload": name, "n": n, "d": d, "K": K, "points": np.dtype(cf["dtype"]).name,
+           "precision": precision, "rounds": out["rounds"], "time_to_graph_ms": round(ms, 3),
+           "end_to_end_ms": round(sorted(e2e)[1], 3), "evals_alg": ev, "evals_per_s": ev / (ms * 1e-3),
+           "per_round_ms": [round(s["ms"], 3) for s in st]}
+    if precision != "plain":
+        rec["rescues"] = resc
+        rec["rescue_rate"] = resc / evaluated if evaluated else 0.0
+    if name == "n200000_d50_k20":
+        qs = synth.subsample(seed, n, RECALL_QUERIES)
+        ei, _ = knnd.knnd_exact_knn(Pd, d, K, torch.from_numpy(qs.astype(np.int32)).cuda(), with_kl=False)
+        got = out["idx"][torch.from_numpy(qs).cuda()].cpu().numpy()
+        ex = ei.cpu().numpy()
+        hits = sum(len(set(a.tolist()) & set(b.tolist())) for a, b in zip(got, ex))
+        rec["recall"] = {"at": K, "queries": RECALL_QUERIES, "hits": hits,
+                         "value": hits / (RECALL_QUERIES * K)}
+    return rec
 
 
 def main():
@@ -223,6 +342,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-instances comparison")
     ap.add_argument("--cpu-receivers", type=int, default=400_000)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (device legs and oracle descents)")
     ap.add_argument("--no-share", action="store_true",
                     help="skip the one-GPU-share round (1/8 of the receivers)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -314,30 +435,22 @@ def main():
     e2e_ms = sorted(e2e)[1]
 
     # roofline of the dominant kernel: the receiver pass (k_recv, one launch
-    # per table-size class, then k_merge; steps a2-a5 on the receiver side), timed with HIP
-    # events on the library's stream around its launches in every timed round
+    # per table-size class, then k_merge; steps a2-a5 on the receiver side),
+    # timed with HIP events on the library's stream around its launches in
+    # every timed round; one "launch" is one round's pass.  Algorithmic bytes:
+    # eval_bytes per evaluation.  The receiver design's own traffic model and
+    # the rocprofv3-measured bytes are reported beside it.
     rounds = [s for o, _ in results for s in o["stats"][1:]]
-    recv_ms = [s["ms_recv"] for s in rounds]
-    hub_ms = [s["ms_hub"] for s in rounds]
-    bytes_alg = sum(recv_bytes(n, K, D, mixed, s["rescues"]) for s in rounds)
-    achieved = bytes_alg / (sum(recv_ms) * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(args.precision),
-                "kernel": "receiver pass: k_recv (every table-size class) + k_merge, one round",
-                "avg_launch_ms": round(sum(recv_ms) / len(recv_ms), 3),
-                "bytes_per_launch": int(bytes_alg / len(recv_ms))}
-    hub = {"kernel": "k_hub_mfma (split 16-bit MFMA cross terms)" if mixed
-           else "k_hub_reg (FP64 keys)", "avg_launch_ms": round(sum(hub_ms) / len(hub_ms), 3),
-           "evals_per_launch": int(sum(s["evals_performed"] - s["rescues"] for s in rounds)
-                                   / len(rounds))}
-    if mixed:
-        # matrix-core use: one multiply-add per coordinate of each stored cross
-        # term, against the dense BF16 peak (the split form issues three MFMAs
-        # per term over coordinates padded to 32, so issued work is about 4.6x)
-        tflops = hub["evals_per_launch"] * 2 * D / (hub["avg_launch_ms"] * 1e-3) / 1e12
-        hub["mfma"] = {"useful_tflops": round(tflops, 3), "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
-                       "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 6)}
+    kernels = kernel_rooflines(rounds, D, mixed)
+    design = sum(recv_bytes(n, K, D, mixed, s["rescues"]) for s in rounds) / len(rounds)
+    traffic = measured_traffic(args.precision)
+    rk = kernels[0]
+    roofline = {"bound": "hbm", "achieved": rk["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": rk["frac"], "traffic": traffic, "kernel": rk["kernel"] + ", one round",
+                "avg_launch_ms": rk["avg_launch_ms"], "bytes_per_launch": rk["work_per_launch"],
+                "bytes_per_eval": eval_bytes(D, mixed), "design_bytes": int(design),
+                "traffic_over_design": round(traffic / design, 3) if traffic else None,
+                "traffic_over_algorithmic": round(traffic / rk["work_per_launch"], 3) if traffic else None}
     steps_ms = sorted(1e3 * t for _, t in results)
 
     line = {
@@ -364,7 +477,7 @@ def main():
         "per_round_ms": [round(s["ms"], 3) for s in last["stats"]],
         "rescues": sum(s["rescues"] for s in last["stats"]),
         "roofline": roofline,
-        "hub": hub,
+        "kernels": kernels,
     }
     if plain is not None:
         line["plain"] = plain
@@ -374,10 +487,20 @@ def main():
     if not args.no_batched:
         log("batched instances: one batched call vs one by one")
         line["batched"] = batched_leg(knnd, synth, torch, args.steps)
+    if not args.no_configs:
+        line["per_config"] = []
+        for name, prec_name in CONFIG_LEGS:
+            log(f"workload {name}, {prec_name}")
+            line["per_config"].append(config_leg(knnd, torch, name, prec_name))
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
+        threads = host_threads()
         log(f"cpu baseline: oracle round 1 on {args.cpu_receivers} receivers, {threads} threads")
         line["cpu_baseline"] = cpu_baseline(P, d, K, seed, args.cpu_receivers, threads)
+        line["cpu_baseline"]["cpu"] = cpu_model()
+        line["cpu_baseline"]["hardware_concurrency"] = os.cpu_count()
+        if not args.no_configs:
+            line["oracle_descents"] = oracle_descents(sorted({c for c, _ in CONFIG_LEGS},
+                                                             key=lambda c: synth.WORKLOADS[c]["n"]))
     print(json.dumps(line), flush=True)
 
 

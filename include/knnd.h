@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define KNND_ABI_VERSION 5
+#define KNND_ABI_VERSION 6
 
 typedef enum {
     KNND_OK = 0,
@@ -98,6 +98,11 @@ typedef enum {
                                    device-wide atomic per edge (the form used
                                    above 2^25 points) instead of the bucketed
                                    counting sort (same result) */
+#define KNND_FLAG_NO_CARRY 0x8  /* evaluate every receiver in late rounds too,
+                                   instead of carrying over the list and the
+                                   evaluation count of a receiver whose
+                                   neighbourhood did not change (same result,
+                                   more work; see `carried` below) */
 
 /*
  * Comparators (Section 2.1: any family of per-point total orders; Section 1.3
@@ -170,6 +175,16 @@ typedef struct {
                                    terms per snapshot edge; 0 in the pull form) */
     double ms_recv;             /* part of ms_join: the receiver kernels (dedup,
                                    rescue, merge, every size class) */
+    int64_t carried;            /* receivers whose list and evaluation count were
+                                   carried over from the last round: its list,
+                                   its friends' and co-friends' lists were all
+                                   unchanged and no list dropped it, so its
+                                   candidate set is the same (Section 3.1) and
+                                   every candidate lost again.  Single descents
+                                   in the hub form, once a round changed at most
+                                   0.1% of the entries; 0 otherwise */
+    int64_t evals_carried;      /* the part of evals_alg those receivers add
+                                   (counted, not evaluated again) */
 } knnd_round_stats;
 
 /* Fill *p with the defaults (FP64, F32 points, M = min(n,10000), 100 rounds,

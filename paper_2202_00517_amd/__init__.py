@@ -27,6 +27,7 @@ KNND_PREC_FP64, KNND_PREC_MIXED_BF16, KNND_PREC_MIXED_FP16 = 0, 1, 2
 KNND_FLAG_NO_SKIP = 0x1
 KNND_FLAG_PULL = 0x2
 KNND_FLAG_ATOMIC_CSR = 0x4
+KNND_FLAG_NO_CARRY = 0x8
 KNND_STOP_FCR, KNND_STOP_FIXED_POINT, KNND_STOP_DELTA = 0, 1, 2
 KNND_CMP_KL, KNND_CMP_KL_REVERSE, KNND_CMP_HELLINGER, KNND_CMP_L2 = 0, 1, 2, 3
 
@@ -38,7 +39,7 @@ EXPORTED = [
 ]
 
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class knnd_params(ctypes.Structure):
@@ -53,7 +54,8 @@ class knnd_round_stats(ctypes.Structure):
                 ("evals_alg", ctypes.c_int64), ("evals_performed", ctypes.c_int64),
                 ("rescues", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("ms_join", ctypes.c_double), ("ms_hub", ctypes.c_double),
-                ("ms_recv", ctypes.c_double)]
+                ("ms_recv", ctypes.c_double), ("carried", ctypes.c_int64),
+                ("evals_carried", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

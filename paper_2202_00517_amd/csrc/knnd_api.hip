@@ -421,6 +421,8 @@ int read_stats(Ctx& c, knnd_round_stats* st, bool joined) {
     st->evals_alg = c.hstats[knnd::STAT_EVALS];
     st->evals_performed = c.hstats[knnd::STAT_PERF];
     st->rescues = c.hstats[knnd::STAT_RESCUES];
+    st->carried = c.hstats[knnd::STAT_CARRIED];
+    st->evals_carried = c.hstats[knnd::STAT_EVCARRY];
     st->ms = ms;
     st->ms_join = msj;
     st->ms_hub = msh;
@@ -465,8 +467,8 @@ int run_round(Ctx& c, knnd_round_stats* st) {
     }
   }
   c.tracking = want && c.track_capable && c.vchg && c.vev;
-  const bool carry = c.tracking && c.track_ok && !c.no_skip_next && !(c.flags & KNND_FLAG_NO_SKIP) &&
-                     c.last_updates * 1000 <= nK;
+  const bool carry = c.tracking && c.track_ok && !c.no_skip_next &&
+                     !(c.flags & (KNND_FLAG_NO_SKIP | KNND_FLAG_NO_CARRY)) && c.last_updates * 1000 <= nK;
   KNND_HIP(knnd::launch_bin(c, carry));
   if (!full) KNND_HIP(knnd::launch_keep_rows(c));
   KNND_HIP(hipEventRecord(c.evj0, c.stream));
@@ -752,6 +754,8 @@ int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t 
         rs.evals_alg = s[knnd::STAT_EVALS];
         rs.evals_performed = s[knnd::STAT_PERF];
         rs.rescues = s[knnd::STAT_RESCUES];
+        rs.carried = 0;  // (groups evaluate every running receiver)
+        rs.evals_carried = 0;
         rs.ms = ms;
         rs.ms_join = msj;
         rs.ms_hub = msh;

@@ -32,7 +32,12 @@ inline int cmp_fold_kind(int cmp) { return cmp == 1 ? CK_REV : (cmp >= 2 ? CK_SQ
 inline int cmp_table_kind(int cmp) { return cmp == 2 ? TK_SQRT : (cmp == 3 ? TK_ID : TK_LOG); }
 
 // Per-round device counters
-enum { STAT_UPDATES = 0, STAT_HITS = 1, STAT_EVALS = 2, STAT_PERF = 3, STAT_RESCUES = 4, STAT_ERR = 5, STAT_N = 8 };
+// (STAT_CARRIED: receivers whose list and count were carried over unchanged;
+// STAT_EVCARRY: the evaluations they add to STAT_EVALS)
+enum {
+  STAT_UPDATES = 0, STAT_HITS = 1, STAT_EVALS = 2, STAT_PERF = 3, STAT_RESCUES = 4, STAT_ERR = 5,
+  STAT_CARRIED = 6, STAT_EVCARRY = 7, STAT_N = 8
+};
 // Per-point counters of one round in a batched group (summed per instance):
 // evaluations and updates of receiver x, keys computed by hub x, keys
 // computed by receiver x (pull form and rescues), rescues of receiver x

@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
   __shared__ int s_wcnt[NCLASS][4];
   __shared__ int s_base[NCLASS];
   const int lane = lane_id();
-  int64_t carried = 0;  // evaluations of receivers whose neighbourhood did not change
+  int64_t carried = 0, ncarried = 0;  // evaluations and number of receivers whose neighbourhood did not change
   // uniform trip count so that every lane takes part in the ballots and barriers
   for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = x0 + threadIdx.x;
@@ -544,6 +544,7 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
       for (int64_t q = rowptr[x]; q < rowptr[x + 1] && same; ++q) same = (vchg[col[q] & IDMASK] & 1) == 0;
       if (same) {
         carried += vev[x * VC_N + VC_EVALS];
+        ++ncarried;
         sl_n[x] = 0;  // k_merge carries the list over
       }
     }
@@ -592,8 +593,15 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
   }
   if (vchg) {  // one atomic per wave
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) carried += (int64_t)shfl_xor_u64((uint64_t)carried, o);
-    if (lane == 0 && carried) atomicAdd((unsigned long long*)&stats[STAT_EVALS], (unsigned long long)carried);
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      carried += (int64_t)shfl_xor_u64((uint64_t)carried, o);
+      ncarried += (int64_t)shfl_xor_u64((uint64_t)ncarried, o);
+    }
+    if (lane == 0 && carried) {
+      atomicAdd((unsigned long long*)&stats[STAT_EVALS], (unsigned long long)carried);
+      atomicAdd((unsigned long long*)&stats[STAT_EVCARRY], (unsigned long long)carried);
+    }
+    if (lane == 0 && ncarried) atomicAdd((unsigned long long*)&stats[STAT_CARRIED], (unsigned long long)ncarried);
   }
 }
 

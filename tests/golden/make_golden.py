@@ -25,12 +25,32 @@ def digest(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
+# Workloads whose accuracy is recorded: recall@K of the final graph against
+# exhaustive search (the share of the true K nearest found, Section 4) on
+# RECALL_QUERIES points drawn without replacement by the tag-7 hash from the
+# workload's seed.
+RECALL_WORKLOADS = {"n200000_d50_k20"}
+RECALL_QUERIES = 2000
+
+
+def recall_hits(P, idx, K, seed):
+    P64 = oracle.widen(P)
+    L = oracle.log_table(P64)
+    qs = synth.subsample(seed, P.shape[0], RECALL_QUERIES)
+    bf, _ = oracle.bruteforce(P64, L, K, qs)
+    return int(sum(len(set(idx[q].tolist()) & set(b.tolist())) for q, b in zip(qs, bf)))
+
+
 def run_single(name):
     c = synth.WORKLOADS[name]
     P = synth.dirichlet(c["data_seed"], c["n"], c["d"], c["dtype"])
     t = time.time()
     res = oracle.build_graph(P, c["d"], c["K"], c["seed"])
     secs = time.time() - t
+    extra = {}
+    if name in RECALL_WORKLOADS:
+        extra = {"recall_queries": RECALL_QUERIES,
+                 "recall_hits": recall_hits(P, res.idx, c["K"], c["seed"])}
     return {
         "workload": f"n={c['n']} d={c['d']} K={c['K']} "
                     f"{np.dtype(c['dtype']).name} points, data seed {c['data_seed']}, seed {c['seed']}",
@@ -42,6 +62,7 @@ def run_single(name):
         "idx_sha256": digest(res.idx),
         "kl_sha256": digest(res.keys),
         "oracle_seconds": secs,
+        **extra,
     }
 
 

@@ -41,7 +41,7 @@ def test_abi_version_and_status_strings():
 def test_params_struct_layout_matches_header():
     assert ctypes.sizeof(knnd.knnd_params) == 40
     assert knnd.knnd_params.delta.offset == 32
-    assert ctypes.sizeof(knnd.knnd_round_stats) == 72
+    assert ctypes.sizeof(knnd.knnd_round_stats) == 88
     p = knnd.default_params()
     assert (p.precision, p.dtype, p.fcr_samples, p.max_rounds, p.flags) == (0, 0, 0, 100, 0)
     assert (p.stop_rule, p.comparator, p.delta) == (knnd.KNND_STOP_FCR, knnd.KNND_CMP_KL, 0.0)

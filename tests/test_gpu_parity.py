@@ -238,6 +238,33 @@ def test_stop_rules_full(n, d, K, ds, seed, rule, delta, form):
         assert g["stats"][g["rounds"]]["updates"] == 0
 
 
+# Receivers whose neighbourhood did not change keep their list and evaluation
+# count (the candidate set is the same, Section 3.1): the fixed-point descent
+# reaches rounds with few changes, where the carry-over fires; its lists, key
+# bits and every per-round count equal the oracle's and those of the same
+# descent with the carry-over switched off.
+@pytest.mark.parametrize("form", [FORMS[0], FORMS[2]], ids=["hub", "bf16"])
+@pytest.mark.parametrize("n,d,K,ds,seed", [(20000, 10, 20, 6, 8), (5000, 4, 8, 9, 3)])
+def test_carry_over_fires_and_matches(n, d, K, ds, seed, form):
+    P = synth.dirichlet(ds, n, d, np.float32)
+    g, o = full_compare(P, d, K, seed, flags=form[0], precision=form[1],
+                        stop_rule=knnd.KNND_STOP_FIXED_POINT)
+    carried = [s["carried"] for s in g["stats"]]
+    assert max(carried) > 0, carried
+    for s in g["stats"]:
+        assert 0 <= s["evals_carried"] <= s["evals_alg"]
+        assert (s["carried"] == 0) == (s["evals_carried"] == 0)
+    h = knnd.knnd_build_ex(P, d, K, seed, knnd.default_params(
+        flags=form[0] | knnd.KNND_FLAG_NO_CARRY, precision=form[1],
+        stop_rule=knnd.KNND_STOP_FIXED_POINT))
+    assert h["rounds"] == g["rounds"]
+    assert all(s["carried"] == 0 and s["evals_carried"] == 0 for s in h["stats"])
+    for a, b in zip(g["stats"], h["stats"]):
+        assert (a["updates"], a["fcr_hits"], a["evals_alg"]) == (b["updates"], b["fcr_hits"], b["evals_alg"])
+    assert np.array_equal(g["idx"], h["idx"])
+    assert np.array_equal(bits(g["kl"]), bits(h["kl"]))
+
+
 def test_stop_rule_round_cap_warns():
     P = synth.dirichlet(9, 5000, 4, np.float32)
     g, o = full_compare(P, 4, 8, 3, max_rounds=4, stop_rule=knnd.KNND_STOP_FIXED_POINT)
@@ -415,11 +442,13 @@ def test_n200000_d50_k20_full_size_and_recall():
     c = synth.WORKLOADS["n200000_d50_k20"]
     P64 = oracle.widen(P)
     L = oracle.log_table(P64)
-    qs = synth.subsample(c["seed"], c["n"], 2000)
+    gold = _golden("n200000_d50_k20")
+    qs = synth.subsample(c["seed"], c["n"], gold["recall_queries"])
     bf, bk = oracle.bruteforce(P64, L, c["K"], qs)
-    rec = np.mean([len(set(g["idx"][q].tolist()) & set(b.tolist())) / c["K"] for q, b in zip(qs, bf)])
-    say(f"n=200000 d=50 K=20 recall@{c['K']} on 2000 queries: {rec:.4f}")
-    assert 0.0 < rec <= 1.0
+    hits = sum(len(set(g["idx"][q].tolist()) & set(b.tolist())) for q, b in zip(qs, bf))
+    say(f"n=200000 d=50 K=20 recall@{c['K']} on {qs.size} queries: {hits / (qs.size * c['K']):.4f}")
+    # the oracle's graph has the same recall, written by make_golden.py
+    assert hits == gold["recall_hits"]
     # the library's exhaustive search, bounded by the descent's K-th keys
     ei, ek = knnd.knnd_exact_knn(P, c["d"], c["K"], qs.astype(np.int32), tau=g["kl"][qs, -1])
     assert np.array_equal(ei, bf)
