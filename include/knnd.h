@@ -242,6 +242,30 @@ int knnd_build_ex(const void* points, int64_t n, int32_t d, int32_t K, uint64_t 
                   int32_t* out_rounds);
 
 /*
+ * For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc / hipFree): the descent of knnd_build_ex
+ * with device pointers (on_device = 1), with every device buffer carved from
+ * a fixed scratch array of KNND_NOALLOC_MAX_BYTES that the library holds on
+ * each device it runs on until the process ends.  The call allocates
+ * nothing: no hipMalloc, hipFree, pinned host memory, events or memory-cache
+ * blocks.  Same arguments, results and errors as knnd_build_ex, except:
+ *   points, out_idx, out_kl   device memory of the current device (caller-owned)
+ *   stats                     host array, as in knnd_build_ex; the ms fields are 0
+ *   returns KNND_ERR_NOMEM, before any device work, when the buffers of the
+ *   descent do not fit the scratch array.  The richest form that fits runs
+ *   (mixed, else hub, else pull form; all give the same results): at K = 16
+ *   and d = 10 about 6*10^4 points fit the mixed form, 3.5*10^4 the hub
+ *   form and 2*10^5 the pull form.
+ * Calls on one device share its scratch array, which keeps the last call's
+ * contents: calls that overlap on one device race (run them in order on one
+ * stream or serialise them).  The stream is synchronised once per round.
+ */
+#define KNND_NOALLOC_MAX_BYTES 268435456ull  /* 256 MiB per device */
+int knnd_build_noalloc(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed,
+                       const knnd_params* p, void* stream, int32_t* out_idx, double* out_kl,
+                       knnd_round_stats* stats, int32_t* out_rounds);
+
+/*
  * Batched form: B independent descents in one call (each instance exactly
  * what knnd_build_ex would return for it with the same params).
  *   inst        host array [B].  Per instance, inputs: points ([n][d+1] in

@@ -36,7 +36,9 @@ EXPORTED = [
     "knnd_build_ex", "knnd_ctx_create", "knnd_ctx_init_graph", "knnd_ctx_set_graph",
     "knnd_ctx_round", "knnd_ctx_round_share", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
     "knnd_ctx_destroy", "knnd_build_batched", "knnd_exact_knn", "knnd_release_cache",
+    "knnd_build_noalloc",
 ]
+KNND_NOALLOC_MAX_BYTES = 256 << 20
 
 
 ABI_VERSION = 6
@@ -110,6 +112,8 @@ def lib():
         "knnd_build_batched": (ctypes.c_int, [P(knnd_instance), i32, P(knnd_params), i32, vp]),
         "knnd_exact_knn": (ctypes.c_int, [vp, i64, i32, i32, i32, i32, vp, i64, vp, i32, vp, vp, vp]),
         "knnd_release_cache": (ctypes.c_int, []),
+        "knnd_build_noalloc": (ctypes.c_int, [vp, i64, i32, i32, u64, P(knnd_params), vp, vp, vp,
+                                              P(knnd_round_stats), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -222,6 +226,37 @@ def knnd_build_ex(points, d, K, seed, params=None, stream=None, with_kl=True):
                              ctypes.byref(rounds))
     if st < 0:
         raise KnndError(st, "knnd_build_ex")
+    r = rounds.value
+    return {"status": st, "idx": idx, "kl": kl, "rounds": r,
+            "stats": [stats[i].as_dict() for i in range(r + 1)]}
+
+
+def knnd_build_noalloc(points, d, K, seed, params=None, stream=None, idx=None, kl=None):
+    """The descent with every device buffer in the library's fixed scratch
+    array (knnd_build_noalloc: nothing is allocated).  points: torch tensor on
+    the GPU; idx / kl: optional caller-allocated device outputs ([n][K] int32
+    and FP64; kl=False for none), allocated here when not given.  Returns a
+    dict like knnd_build_ex's."""
+    points = _check_points(points, d)
+    if not _is_device(points):
+        raise ValueError("knnd_build_noalloc takes device tensors")
+    n = points.shape[0]
+    p = params if params is not None else default_params()
+    p.dtype = _dtype_code(points)
+    R = (p.max_rounds if p.max_rounds > 0 else 100) + 1
+    stats = (knnd_round_stats * R)()
+    if idx is None:
+        idx = _empty(points, (n, K), np.int32)
+    if kl is None:
+        kl = _empty(points, (n, K), np.float64)
+    elif kl is False:
+        kl = None
+    rounds = ctypes.c_int32(0)
+    st = lib().knnd_build_noalloc(_ptr(points), n, d, K, seed, ctypes.byref(p),
+                                  _stream_of(points, stream), _ptr(idx), _ptr(kl), stats,
+                                  ctypes.byref(rounds))
+    if st < 0:
+        raise KnndError(st, "knnd_build_noalloc")
     r = rounds.value
     return {"status": st, "idx": idx, "kl": kl, "rounds": r,
             "stats": [stats[i].as_dict() for i in range(r + 1)]}

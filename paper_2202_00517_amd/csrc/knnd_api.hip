@@ -143,10 +143,42 @@ int map_err(hipError_t e) { return e == hipErrorOutOfMemory ? KNND_ERR_NOMEM : K
     if (e_ != hipSuccess) return map_err(e_);         \
   } while (0)
 
-template <class T>
-hipError_t dalloc(T** p, size_t count) {
-  return knnd::pmalloc(p, count * sizeof(T) + 16);
+// Device buffers of a context: from the memory cache, or (fixed-scratch
+// mode) carved from the context's arena at 256-byte alignment.
+hipError_t ctx_alloc(Ctx& c, void** p, size_t bytes) {
+  if (!c.arena) return knnd::pool_malloc(p, bytes);
+  *p = nullptr;
+  const size_t off = (c.arena_used + 255) & ~(size_t)255;
+  if (off > c.arena_size || bytes > c.arena_size - off) return hipErrorOutOfMemory;
+  *p = c.arena + off;
+  c.arena_used = off + bytes;
+  return hipSuccess;
 }
+
+template <class T>
+hipError_t dalloc(Ctx& c, T** p, size_t count) {
+  return ctx_alloc(c, reinterpret_cast<void**>(p), count * sizeof(T) + 16);
+}
+
+template <class T>
+hipError_t balloc(Ctx& c, T** p, size_t bytes) {
+  return ctx_alloc(c, reinterpret_cast<void**>(p), bytes);
+}
+
+// Give back optional buffers whose allocation did not complete (arena: roll
+// the bump pointer back to `mark`); the pointers are cleared.
+template <class... T>
+void drop_optional(Ctx& c, size_t mark, T**... ps) {
+  (void)hipGetLastError();
+  if (c.arena)
+    c.arena_used = mark;
+  else
+    (knnd::pool_free(*ps), ...);
+  ((*ps = nullptr), ...);
+}
+
+// HIP events of the per-round timings (none in fixed-scratch mode)
+hipError_t rec(hipEvent_t ev, hipStream_t s) { return ev ? hipEventRecord(ev, s) : hipSuccess; }
 
 void free_ctx(Ctx& c) {
   void* bufs[] = {c.P,      c.L,      c.F[0],   c.F[1],      c.keys[0],     c.keys[1],  c.deg,
@@ -158,8 +190,9 @@ void free_ctx(Ctx& c) {
                   c.vchg, c.vev};
   // the blocks go back to the cache: the context's work must have finished
   (void)hipStreamSynchronize(c.stream);
-  for (void* b : bufs) knnd::pool_free(b);
-  if (c.hstats) (void)hipHostFree(c.hstats);
+  if (!c.arena)
+    for (void* b : bufs) knnd::pool_free(b);
+  if (c.hstats && c.hstats != c.hstats_local) (void)hipHostFree(c.hstats);
   if (c.histats) (void)hipHostFree(c.histats);
   if (c.ev0) (void)hipEventDestroy(c.ev0);
   if (c.ev1) (void)hipEventDestroy(c.ev1);
@@ -236,82 +269,91 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   // holds, between 32 and 128 (more than 32 cut its tail of few, very large
   // receivers; more than 128 gained nothing at 10^6 points)
   c.gblocks = (int)std::min<int64_t>(128, std::max<int64_t>(32, ((int64_t)4 << 30) / (10 * c.gstride)));
+  // (fixed scratch: fewer blocks for the two global-memory classes, whose
+  // per-block regions would otherwise dominate a small arena)
+  if (c.arena) c.gblocks = 16;
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = knnd::pmalloc(&c.P, ((size_t)n * c.D + knnd::HUB_MAXD) * esz);
-  if (e == hipSuccess) e = dalloc(&c.L, (size_t)n * c.Dp + knnd::HUB_MAXD);
+  if (e == hipSuccess) e = balloc(c, &c.P, ((size_t)n * c.D + knnd::HUB_MAXD) * esz);
+  if (e == hipSuccess) e = dalloc(c, &c.L, (size_t)n * c.Dp + knnd::HUB_MAXD);
   for (int b = 0; b < 2; ++b) {
-    if (e == hipSuccess) e = dalloc(&c.F[b], (size_t)n * c.Ks);
-    if (e == hipSuccess) e = dalloc(&c.keys[b], nK);
+    if (e == hipSuccess) e = dalloc(c, &c.F[b], (size_t)n * c.Ks);
+    if (e == hipSuccess) e = dalloc(c, &c.keys[b], nK);
   }
-  if (e == hipSuccess) e = dalloc(&c.deg, (size_t)n);
-  if (e == hipSuccess) e = dalloc(&c.fill, (size_t)n);
-  if (e == hipSuccess) e = dalloc(&c.rowptr, (size_t)n + 1);
-  if (e == hipSuccess) e = dalloc(&c.col, nK);
-  if (e == hipSuccess) e = dalloc(&c.colslot, nK);
-  if (e == hipSuccess) e = dalloc(&c.tilesum, (size_t)ntiles + 1);
+  if (e == hipSuccess) e = dalloc(c, &c.deg, (size_t)n);
+  if (e == hipSuccess) e = dalloc(c, &c.fill, (size_t)n);
+  if (e == hipSuccess) e = dalloc(c, &c.rowptr, (size_t)n + 1);
+  if (e == hipSuccess) e = dalloc(c, &c.col, nK);
+  if (e == hipSuccess) e = dalloc(c, &c.colslot, nK);
+  if (e == hipSuccess) e = dalloc(c, &c.tilesum, (size_t)ntiles + 1);
   // bucketed CSR: targets per bucket the smallest power of two >= 256 giving
   // at most CSR_MAXB buckets
   c.csr_shift = 8;
   while (c.csr_shift < 13 && ((n + ((int64_t)1 << c.csr_shift) - 1) >> c.csr_shift) > knnd::CSR_MAXB) ++c.csr_shift;
   if (((n + ((int64_t)1 << c.csr_shift) - 1) >> c.csr_shift) <= knnd::CSR_MAXB && nK < ((size_t)1 << 31) &&
       !(prm.flags & KNND_FLAG_ATOMIC_CSR)) {
-    if (e == hipSuccess) e = dalloc(&c.csr_T, nK);
-    if (e == hipSuccess) e = dalloc(&c.csr_bcount, (size_t)knnd::CSR_MAXB);
-    if (e == hipSuccess) e = dalloc(&c.csr_bfill, (size_t)knnd::CSR_MAXB);
-    if (e == hipSuccess) e = dalloc(&c.csr_bbase, (size_t)knnd::CSR_MAXB + 1);
+    if (e == hipSuccess) e = dalloc(c, &c.csr_T, nK);
+    if (e == hipSuccess) e = dalloc(c, &c.csr_bcount, (size_t)knnd::CSR_MAXB);
+    if (e == hipSuccess) e = dalloc(c, &c.csr_bfill, (size_t)knnd::CSR_MAXB);
+    if (e == hipSuccess) e = dalloc(c, &c.csr_bbase, (size_t)knnd::CSR_MAXB + 1);
   }
-  if (e == hipSuccess) e = dalloc(&c.class_count, (size_t)knnd::NCLASS);
-  if (e == hipSuccess) e = dalloc(&c.class_list, (size_t)knnd::NCLASS * n);
-  if (e == hipSuccess) e = dalloc(&c.gtab, (size_t)c.gblocks * c.gstride);
-  if (e == hipSuccess) e = dalloc(&c.gcand, (size_t)c.gblocks * (c.gstride / 2));
-  if (e == hipSuccess) e = dalloc(&c.gckey, (size_t)c.gblocks * (c.gstride / 2));
-  c.bblocks = 4 * c.num_cu;
-  if (e == hipSuccess) e = dalloc(&c.bcand, (size_t)c.bblocks * knnd::BIG_CAND);
-  if (e == hipSuccess) e = dalloc(&c.bckey, (size_t)c.bblocks * knnd::BIG_CAND);
-  if (e == hipSuccess) e = dalloc(&c.dstats, (size_t)knnd::STAT_N);
-  if (e == hipSuccess) e = dalloc(&c.dflag, (size_t)4);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c.hstats), knnd::STAT_N * sizeof(int64_t));
-  if (e == hipSuccess) e = hipEventCreate(&c.ev0);
-  if (e == hipSuccess) e = hipEventCreate(&c.ev1);
-  if (e == hipSuccess) e = hipEventCreate(&c.evj0);
-  if (e == hipSuccess) e = hipEventCreate(&c.evj1);
-  if (e == hipSuccess) e = hipEventCreate(&c.evh);
+  if (e == hipSuccess) e = dalloc(c, &c.class_count, (size_t)knnd::NCLASS);
+  if (e == hipSuccess) e = dalloc(c, &c.class_list, (size_t)knnd::NCLASS * n);
+  if (e == hipSuccess) e = dalloc(c, &c.gtab, (size_t)c.gblocks * c.gstride);
+  if (e == hipSuccess) e = dalloc(c, &c.gcand, (size_t)c.gblocks * (c.gstride / 2));
+  if (e == hipSuccess) e = dalloc(c, &c.gckey, (size_t)c.gblocks * (c.gstride / 2));
+  // (fixed scratch: one candidate region per CU for the big LDS classes)
+  c.bblocks = c.arena ? std::min(c.num_cu, 64) : 4 * c.num_cu;
+  if (e == hipSuccess) e = dalloc(c, &c.bcand, (size_t)c.bblocks * knnd::BIG_CAND);
+  if (e == hipSuccess) e = dalloc(c, &c.bckey, (size_t)c.bblocks * knnd::BIG_CAND);
+  if (e == hipSuccess) e = dalloc(c, &c.dstats, (size_t)knnd::STAT_N);
+  if (e == hipSuccess) e = dalloc(c, &c.dflag, (size_t)4);
+  if (c.arena) {
+    c.hstats = c.hstats_local;
+  } else {
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c.hstats), knnd::STAT_N * sizeof(int64_t));
+    if (e == hipSuccess) e = hipEventCreate(&c.ev0);
+    if (e == hipSuccess) e = hipEventCreate(&c.ev1);
+    if (e == hipSuccess) e = hipEventCreate(&c.evj0);
+    if (e == hipSuccess) e = hipEventCreate(&c.evj1);
+    if (e == hipSuccess) e = hipEventCreate(&c.evh);
+  }
   if (e != hipSuccess) return map_err(e);
   // Hub form: candidate rows of a hub must fit in LDS, and the key slots
   // (K(K+Ks+1) per point) must fit in memory; otherwise the pull form.  The
   // mixed-precision form needs the hub form, D <= 64 (MFMA K dimension) and
-  // the KL comparator (its error bound is derived for that key).
+  // the KL comparator (its error bound is derived for that key).  Buffers of
+  // the hub and mixed forms are optional: when they do not fit, the next
+  // form runs (same results).
   c.use_hub = !(c.flags & KNND_FLAG_PULL) && (size_t)(K + 1) * c.Ds * sizeof(double) <= 64 * 1024;
   c.mixed = c.use_hub && c.precision != KNND_PREC_FP64 && c.D <= 64 && c.cmp == KNND_CMP_KL;
-  if (c.mixed) {
-    c.dk = c.D <= 32 ? 32 : 64;
-    // rows of 2 dk 16-bit values: dk high parts, then dk low parts
-    if (e == hipSuccess) e = knnd::pmalloc(&c.Ph, (size_t)n * c.dk * 4 + 64);
-    if (e == hipSuccess) e = knnd::pmalloc(&c.Lh, (size_t)n * c.dk * 4 + 64);
-    if (e == hipSuccess) e = dalloc(&c.S, (size_t)n);
-    if (e == hipSuccess && dalloc(&c.seg32, nK * (size_t)(K + c.Ks + 1)) != hipSuccess) {
-      (void)hipGetLastError();
+  if (c.use_hub) {
+    const size_t mark = c.arena_used;
+    const size_t sl = (size_t)n * knnd::SHORT_LIST;
+    bool ok = dalloc(c, &c.sl_n, (size_t)n) == hipSuccess && dalloc(c, &c.sl_id, sl) == hipSuccess;
+    if (ok && c.use_hub && c.ck == knnd::CK_REV && c.dtype == KNND_F32)
+      ok = dalloc(c, &c.Pw, (size_t)n * c.D + knnd::HUB_MAXD) == hipSuccess;
+    if (ok && c.mixed) {
+      const size_t mmark = c.arena_used;
+      c.dk = c.D <= 32 ? 32 : 64;
+      // rows of 2 dk 16-bit values: dk high parts, then dk low parts
+      const bool mok = balloc(c, &c.Ph, (size_t)n * c.dk * 4 + 64) == hipSuccess &&
+                       balloc(c, &c.Lh, (size_t)n * c.dk * 4 + 64) == hipSuccess &&
+                       dalloc(c, &c.S, (size_t)n) == hipSuccess &&
+                       dalloc(c, &c.seg32, nK * (size_t)(K + c.Ks + 1)) == hipSuccess;
+      if (!mok) {
+        drop_optional(c, mmark, &c.Ph, &c.Lh, &c.S, &c.seg32);
+        c.mixed = false;
+      }
+    }
+    if (ok && !c.mixed)
+      ok = dalloc(c, &c.seg, nK * (size_t)(K + c.Ks + 1)) == hipSuccess &&
+           dalloc(c, &c.sl_key, sl) == hipSuccess;
+    if (!ok) {
+      drop_optional(c, mark, &c.sl_n, &c.sl_id, &c.Pw, &c.Ph, &c.Lh, &c.S, &c.seg32, &c.seg, &c.sl_key);
+      c.use_hub = false;
       c.mixed = false;
     }
-    if (e != hipSuccess) return map_err(e);
   }
-  if (c.use_hub && !c.mixed && dalloc(&c.seg, nK * (size_t)(K + c.Ks + 1)) != hipSuccess) {
-    (void)hipGetLastError();
-    c.seg = nullptr;
-    c.use_hub = false;
-  }
-  if (c.use_hub && c.ck == knnd::CK_REV && c.dtype == KNND_F32) {
-    e = dalloc(&c.Pw, (size_t)n * c.D + knnd::HUB_MAXD);
-    if (e != hipSuccess) return map_err(e);
-  }
-  if (c.use_hub) {
-    const size_t sl = (size_t)n * knnd::SHORT_LIST;
-    e = dalloc(&c.sl_n, (size_t)n);
-    if (e == hipSuccess) e = dalloc(&c.sl_id, sl);
-    if (e == hipSuccess && !c.mixed) e = dalloc(&c.sl_key, sl);
-    if (e != hipSuccess) return map_err(e);
-  }
-
   return KNND_OK;
 }
 
@@ -382,13 +424,12 @@ int prepare_mixed(Ctx& c, size_t nK) {
     // fall back to the exact hub form
     c.mixed = false;
     (void)hipStreamSynchronize(c.stream);
-    knnd::pool_free(c.seg32);
+    if (!c.arena) knnd::pool_free(c.seg32);  // (an arena keeps the space: the bump pointer only grows)
     c.seg32 = nullptr;
-    if (dalloc(&c.seg, nK * (size_t)(c.K + c.Ks + 1)) != hipSuccess ||
-        dalloc(&c.sl_key, (size_t)c.n * knnd::SHORT_LIST) != hipSuccess) {
-      (void)hipGetLastError();
-      knnd::pool_free(c.seg);
-      c.seg = nullptr;
+    const size_t mark = c.arena_used;
+    if (dalloc(c, &c.seg, nK * (size_t)(c.K + c.Ks + 1)) != hipSuccess ||
+        dalloc(c, &c.sl_key, (size_t)c.n * knnd::SHORT_LIST) != hipSuccess) {
+      drop_optional(c, mark, &c.seg, &c.sl_key);
       c.use_hub = false;  // pull form: needs neither
     }
     return KNND_OK;
@@ -409,8 +450,8 @@ int read_stats(Ctx& c, knnd_round_stats* st, bool joined) {
   KNND_HIP(hipMemcpyAsync(c.hstats, c.dstats, knnd::STAT_N * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
   KNND_HIP(hipStreamSynchronize(c.stream));
   float ms = 0.f, msj = 0.f, msh = 0.f, msr = 0.f;
-  KNND_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
-  if (joined) {
+  if (c.ev0) KNND_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+  if (joined && c.ev0) {
     KNND_HIP(hipEventElapsedTime(&msj, c.evj0, c.evj1));
     KNND_HIP(hipEventElapsedTime(&msh, c.evj0, c.evh));
     KNND_HIP(hipEventElapsedTime(&msr, c.evh, c.evj1));
@@ -435,10 +476,10 @@ int read_stats(Ctx& c, knnd_round_stats* st, bool joined) {
 
 int init_graph(Ctx& c, knnd_round_stats* st) {
   KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
-  KNND_HIP(hipEventRecord(c.ev0, c.stream));
+  KNND_HIP(rec(c.ev0, c.stream));
   KNND_HIP(knnd::launch_init_graph(c));
   KNND_HIP(knnd::launch_fcr(c, c.F[c.cur], 0, c.dstats + knnd::STAT_HITS));
-  KNND_HIP(hipEventRecord(c.ev1, c.stream));
+  KNND_HIP(rec(c.ev1, c.stream));
   c.round = 0;
   c.have_graph = true;
   c.track_ok = false;
@@ -448,7 +489,7 @@ int init_graph(Ctx& c, knnd_round_stats* st) {
 int run_round(Ctx& c, knnd_round_stats* st) {
   if (!c.have_graph) return KNND_ERR_ARG;
   KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
-  KNND_HIP(hipEventRecord(c.ev0, c.stream));
+  KNND_HIP(rec(c.ev0, c.stream));
   KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
   // receivers whose neighbourhood did not change keep their list and count.
   // A changed list touches about 2K neighbourhoods, so few are unchanged
@@ -460,9 +501,12 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   const int64_t nK = c.n * (int64_t)c.K;
   const bool want = c.track_capable && full && c.last_updates >= 0 && c.last_updates * 500 <= nK;
   if (want && !c.vchg) {  // first use: 24 bytes per point
-    if (dalloc(&c.vchg, (size_t)c.n) != hipSuccess || dalloc(&c.vev, (size_t)c.n * knnd::VC_N) != hipSuccess ||
-        knnd::launch_zero_i32(c.vchg, c.n, c.stream) != hipSuccess) {
-      (void)hipGetLastError();  // no tracking then: every receiver is evaluated, as without it
+    const size_t mark = c.arena_used;
+    if (dalloc(c, &c.vchg, (size_t)c.n) != hipSuccess || dalloc(c, &c.vev, (size_t)c.n * knnd::VC_N) != hipSuccess) {
+      drop_optional(c, mark, &c.vchg, &c.vev);  // no tracking then: every receiver is evaluated, as without it
+      c.track_capable = false;
+    } else if (knnd::launch_zero_i32(c.vchg, c.n, c.stream) != hipSuccess) {
+      (void)hipGetLastError();
       c.track_capable = false;
     }
   }
@@ -471,14 +515,14 @@ int run_round(Ctx& c, knnd_round_stats* st) {
                      !(c.flags & (KNND_FLAG_NO_SKIP | KNND_FLAG_NO_CARRY)) && c.last_updates * 1000 <= nK;
   KNND_HIP(knnd::launch_bin(c, carry));
   if (!full) KNND_HIP(knnd::launch_keep_rows(c));
-  KNND_HIP(hipEventRecord(c.evj0, c.stream));
+  KNND_HIP(rec(c.evj0, c.stream));
   KNND_HIP(knnd::launch_join_hub(c, c.dstats));
-  KNND_HIP(hipEventRecord(c.evh, c.stream));
+  KNND_HIP(rec(c.evh, c.stream));
   KNND_HIP(knnd::launch_join_recv(c, c.dstats));
-  KNND_HIP(hipEventRecord(c.evj1, c.stream));
+  KNND_HIP(rec(c.evj1, c.stream));
   if (c.tracking) KNND_HIP(knnd::launch_track(c));
   KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], c.round + 1, c.dstats + knnd::STAT_HITS));
-  KNND_HIP(hipEventRecord(c.ev1, c.stream));
+  KNND_HIP(rec(c.ev1, c.stream));
   c.cur ^= 1;
   c.round += 1;
   c.no_skip_next = !full;
@@ -586,15 +630,15 @@ int create_group(Group& g, const knnd_instance* inst, const knnd_params& prm, in
   if (st != KNND_OK) return st;
   c.nb = nb;
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = dalloc(&c.inst_of, (size_t)N);
-  if (e == hipSuccess) e = dalloc(&c.ioff, (size_t)nb + 1);
-  if (e == hipSuccess) e = dalloc(&c.iseed, (size_t)nb);
-  if (e == hipSuccess) e = dalloc(&c.iM, (size_t)nb);
-  if (e == hipSuccess) e = dalloc(&c.iD, (size_t)nb);
-  if (e == hipSuccess) e = dalloc(&c.iactive, (size_t)nb);
-  if (e == hipSuccess) e = dalloc(&c.istats, (size_t)nb * knnd::STAT_N);
-  if (e == hipSuccess) e = dalloc(&c.vcnt, (size_t)N * knnd::VC_N);
-  if (e == hipSuccess && !on_device) e = dalloc(&g.staging, (size_t)nmax * c.K);
+  if (e == hipSuccess) e = dalloc(c, &c.inst_of, (size_t)N);
+  if (e == hipSuccess) e = dalloc(c, &c.ioff, (size_t)nb + 1);
+  if (e == hipSuccess) e = dalloc(c, &c.iseed, (size_t)nb);
+  if (e == hipSuccess) e = dalloc(c, &c.iM, (size_t)nb);
+  if (e == hipSuccess) e = dalloc(c, &c.iD, (size_t)nb);
+  if (e == hipSuccess) e = dalloc(c, &c.iactive, (size_t)nb);
+  if (e == hipSuccess) e = dalloc(c, &c.istats, (size_t)nb * knnd::STAT_N);
+  if (e == hipSuccess) e = dalloc(c, &c.vcnt, (size_t)N * knnd::VC_N);
+  if (e == hipSuccess && !on_device) e = dalloc(c, &g.staging, (size_t)nmax * c.K);
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&c.histats), (size_t)nb * knnd::STAT_N * sizeof(int64_t));
   if (e != hipSuccess) return map_err(e);
@@ -661,7 +705,7 @@ int group_round(Group& g, int r) {
   Ctx& c = g.c;
   KNND_HIP(knnd::launch_zero_i64(c.istats, (int64_t)c.nb * knnd::STAT_N, c.stream));
   KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
-  KNND_HIP(hipEventRecord(c.ev0, c.stream));
+  KNND_HIP(rec(c.ev0, c.stream));
   if (r == 0) {
     KNND_HIP(knnd::launch_init_graph(c));
     KNND_HIP(knnd::launch_fcr(c, c.F[c.cur], 0, nullptr));
@@ -669,16 +713,16 @@ int group_round(Group& g, int r) {
     KNND_HIP(knnd::launch_zero_i32(c.vcnt, c.n * knnd::VC_N, c.stream));
     KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
     KNND_HIP(knnd::launch_bin(c, false));
-    KNND_HIP(hipEventRecord(c.evj0, c.stream));
+    KNND_HIP(rec(c.evj0, c.stream));
     KNND_HIP(knnd::launch_join_hub(c, c.dstats));
-    KNND_HIP(hipEventRecord(c.evh, c.stream));
+    KNND_HIP(rec(c.evh, c.stream));
     KNND_HIP(knnd::launch_join_recv(c, c.dstats));
-    KNND_HIP(hipEventRecord(c.evj1, c.stream));
+    KNND_HIP(rec(c.evj1, c.stream));
     KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], r, nullptr));
     KNND_HIP(knnd::launch_batch_reduce(c));
     c.cur ^= 1;
   }
-  KNND_HIP(hipEventRecord(c.ev1, c.stream));
+  KNND_HIP(rec(c.ev1, c.stream));
   c.round = r;
   KNND_HIP(hipMemcpyAsync(c.histats, c.istats, (size_t)c.nb * knnd::STAT_N * 8, hipMemcpyDeviceToHost, c.stream));
   KNND_HIP(hipMemcpyAsync(c.hstats, c.dstats, knnd::STAT_N * 8, hipMemcpyDeviceToHost, c.stream));
@@ -791,6 +835,72 @@ int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t 
   return worst;
 }
 
+// A whole descent on a created context: start graph, rounds until the stop
+// rule, lists (and keys) copied out.
+int descend(Ctx& c, const knnd_params* p, int32_t on_device, int32_t* out_idx, double* out_kl,
+            knnd_round_stats* stats, int32_t* out_rounds) {
+  knnd_params prm;
+  (void)resolve_params(p, c.n, &prm);  // already accepted by create
+  knnd_round_stats rs;
+  int st = init_graph(c, &rs);
+  if (st == KNND_OK) {
+    if (stats) stats[0] = rs;
+    int64_t hits_prev = rs.fcr_hits;
+    for (;;) {
+      st = run_round(c, &rs);
+      if (st != KNND_OK) break;
+      if (stats) stats[c.round] = rs;
+      bool capped = false;
+      if (should_stop(prm, c.n, c.K, hits_prev, rs.fcr_hits, rs.updates, c.round, &capped)) {
+        if (capped) st = KNND_WARN_MAX_ROUNDS;
+        break;
+      }
+      hits_prev = rs.fcr_hits;
+    }
+  }
+  if (st == KNND_OK || st == KNND_WARN_MAX_ROUNDS) {
+    const int gst = get_graph(c, out_idx, out_kl, on_device);
+    if (gst != KNND_OK) st = gst;
+    *out_rounds = c.round;
+  }
+  return st;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of knnd_build_noalloc: KNND_NOALLOC_MAX_BYTES in the
+// library's own code object, so every device the library runs on holds a
+// copy of its own until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the device
+// symbol): the address of each device's copy is looked up once, with that
+// device current, and kept per device.  Every call on a device shares that
+// device's copy; calls that overlap on one device race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[KNND_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// The address of device `dev`'s copy of the scratch array (dev is current).
+int scratch_address(int dev, unsigned char** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return KNND_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return KNND_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return KNND_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -912,32 +1022,26 @@ int knnd_build_ex(const void* points, int64_t n, int32_t d, int32_t K, uint64_t 
   knnd_ctx* h = nullptr;
   int st = knnd_ctx_create(points, n, d, K, seed, p, on_device, stream, &h);
   if (st != KNND_OK) return st;
-  Ctx& c = h->c;
-  knnd_params prm;
-  (void)resolve_params(p, n, &prm);  // already accepted by knnd_ctx_create
-  knnd_round_stats rs;
-  st = init_graph(c, &rs);
-  if (st == KNND_OK) {
-    if (stats) stats[0] = rs;
-    int64_t hits_prev = rs.fcr_hits;
-    for (;;) {
-      st = run_round(c, &rs);
-      if (st != KNND_OK) break;
-      if (stats) stats[c.round] = rs;
-      bool capped = false;
-      if (should_stop(prm, c.n, c.K, hits_prev, rs.fcr_hits, rs.updates, c.round, &capped)) {
-        if (capped) st = KNND_WARN_MAX_ROUNDS;
-        break;
-      }
-      hits_prev = rs.fcr_hits;
-    }
-  }
-  if (st == KNND_OK || st == KNND_WARN_MAX_ROUNDS) {
-    const int gst = get_graph(c, out_idx, out_kl, on_device);
-    if (gst != KNND_OK) st = gst;
-    *out_rounds = c.round;
-  }
+  st = descend(h->c, p, on_device, out_idx, out_kl, stats, out_rounds);
   knnd_ctx_destroy(h);
+  return st;
+}
+
+int knnd_build_noalloc(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,
+                       void* stream, int32_t* out_idx, double* out_kl, knnd_round_stats* stats,
+                       int32_t* out_rounds) {
+  if (!points || !out_idx || !out_rounds) return KNND_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return KNND_ERR_DEVICE;
+  unsigned char* base = nullptr;
+  int st = scratch_address(dev, &base);
+  if (st != KNND_OK) return st;
+  Ctx c;  // (on the stack: nothing is allocated)
+  c.arena = base;
+  c.arena_size = (size_t)KNND_NOALLOC_MAX_BYTES;
+  st = create(points, n, d, K, seed, p, 1, stream, c);
+  if (st == KNND_OK) st = descend(c, p, 1, out_idx, out_kl, stats, out_rounds);
+  free_ctx(c);  // (synchronises the stream; an arena gives nothing back)
   return st;
 }
 

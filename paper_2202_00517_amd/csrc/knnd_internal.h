@@ -128,7 +128,13 @@ struct Ctx {
   int64_t gstride = 0;
   int gblocks = 0;
   int64_t* dstats = nullptr;  // [STAT_N] device
-  int64_t* hstats = nullptr;  // [STAT_N] pinned host
+  int64_t* hstats = nullptr;  // [STAT_N] pinned host (fixed-scratch mode: hstats_local)
+  // Fixed-scratch mode (the entry point that allocates nothing): every device
+  // buffer is carved from [arena, arena + arena_size) by a bump pointer
+  // instead of coming from the memory cache; no events, no pinned memory
+  unsigned char* arena = nullptr;
+  size_t arena_size = 0, arena_used = 0;
+  int64_t hstats_local[STAT_N] = {};
   int32_t* dflag = nullptr;   // device scratch flag
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evj0 = nullptr, evj1 = nullptr, evh = nullptr;
 
