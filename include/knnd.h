@@ -84,7 +84,14 @@ typedef enum { KNND_F32 = 0, KNND_F64 = 1 } knnd_dtype;
 typedef enum {
     KNND_PREC_FP64 = 0,         /* every key computed in canonical FP64 */
     KNND_PREC_MIXED_BF16 = 1,   /* BF16 split operands, FP64 rescue */
-    KNND_PREC_MIXED_FP16 = 2    /* FP16 split operands, FP64 rescue */
+    KNND_PREC_MIXED_FP16 = 2,   /* FP16 split operands, FP64 rescue */
+    KNND_PREC_AUTO = 3          /* the exact FP64 form or the BF16 mixed form,
+                                   whichever the library's autotuner measures
+                                   faster on the first round's join (per group
+                                   in batched calls); choices are cached per
+                                   workload shape in the process and, when the
+                                   environment variable KNND_TUNE_CACHE names a
+                                   file, in that file */
 } knnd_precision;
 
 /* flags */
@@ -98,6 +105,14 @@ typedef enum {
                                    device-wide atomic per edge (the form used
                                    above 2^25 points) instead of the bucketed
                                    counting sort (same result) */
+#define KNND_FLAG_NO_GRAPH 0x10 /* batched calls: enqueue every round's kernels
+                                   one by one instead of replaying the rounds
+                                   after the second from captured graphs
+                                   (same result) */
+#define KNND_FLAG_NO_TUNE 0x20  /* no timing of candidate join schedules:
+                                   k_hub_reg in the exact form, and
+                                   KNND_PREC_AUTO runs the BF16 mixed form
+                                   (same result) */
 #define KNND_FLAG_NO_CARRY 0x8  /* evaluate every receiver in late rounds too,
                                    instead of carrying over the list and the
                                    evaluation count of a receiver whose
@@ -279,9 +294,14 @@ int knnd_build_noalloc(const void* points, int64_t n, int32_t d, int32_t K, uint
  *   stream      as in knnd_build_ex; the host synchronises once per round for
  *               all instances together.
  * Instances are grouped by K and number of coordinates; a group runs as one
- * set of launches per round, and an instance leaves its group's rounds after
- * its own stop test.  Per-round times in an instance's stats are those of its
- * group's round.  Returns KNND_OK, KNND_WARN_MAX_ROUNDS when some instance hit
+ * set of persistent kernel launches per round, and an instance leaves its
+ * group's rounds after its own stop test.  Rounds after the second are one
+ * launch of a captured graph holding every running group's kernels (two
+ * graphs, one per parity of the double-buffered lists; captured again when
+ * a whole group has stopped; KNND_FLAG_NO_GRAPH enqueues the kernels one by
+ * one instead).  `ms` in an instance's stats is the device time of the
+ * whole round of every running group; ms_join, ms_hub and ms_recv are 0.
+ * Returns KNND_OK, KNND_WARN_MAX_ROUNDS when some instance hit
  * the round cap, or the first error (then every output is unspecified);
  * argument errors of any instance are reported before any device work.
  */

@@ -23,11 +23,13 @@ KNND_ERR_DEVICE = -4
 KNND_ERR_UNSUPPORTED = -5
 
 KNND_F32, KNND_F64 = 0, 1
-KNND_PREC_FP64, KNND_PREC_MIXED_BF16, KNND_PREC_MIXED_FP16 = 0, 1, 2
+KNND_PREC_FP64, KNND_PREC_MIXED_BF16, KNND_PREC_MIXED_FP16, KNND_PREC_AUTO = 0, 1, 2, 3
 KNND_FLAG_NO_SKIP = 0x1
 KNND_FLAG_PULL = 0x2
 KNND_FLAG_ATOMIC_CSR = 0x4
 KNND_FLAG_NO_CARRY = 0x8
+KNND_FLAG_NO_GRAPH = 0x10
+KNND_FLAG_NO_TUNE = 0x20
 KNND_STOP_FCR, KNND_STOP_FIXED_POINT, KNND_STOP_DELTA = 0, 1, 2
 KNND_CMP_KL, KNND_CMP_KL_REVERSE, KNND_CMP_HELLINGER, KNND_CMP_L2 = 0, 1, 2, 3
 

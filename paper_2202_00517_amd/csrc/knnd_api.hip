@@ -8,8 +8,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <string>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -214,7 +217,7 @@ int resolve_params(const knnd_params* p, int64_t n, knnd_params* out) {
   if (out->fcr_samples <= 0) out->fcr_samples = n < 10000 ? n : 10000;
   if (out->max_rounds <= 0) out->max_rounds = 100;
   if (out->dtype != KNND_F32 && out->dtype != KNND_F64) return KNND_ERR_ARG;
-  if (out->precision < KNND_PREC_FP64 || out->precision > KNND_PREC_MIXED_FP16) return KNND_ERR_ARG;
+  if (out->precision < KNND_PREC_FP64 || out->precision > KNND_PREC_AUTO) return KNND_ERR_ARG;
   if (out->stop_rule < KNND_STOP_FCR || out->stop_rule > KNND_STOP_DELTA) return KNND_ERR_ARG;
   if (out->comparator < KNND_CMP_KL || out->comparator > KNND_CMP_L2) return KNND_ERR_ARG;
   if (!(out->delta >= 0.0) || !std::isfinite(out->delta)) return KNND_ERR_ARG;
@@ -252,8 +255,12 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   while (c.Ks < K) c.Ks <<= 1;
   c.seed = seed;
   c.dtype = prm.dtype;
-  c.precision = prm.precision;
+  // (the automatic mode splits operands like the BF16 mode when it runs mixed)
+  c.auto_prec = prm.precision == KNND_PREC_AUTO;
+  c.precision = c.auto_prec ? KNND_PREC_MIXED_BF16 : prm.precision;
   c.flags = prm.flags;
+  // (the tuner times with HIP events: none in fixed-scratch mode)
+  c.tune = c.auto_prec && !c.arena && !(prm.flags & KNND_FLAG_NO_TUNE);
   c.cmp = prm.comparator;
   c.ck = knnd::cmp_fold_kind(c.cmp);
   c.tk = knnd::cmp_table_kind(c.cmp);
@@ -345,15 +352,24 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
         c.mixed = false;
       }
     }
-    if (ok && !c.mixed)
-      ok = dalloc(c, &c.seg, nK * (size_t)(K + c.Ks + 1)) == hipSuccess &&
-           dalloc(c, &c.sl_key, sl) == hipSuccess;
+    // (the automatic mode keeps the exact form's slots too, so that either
+    // form can run)
+    if (ok && (!c.mixed || c.auto_prec)) {
+      const size_t pmark = c.arena_used;
+      const bool pok = dalloc(c, &c.seg, nK * (size_t)(K + c.Ks + 1)) == hipSuccess &&
+                       dalloc(c, &c.sl_key, sl) == hipSuccess;
+      if (!pok) {
+        drop_optional(c, pmark, &c.seg, &c.sl_key);
+        ok = c.mixed;  // mixed only
+      }
+    }
     if (!ok) {
       drop_optional(c, mark, &c.sl_n, &c.sl_id, &c.Pw, &c.Ph, &c.Lh, &c.S, &c.seg32, &c.seg, &c.sl_key);
       c.use_hub = false;
       c.mixed = false;
     }
   }
+  c.plain_ok = c.use_hub && c.seg && c.sl_key;
   return KNND_OK;
 }
 
@@ -426,14 +442,18 @@ int prepare_mixed(Ctx& c, size_t nK) {
     (void)hipStreamSynchronize(c.stream);
     if (!c.arena) knnd::pool_free(c.seg32);  // (an arena keeps the space: the bump pointer only grows)
     c.seg32 = nullptr;
-    const size_t mark = c.arena_used;
-    if (dalloc(c, &c.seg, nK * (size_t)(c.K + c.Ks + 1)) != hipSuccess ||
-        dalloc(c, &c.sl_key, (size_t)c.n * knnd::SHORT_LIST) != hipSuccess) {
-      drop_optional(c, mark, &c.seg, &c.sl_key);
-      c.use_hub = false;  // pull form: needs neither
+    if (!c.plain_ok) {
+      const size_t mark = c.arena_used;
+      if (dalloc(c, &c.seg, nK * (size_t)(c.K + c.Ks + 1)) != hipSuccess ||
+          dalloc(c, &c.sl_key, (size_t)c.n * knnd::SHORT_LIST) != hipSuccess) {
+        drop_optional(c, mark, &c.seg, &c.sl_key);
+        c.use_hub = false;  // pull form: needs neither
+      }
+      c.plain_ok = c.use_hub;
     }
     return KNND_OK;
   }
+  c.mixed_ok = true;
   const double u = (bf16 ? 0x1p-8 : 0x1p-11) + 0x1p-23;
   const double s = bf16 ? 0x1p-133 : 0x1p-24;
   const double m = 3.0 * c.D + 3.0;         // FP32 rounding steps
@@ -486,11 +506,134 @@ int init_graph(Ctx& c, knnd_round_stats* st) {
   return read_stats(c, st, false);
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner of the join's schedule.  Candidates: the exact hub form with the
+// register-staged hub kernel (k_hub_reg) or the LDS-staged one (k_hub_lds),
+// and, under KNND_PREC_AUTO, the BF16 mixed form.  Every candidate computes
+// the same lists, keys and counts, so a choice changes only speed: the join
+// of the coming round (binning, hub kernel, receiver pass) is run once per
+// candidate from the round-start snapshot, timed with HIP events, and the
+// fastest is kept; the round then runs in full with it.  Choices are cached
+// by workload shape (K, coordinates, size class, single or batched,
+// comparator, precision mode) for the rest of the process and, when
+// KNND_TUNE_CACHE names a file, in that file: one line per shape,
+// "<shape> | <mixed> <hub_lds> | <ms of each candidate>".
+// ---------------------------------------------------------------------------
+struct Sched {
+  bool mixed;
+  bool hub_lds;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Sched> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("KNND_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* bar = std::strchr(line, '|');
+    int m = 0, h = 0;
+    if (!bar || std::sscanf(bar + 1, "%d %d", &m, &h) != 2) continue;
+    std::string key(line, (size_t)(bar - line));
+    while (!key.empty() && key.back() == ' ') key.pop_back();
+    g_tune[key] = Sched{m != 0, h != 0};
+  }
+  std::fclose(f);
+}
+
+std::string tune_key(const Ctx& c, bool group) {
+  int lg = 0;
+  while (((int64_t)1 << lg) < c.n) ++lg;
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "gfx950 K=%d D=%d log2n=%d batched=%d cmp=%d prec=%d", c.K, c.D, lg, group ? 1 : 0,
+                c.cmp, c.auto_prec ? (int)KNND_PREC_AUTO : c.precision);
+  return buf;
+}
+
+void apply_sched(Ctx& c, Sched s) {
+  c.mixed = s.mixed;
+  c.hub_lds = s.hub_lds;
+}
+
+// Choose the join's schedule for context c; its reverse-neighbour lists for
+// the coming round must be built.  group: a batched group (its per-instance
+// and per-point counters are cleared between trials too).
+int tune_join(Ctx& c, bool group) {
+  Sched cand[3];
+  int nc = 0;
+  const bool lds_fits = (size_t)(c.K + 1) * c.Ds * sizeof(double) <= 64 * 1024;
+  if (c.plain_ok && (c.auto_prec || !c.mixed)) {
+    cand[nc++] = Sched{false, false};
+    if (lds_fits) cand[nc++] = Sched{false, true};
+  }
+  if (c.mixed_ok && (c.auto_prec || c.mixed)) cand[nc++] = Sched{true, false};
+  if (nc == 0 || !c.evj0) return KNND_OK;
+  if (nc == 1) {
+    apply_sched(c, cand[0]);
+    return KNND_OK;
+  }
+  const std::string key = tune_key(c, group);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      apply_sched(c, it->second);
+      return KNND_OK;
+    }
+  }
+  float ms[3] = {0.f, 0.f, 0.f};
+  int best = 0;
+  for (int i = 0; i < nc; ++i) {
+    apply_sched(c, cand[i]);
+    KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
+    if (group) {
+      KNND_HIP(knnd::launch_zero_i64(c.istats, (int64_t)c.nb * knnd::STAT_N, c.stream));
+      KNND_HIP(knnd::launch_zero_i32(c.vcnt, c.n * knnd::VC_N, c.stream));
+    }
+    KNND_HIP(knnd::launch_bin(c, false));
+    KNND_HIP(hipEventRecord(c.evj0, c.stream));
+    KNND_HIP(knnd::launch_join_hub(c, c.dstats));
+    KNND_HIP(knnd::launch_join_recv(c, c.dstats));
+    KNND_HIP(hipEventRecord(c.evj1, c.stream));
+    KNND_HIP(hipStreamSynchronize(c.stream));
+    KNND_HIP(hipEventElapsedTime(&ms[i], c.evj0, c.evj1));
+    if (ms[i] < ms[best]) best = i;
+  }
+  apply_sched(c, cand[best]);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = cand[best];
+  const char* path = std::getenv("KNND_TUNE_CACHE");
+  if (path && *path) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s | %d %d |", key.c_str(), cand[best].mixed ? 1 : 0, cand[best].hub_lds ? 1 : 0);
+      for (int i = 0; i < nc; ++i)
+        std::fprintf(f, " %s%s:%.3f", cand[i].mixed ? "mixed" : "exact", cand[i].hub_lds ? "/lds" : "", ms[i]);
+      std::fprintf(f, "\n");
+      std::fclose(f);
+    }
+  }
+  return KNND_OK;
+}
+
 int run_round(Ctx& c, knnd_round_stats* st) {
   if (!c.have_graph) return KNND_ERR_ARG;
   KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
   KNND_HIP(rec(c.ev0, c.stream));
   KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
+  if (c.tune && !c.tuned && c.own0 == 0 && c.own1 == c.n) {
+    // (the first round's time includes the trials)
+    c.tuned = true;
+    const int t = tune_join(c, false);
+    if (t != KNND_OK) return t;
+    KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
+  }
   // receivers whose neighbourhood did not change keep their list and count.
   // A changed list touches about 2K neighbourhoods, so few are unchanged
   // until few lists change: the flags are gathered once the last round
@@ -629,6 +772,7 @@ int create_group(Group& g, const knnd_instance* inst, const knnd_params& prm, in
   int st = setup(c, N, Dmax - 1, first.K, 0, prm, stream);
   if (st != KNND_OK) return st;
   c.nb = nb;
+  c.tune = !(prm.flags & KNND_FLAG_NO_TUNE);
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = dalloc(c, &c.inst_of, (size_t)N);
   if (e == hipSuccess) e = dalloc(c, &c.ioff, (size_t)nb + 1);
@@ -639,8 +783,6 @@ int create_group(Group& g, const knnd_instance* inst, const knnd_params& prm, in
   if (e == hipSuccess) e = dalloc(c, &c.istats, (size_t)nb * knnd::STAT_N);
   if (e == hipSuccess) e = dalloc(c, &c.vcnt, (size_t)N * knnd::VC_N);
   if (e == hipSuccess && !on_device) e = dalloc(c, &g.staging, (size_t)nmax * c.K);
-  if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&c.histats), (size_t)nb * knnd::STAT_N * sizeof(int64_t));
   if (e != hipSuccess) return map_err(e);
 
   std::vector<int32_t> inst_of((size_t)N), iD(nb), act(nb, 1);
@@ -699,13 +841,46 @@ int create_group(Group& g, const knnd_instance* inst, const knnd_params& prm, in
   return finish_create(c);
 }
 
-// Enqueue round r (r = 0: the start graph and its FCR) of every running
-// instance of the group, and the copy of the per-instance counters.
-int group_round(Group& g, int r) {
+// Per-call state of a batched call.  Every group's counters of a round land
+// in one device array, copied to the host once per round.  Rounds after the
+// second are replayed from two captured graphs (one per parity of the
+// double-buffered lists) holding the kernels of every running group; the
+// round index the FCR sample hashes is read from the device and advanced by
+// the graph's last kernel.  A graph is captured again only when a whole
+// group has stopped (a stopped instance inside a running group is skipped by
+// the kernels through its device flag).
+struct Batch {
+  std::vector<Group> groups;
+  std::vector<int64_t> slot;   // first row of each group's instances in dall
+  int64_t sum_nb = 0;          // rows of instance counters; the group rows follow
+  int64_t* dall = nullptr;     // device [sum_nb + groups][STAT_N]
+  int64_t* hall = nullptr;     // pinned host copy
+  int64_t* dround = nullptr;   // device round index of graph-launched rounds
+  hipStream_t cs = nullptr;    // capture stream
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::vector<char> captured;  // running groups the graphs hold
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+void drop_graphs(Batch& bt) {
+  for (int p = 0; p < 2; ++p) {
+    if (bt.exec[p]) (void)hipGraphExecDestroy(bt.exec[p]);
+    if (bt.graph[p]) (void)hipGraphDestroy(bt.graph[p]);
+    bt.exec[p] = nullptr;
+    bt.graph[p] = nullptr;
+  }
+  bt.captured.clear();
+}
+
+// Enqueue round r (r = 0: the start graph and its FCR) of group gi on its
+// stream, and the copy of its counters into dall.  round_dev: the device
+// round index for the FCR sample (graph-launched rounds), else r.
+int enqueue_group_round(Batch& bt, size_t gi, int r, const int64_t* round_dev) {
+  Group& g = bt.groups[gi];
   Ctx& c = g.c;
   KNND_HIP(knnd::launch_zero_i64(c.istats, (int64_t)c.nb * knnd::STAT_N, c.stream));
   KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
-  KNND_HIP(rec(c.ev0, c.stream));
   if (r == 0) {
     KNND_HIP(knnd::launch_init_graph(c));
     KNND_HIP(knnd::launch_fcr(c, c.F[c.cur], 0, nullptr));
@@ -713,19 +888,52 @@ int group_round(Group& g, int r) {
     KNND_HIP(knnd::launch_zero_i32(c.vcnt, c.n * knnd::VC_N, c.stream));
     KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
     KNND_HIP(knnd::launch_bin(c, false));
-    KNND_HIP(rec(c.evj0, c.stream));
     KNND_HIP(knnd::launch_join_hub(c, c.dstats));
-    KNND_HIP(rec(c.evh, c.stream));
     KNND_HIP(knnd::launch_join_recv(c, c.dstats));
-    KNND_HIP(rec(c.evj1, c.stream));
-    KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], r, nullptr));
+    KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], r, nullptr, round_dev));
     KNND_HIP(knnd::launch_batch_reduce(c));
-    c.cur ^= 1;
   }
-  KNND_HIP(rec(c.ev1, c.stream));
-  c.round = r;
-  KNND_HIP(hipMemcpyAsync(c.histats, c.istats, (size_t)c.nb * knnd::STAT_N * 8, hipMemcpyDeviceToHost, c.stream));
-  KNND_HIP(hipMemcpyAsync(c.hstats, c.dstats, knnd::STAT_N * 8, hipMemcpyDeviceToHost, c.stream));
+  KNND_HIP(knnd::launch_copy_i64(bt.dall + bt.slot[gi] * knnd::STAT_N, c.istats, (int64_t)c.nb * knnd::STAT_N,
+                                 c.stream));
+  KNND_HIP(knnd::launch_copy_i64(bt.dall + (bt.sum_nb + (int64_t)gi) * knnd::STAT_N, c.dstats, knnd::STAT_N,
+                                 c.stream));
+  return KNND_OK;
+}
+
+// Capture the round of every running group, for both parities.  On failure
+// the call goes on with rounds enqueued one by one.
+int capture_graphs(Batch& bt) {
+  drop_graphs(bt);
+  if (!bt.cs) KNND_HIP(hipStreamCreateWithFlags(&bt.cs, hipStreamNonBlocking));
+  for (int p = 0; p < 2; ++p) {
+    std::vector<std::pair<hipStream_t, int>> saved;
+    for (Group& g : bt.groups) {
+      saved.emplace_back(g.c.stream, g.c.cur);
+      g.c.stream = bt.cs;
+      g.c.cur = p;
+    }
+    int st = KNND_OK;
+    if (hipStreamBeginCapture(bt.cs, hipStreamCaptureModeRelaxed) != hipSuccess) st = KNND_ERR_DEVICE;
+    for (size_t gi = 0; gi < bt.groups.size() && st == KNND_OK; ++gi)
+      if (bt.groups[gi].running > 0) st = enqueue_group_round(bt, gi, 1, bt.dround);
+    if (st == KNND_OK && knnd::launch_add_i64(bt.dround, 1, bt.cs) != hipSuccess) st = KNND_ERR_DEVICE;
+    hipGraph_t gr = nullptr;
+    const hipError_t ee = hipStreamEndCapture(bt.cs, &gr);  // (ends a capture that failed midway too)
+    bt.graph[p] = gr;
+    for (size_t gi = 0; gi < bt.groups.size(); ++gi) {
+      bt.groups[gi].c.stream = saved[gi].first;
+      bt.groups[gi].c.cur = saved[gi].second;
+    }
+    if (st == KNND_OK && (ee != hipSuccess || !gr)) st = KNND_ERR_DEVICE;
+    if (st == KNND_OK && hipGraphInstantiate(&bt.exec[p], gr, nullptr, nullptr, 0) != hipSuccess) st = KNND_ERR_DEVICE;
+    if (st != KNND_OK) {
+      (void)hipGetLastError();
+      drop_graphs(bt);
+      return st;
+    }
+  }
+  bt.captured.clear();
+  for (const Group& g : bt.groups) bt.captured.push_back(g.running > 0);
   return KNND_OK;
 }
 
@@ -758,40 +966,88 @@ int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t 
     if (st != KNND_OK) return st;
     by_shape[{in.K, coord_bucket(in.d + 1)}].push_back(b);
   }
-  std::vector<Group> groups(by_shape.size());
+  hipStream_t strm = reinterpret_cast<hipStream_t>(stream);
+  Batch bt;
+  std::vector<Group>& groups = bt.groups;
+  groups.resize(by_shape.size());
   size_t gi = 0;
-  for (auto& kv : by_shape) groups[gi++].members = kv.second;
+  for (auto& kv : by_shape) {
+    groups[gi].members = kv.second;
+    bt.slot.push_back(bt.sum_nb);
+    bt.sum_nb += (int64_t)kv.second.size();
+    ++gi;
+  }
   int worst = KNND_OK;
   auto fail = [&](int s) {
-    for (Group& g : groups) {
-      (void)hipStreamSynchronize(g.c.stream);
-      free_group(g);
-    }
+    (void)hipStreamSynchronize(strm);
+    drop_graphs(bt);
+    if (bt.cs) (void)hipStreamDestroy(bt.cs);
+    for (Group& g : groups) free_group(g);
+    knnd::pool_free(bt.dall);
+    knnd::pool_free(bt.dround);
+    if (bt.hall) (void)hipHostFree(bt.hall);
+    if (bt.e0) (void)hipEventDestroy(bt.e0);
+    if (bt.e1) (void)hipEventDestroy(bt.e1);
     return s;
   };
+  const size_t rows = (size_t)bt.sum_nb + groups.size();
+  if (knnd::pmalloc(&bt.dall, rows * knnd::STAT_N * sizeof(int64_t)) != hipSuccess ||
+      knnd::pmalloc(&bt.dround, 64) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&bt.hall), rows * knnd::STAT_N * sizeof(int64_t)) != hipSuccess ||
+      hipEventCreate(&bt.e0) != hipSuccess || hipEventCreate(&bt.e1) != hipSuccess)
+    return fail(KNND_ERR_NOMEM);
   for (Group& g : groups) {
     st = create_group(g, inst, prm, on_device, stream);
     if (st != KNND_OK) return fail(st);
   }
+  bool graphs = !(prm.flags & KNND_FLAG_NO_GRAPH);
+  bool round_set = false;  // dround holds the index of the next graph-launched round
   int running = B;
   for (int r = 0; running > 0; ++r) {
+    if (hipEventRecord(bt.e0, strm) != hipSuccess) return fail(KNND_ERR_DEVICE);
+    bool replay = graphs && r >= 2;
+    if (replay) {
+      std::vector<char> now;
+      for (const Group& g : groups) now.push_back(g.running > 0);
+      if (now != bt.captured && capture_graphs(bt) != KNND_OK) graphs = replay = false;
+    }
+    if (replay) {
+      if (!round_set && knnd::launch_set_i64(bt.dround, r, strm) != hipSuccess) return fail(KNND_ERR_DEVICE);
+      round_set = true;
+      if (hipGraphLaunch(bt.exec[(r - 1) & 1], strm) != hipSuccess) return fail(KNND_ERR_DEVICE);
+    } else {
+      for (size_t q = 0; q < groups.size(); ++q) {
+        Ctx& c = groups[q].c;
+        if (groups[q].running == 0) continue;
+        if (r == 1 && c.tune && !c.tuned) {  // the join's schedule, from this round's snapshot
+          c.tuned = true;
+          if (knnd::launch_csr(c, c.F[c.cur]) != hipSuccess) return fail(KNND_ERR_DEVICE);
+          if ((st = tune_join(c, true)) != KNND_OK) return fail(st);
+        }
+        if ((st = enqueue_group_round(bt, q, r, nullptr)) != KNND_OK) return fail(st);
+      }
+    }
     for (Group& g : groups)
-      if (g.running > 0 && (st = group_round(g, r)) != KNND_OK) return fail(st);
-    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return fail(KNND_ERR_DEVICE);
-    for (Group& g : groups) {
+      if (g.running > 0) {
+        if (r > 0) g.c.cur ^= 1;
+        g.c.round = r;
+      }
+    if (hipEventRecord(bt.e1, strm) != hipSuccess ||
+        hipMemcpyAsync(bt.hall, bt.dall, rows * knnd::STAT_N * sizeof(int64_t), hipMemcpyDeviceToHost, strm) !=
+            hipSuccess ||
+        hipStreamSynchronize(strm) != hipSuccess)
+      return fail(KNND_ERR_DEVICE);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, bt.e0, bt.e1) != hipSuccess) return fail(KNND_ERR_DEVICE);
+    for (size_t q = 0; q < groups.size(); ++q) {
+      Group& g = groups[q];
       if (g.running == 0 || g.c.round != r) continue;
       Ctx& c = g.c;
-      if (c.hstats[knnd::STAT_ERR] != 0) return fail(KNND_ERR_DEVICE);
-      float ms = 0.f, msj = 0.f, msh = 0.f, msr = 0.f;
-      if (hipEventElapsedTime(&ms, c.ev0, c.ev1) != hipSuccess) return fail(KNND_ERR_DEVICE);
-      if (r > 0 && (hipEventElapsedTime(&msj, c.evj0, c.evj1) != hipSuccess ||
-                    hipEventElapsedTime(&msh, c.evj0, c.evh) != hipSuccess ||
-                    hipEventElapsedTime(&msr, c.evh, c.evj1) != hipSuccess))
-        return fail(KNND_ERR_DEVICE);
+      if (bt.hall[(bt.sum_nb + (int64_t)q) * knnd::STAT_N + knnd::STAT_ERR] != 0) return fail(KNND_ERR_DEVICE);
       for (int j = 0; j < c.nb; ++j) {
         if (!g.active[j]) continue;
         knnd_instance& in = inst[g.members[j]];
-        const int64_t* s = c.histats + (size_t)j * knnd::STAT_N;
+        const int64_t* s = bt.hall + (size_t)(bt.slot[q] + j) * knnd::STAT_N;
         knnd_round_stats rs;
         rs.updates = s[knnd::STAT_UPDATES];
         rs.fcr_hits = s[knnd::STAT_HITS];
@@ -800,10 +1056,8 @@ int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t 
         rs.rescues = s[knnd::STAT_RESCUES];
         rs.carried = 0;  // (groups evaluate every running receiver)
         rs.evals_carried = 0;
-        rs.ms = ms;
-        rs.ms_join = msj;
-        rs.ms_hub = msh;
-        rs.ms_recv = msr;
+        rs.ms = ms;  // the round of every running group
+        rs.ms_join = rs.ms_hub = rs.ms_recv = 0.0;
         if (in.stats) in.stats[r] = rs;
         if (r == 0) {
           g.hits_prev[j] = rs.fcr_hits;

@@ -106,6 +106,15 @@ struct Ctx {
   float* seg32 = nullptr;     // [nK(K+Ks+1)] cross terms C~ by snapshot edge
   double eps_relq = 0.0, eps_abs = 0.0;  // mixed-form error bound: e_rel / (1 - e_rel) and e_abs
   bool use_hub = false;
+  // Join schedule (every choice gives the same results; see the tuner in
+  // knnd_api.hip): the exact hub form runs k_hub_lds instead of k_hub_reg
+  bool hub_lds = false;
+  mutable int hub_lds_grid = 0;  // its grid, fixed on first use
+  bool auto_prec = false;        // KNND_PREC_AUTO: the tuner picks exact or mixed
+  bool tune = false;             // time the candidate schedules on the first round
+  bool tuned = false;
+  bool mixed_ok = false;         // the mixed form's operands and bound are ready
+  bool plain_ok = false;         // the exact hub form's key slots are ready
   // short candidate lists handed from the receiver kernel to k_merge (hub form)
   int32_t* sl_n = nullptr;     // [n] list length, -1 when the receiver kernel merged itself
   uint32_t* sl_id = nullptr;   // [n][SHORT_LIST]
@@ -210,7 +219,8 @@ hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_log_table(const Ctx& c, int32_t* bad);
 hipError_t launch_widen(const Ctx& c);
 hipError_t launch_init_graph(const Ctx& c);
-hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits);
+hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits,
+                      const int64_t* round_dev = nullptr);
 hipError_t launch_csr(const Ctx& c, const uint32_t* F);
 hipError_t launch_bin(const Ctx& c, bool carry);
 hipError_t launch_join_hub(const Ctx& c, int64_t* stats);
@@ -224,5 +234,8 @@ hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_
 hipError_t launch_batch_reduce(const Ctx& c);
 hipError_t launch_emit(const Ctx& c, int64_t off, int64_t n_b, int32_t* out_idx);
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_copy_i64(int64_t* dst, const int64_t* src, int64_t cnt, hipStream_t s);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 
 }  // namespace knnd

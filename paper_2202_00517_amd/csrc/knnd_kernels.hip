@@ -222,10 +222,13 @@ __global__ __launch_bounds__(256) void k_fcr_batched(const uint32_t* __restrict_
                                                      const int64_t* __restrict__ ioff,
                                                      const uint64_t* __restrict__ iseed,
                                                      const int64_t* __restrict__ iM,
-                                                     const int32_t* __restrict__ iactive, int64_t round,
+                                                     const int32_t* __restrict__ iactive, int64_t round_arg,
+                                                     const int64_t* __restrict__ round_dev,
                                                      int64_t* __restrict__ istats) {
   const int b = blockIdx.y;
   if (!iactive[b]) return;  // whole block
+  // (rounds replayed from a captured graph read their index from the device)
+  const int64_t round = round_dev ? *round_dev : round_arg;
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t base = ioff[b], nn = ioff[b + 1] - base;
   const uint64_t seed = iseed[b];
@@ -276,6 +279,20 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const int32_t* __restrict_
     st[STAT_PERF] = tot[VC_HUBPERF] + tot[VC_RECVPERF];
     st[STAT_RESCUES] = tot[VC_RESC];
   }
+}
+
+// Small helpers of the batched rounds: copy counters, set and advance the
+// device round index (kernels rather than memset/memcpy nodes, so that a
+// captured round holds kernels only).
+__global__ void k_copy_i64(int64_t* __restrict__ dst, const int64_t* __restrict__ src, int64_t cnt) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cnt; t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+__global__ void k_add_i64(int64_t* p, int64_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p += v;
 }
 
 // Rows [off, off + nb) of the lists, as indices local to their instance.
@@ -1966,6 +1983,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIX ? 5 : 1
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// Resident blocks per CU of a kernel without dynamic LDS, queried once per
+// kernel and block size (so that launches recorded into a graph make no
+// other runtime call).
+template <auto KERN, int BLOCK>
+static int occupancy() {
+  static const int v = [] {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, KERN, BLOCK, 0) != hipSuccess || per_cu < 1) {
+      (void)hipGetLastError();
+      per_cu = 1;
+    }
+    return per_cu;
+  }();
+  return v;
+}
+
 static inline int grid_for(int64_t work, int block, int cap_blocks) {
   int64_t g = (work + block - 1) / block;
   if (g < 1) g = 1;
@@ -2021,12 +2054,13 @@ hipError_t launch_init_graph(const Ctx& c) {
   return hipGetLastError();
 }
 
-// (batched group: per-instance samples, hits into istats; `hits` unused)
-hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits) {
+// (batched group: per-instance samples, hits into istats; `hits` unused;
+// round_dev, when given, holds the round index instead of `round`)
+hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits, const int64_t* round_dev) {
   if (c.nb > 0) {
     const int gx = grid_for(c.Mmax, 256, 1 << 30);
     hipLaunchKernelGGL(k_fcr_batched, dim3(gx, c.nb), dim3(256), 0, c.stream, F, c.K, c.Ks, c.ioff, c.iseed, c.iM,
-                       c.iactive, round, c.istats);
+                       c.iactive, round, round_dev, c.istats);
     return hipGetLastError();
   }
   const int g = grid_for(c.M, 256, 1 << 30);
@@ -2043,6 +2077,21 @@ hipError_t launch_emit(const Ctx& c, int64_t off, int64_t n_b, int32_t* out_idx)
   const int64_t cnt = n_b * c.K;
   hipLaunchKernelGGL(k_emit, dim3(grid_for(cnt, 256, 4096)), dim3(256), 0, c.stream, c.F[c.cur], off, cnt, c.K,
                      c.Ks, out_idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_i64(int64_t* dst, const int64_t* src, int64_t cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_i64, dim3(grid_for(cnt, 256, 64)), dim3(256), 0, s, dst, src, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();
 }
 
@@ -2106,11 +2155,7 @@ static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
     // small tables: two waves per receiver, twice the receivers in flight
     constexpr int NWC = CAP <= SMALL_NW_CAP ? 2 : 4;
     auto kern = k_recv<CAP, PT, MODE, NWC>;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NWC * 64, 0) != hipSuccess || per_cu < 1) {
-      (void)hipGetLastError();
-      per_cu = 1;
-    }
+    const int per_cu = occupancy<k_recv<CAP, PT, MODE, NWC>, NWC * 64>();
     int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
     if (CAP >= 8192) grid = std::min(grid, c.bblocks);  // one global candidate region per block
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NWC * 64), 0, c.stream, a, c.class_list, c.class_count, cls);
@@ -2134,8 +2179,7 @@ static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
 template <int MAXD, typename PT, int CK>
 static hipError_t launch_hub_reg(const Ctx& c, const JoinArgs& a) {
   auto kern = k_hub_reg<MAXD, PT, CK>;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int per_cu = occupancy<k_hub_reg<MAXD, PT, CK>, 256>();
   const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu * 4);
   // candidate point rows as FP64 (read only by the reverse-KL fold)
   const double* Pd = c.Pw ? c.Pw : reinterpret_cast<const double*>(c.P);
@@ -2145,21 +2189,27 @@ static hipError_t launch_hub_reg(const Ctx& c, const JoinArgs& a) {
 
 template <typename PT, int CK>
 static hipError_t launch_hub(const Ctx& c, const JoinArgs& a) {
-  if (c.D <= 8) return launch_hub_reg<8, PT, CK>(c, a);
-  if (c.D <= 12) return launch_hub_reg<12, PT, CK>(c, a);
-  if (c.D <= 16) return launch_hub_reg<16, PT, CK>(c, a);
-  if (c.D <= 24) return launch_hub_reg<24, PT, CK>(c, a);
-  if (c.D <= 32) return launch_hub_reg<32, PT, CK>(c, a);
-  if (c.D <= 40) return launch_hub_reg<40, PT, CK>(c, a);
-  if (c.D <= 52) return launch_hub_reg<52, PT, CK>(c, a);
-  if (c.D <= HUB_MAXD) return launch_hub_reg<HUB_MAXD, PT, CK>(c, a);
+  if (!c.hub_lds) {
+    if (c.D <= 8) return launch_hub_reg<8, PT, CK>(c, a);
+    if (c.D <= 12) return launch_hub_reg<12, PT, CK>(c, a);
+    if (c.D <= 16) return launch_hub_reg<16, PT, CK>(c, a);
+    if (c.D <= 24) return launch_hub_reg<24, PT, CK>(c, a);
+    if (c.D <= 32) return launch_hub_reg<32, PT, CK>(c, a);
+    if (c.D <= 40) return launch_hub_reg<40, PT, CK>(c, a);
+    if (c.D <= 52) return launch_hub_reg<52, PT, CK>(c, a);
+    if (c.D <= HUB_MAXD) return launch_hub_reg<HUB_MAXD, PT, CK>(c, a);
+  }
   const size_t lds = (size_t)(c.K + 1) * c.Ds * sizeof(double);
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hub_lds<PT, CK>, 256, lds) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  const int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu * 2);
-  hipLaunchKernelGGL((k_hub_lds<PT, CK>), dim3(grid), dim3(256), lds, c.stream, a);
+  if (c.hub_lds_grid == 0) {  // (queried once per context, before any graph capture)
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hub_lds<PT, CK>, 256, lds) != hipSuccess ||
+        per_cu < 1) {
+      (void)hipGetLastError();
+      per_cu = 1;
+    }
+    c.hub_lds_grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu * 2);
+  }
+  hipLaunchKernelGGL((k_hub_lds<PT, CK>), dim3(c.hub_lds_grid), dim3(256), lds, c.stream, a);
   return hipGetLastError();
 }
 
@@ -2172,19 +2222,16 @@ static hipError_t launch_hub_kind(const Ctx& c, const JoinArgs& a) {
 
 template <int DK, typename H>
 static hipError_t launch_hub_mfma_t(const Ctx& c, const JoinArgs& a) {
+  const int per_cu = (a.K + 1 <= 32) ? occupancy<k_hub_mfma<DK, H, 2>, 256>()
+                     : ((a.K + 1 <= 48) ? occupancy<k_hub_mfma<DK, H, 3>, 256>() : occupancy<k_hub_mfma<DK, H, 5>, 256>());
   auto kern = (a.K + 1 <= 32) ? k_hub_mfma<DK, H, 2> : ((a.K + 1 <= 48) ? k_hub_mfma<DK, H, 3> : k_hub_mfma<DK, H, 5>);
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) {
-    (void)hipGetLastError();
-    per_cu = 1;
-  }
   const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu * 4);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, (const H*)c.Ph, (const H*)c.Lh, c.seg32);
   return hipGetLastError();
 }
 
 static hipError_t launch_hub_mfma(const Ctx& c, const JoinArgs& a) {
-  if (c.precision == 1) return c.dk == 32 ? launch_hub_mfma_t<32, __bf16>(c, a) : launch_hub_mfma_t<64, __bf16>(c, a);
+  if (c.precision != 2) return c.dk == 32 ? launch_hub_mfma_t<32, __bf16>(c, a) : launch_hub_mfma_t<64, __bf16>(c, a);
   return c.dk == 32 ? launch_hub_mfma_t<32, _Float16>(c, a) : launch_hub_mfma_t<64, _Float16>(c, a);
 }
 
@@ -2195,7 +2242,7 @@ static void launch_prep_t(const Ctx& c, unsigned long long* maxbits) {
 }
 
 hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits) {
-  if (c.precision == 1) {
+  if (c.precision != 2) {
     if (c.dtype == 0) launch_prep_t<float, __bf16>(c, maxbits); else launch_prep_t<double, __bf16>(c, maxbits);
   } else {
     if (c.dtype == 0) launch_prep_t<float, _Float16>(c, maxbits); else launch_prep_t<double, _Float16>(c, maxbits);

@@ -49,7 +49,7 @@ def test_params_struct_layout_matches_header():
 
 @pytest.mark.parametrize("kw", [dict(stop_rule=3), dict(stop_rule=-1), dict(comparator=4), dict(comparator=-1),
                                 dict(stop_rule=2, delta=-0.5), dict(stop_rule=2, delta=float("nan")),
-                                dict(stop_rule=2, delta=float("inf")), dict(precision=3)])
+                                dict(stop_rule=2, delta=float("inf")), dict(precision=4)])
 def test_bad_params_are_argument_errors_before_device_work(kw):
     P = np.full((10, 4), 0.25, dtype=np.float32)
     idx = np.empty((10, 3), dtype=np.int32)

@@ -539,6 +539,59 @@ def test_batched_mix_vs_oracle(prec):
         _compare_instance(g, P, d, K, s, f"instance n={P.shape[0]} d={d} K={K}")
 
 
+# Rounds replayed from captured graphs (the default) against the same rounds
+# enqueued kernel by kernel: every instance identical, bit for bit.  Groups
+# of this mix stop at different rounds, so the graphs are captured again
+# while the call runs.
+@pytest.mark.parametrize("prec", [knnd.KNND_PREC_FP64, knnd.KNND_PREC_MIXED_BF16], ids=["plain", "bf16"])
+def test_batched_graph_replay_matches_eager(prec):
+    inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX]
+    say(f"batched: graph replay vs eager, precision {prec}")
+    st1, a = knnd.knnd_build_batched(inst, knnd.default_params(precision=prec))
+    st2, b = knnd.knnd_build_batched(inst, knnd.default_params(precision=prec, flags=knnd.KNND_FLAG_NO_GRAPH))
+    assert st1 == st2 == knnd.KNND_OK
+    assert max(g["rounds"] for g in a) >= 4
+    for x, y in zip(a, b):
+        assert (x["status"], x["rounds"]) == (y["status"], y["rounds"])
+        for sx, sy in zip(x["stats"], y["stats"]):
+            for f in ("updates", "fcr_hits", "evals_alg", "evals_performed", "rescues"):
+                assert sx[f] == sy[f], f
+        assert np.array_equal(x["idx"], y["idx"])
+        assert np.array_equal(bits(x["kl"]), bits(y["kl"]))
+
+
+# The autotuner: under KNND_PREC_AUTO each group's join runs the exact or the
+# BF16 mixed form, whichever its first-round trials measured faster (the
+# exact form on either hub kernel); every choice gives the oracle's result.
+# Its choices are appended to the file KNND_TUNE_CACHE names.
+def test_batched_autotuned_vs_oracle(tmp_path, monkeypatch):
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("KNND_TUNE_CACHE", str(path))
+    inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX]
+    say("batched: autotuned precision and hub kernel")
+    st, outs = knnd.knnd_build_batched(inst, knnd.default_params(precision=knnd.KNND_PREC_AUTO))
+    assert st == knnd.KNND_OK
+    for (P, d, K, s), g in zip(inst, outs):
+        _compare_instance(g, P, d, K, s, f"instance n={P.shape[0]} d={d} K={K}")
+    lines = [ln for ln in path.read_text().splitlines() if "prec=3" in ln and "batched=1" in ln]
+    assert lines, "no tuned shape recorded"
+    for ln in lines:
+        key, choice, trials = (x.strip() for x in ln.split("|"))
+        mixed, lds = (int(v) for v in choice.split())
+        assert len(trials.split()) >= 2 and not (mixed and lds)
+    # a second call reuses the cached choices (no trials) and gives the same result
+    st2, again = knnd.knnd_build_batched(inst, knnd.default_params(precision=knnd.KNND_PREC_AUTO))
+    assert st2 == st
+    for a, b in zip(outs, again):
+        assert np.array_equal(a["idx"], b["idx"]) and np.array_equal(bits(a["kl"]), bits(b["kl"]))
+
+
+@pytest.mark.parametrize("n,d,K,ds,seed", [(3001, 20, 30, 5, 7), (20000, 10, 20, 6, 8)])
+def test_single_autotuned_vs_oracle(n, d, K, ds, seed):
+    P = synth.dirichlet(ds, n, d, np.float32)
+    full_compare(P, d, K, seed, precision=knnd.KNND_PREC_AUTO)
+
+
 # Other stop rules (Section 1.2, Table 1, and Section 1.3, item (b)): same rounds, another
 # stopping round; each instance stops on its own n.
 @pytest.mark.parametrize("rule,delta", [(knnd.KNND_STOP_FIXED_POINT, 0.0), (knnd.KNND_STOP_DELTA, 0.002)],
