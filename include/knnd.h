@@ -391,6 +391,15 @@ int knnd_ctx_round_share(knnd_ctx* c, int64_t first, int64_t count, knnd_round_s
 /* Copy the current lists out: idx [n][K] int32, kl optional [n][K] FP64 (kind). */
 int knnd_ctx_get_graph(knnd_ctx* c, int32_t* idx, double* kl, int32_t on_device);
 
+/* The co-friend lists (reverse neighbours, Section 3.1) of the current
+   lists, as the next round builds them: the points x with y in F(x) are
+   col[rowptr[y] .. rowptr[y+1]), each segment in increasing order.  rowptr
+   [n+1] int64 and col [n*K] int32 are host memory (on_device must be 0, else
+   KNND_ERR_UNSUPPORTED).  The join itself leaves the order inside a segment
+   free (nothing it computes depends on it); the segments are sorted on the
+   host here.  Synchronises the context's stream. */
+int knnd_ctx_get_cofriends(knnd_ctx* c, int64_t* rowptr, int32_t* col, int32_t on_device);
+
 /* Copy the feature table out: L [n][d+1] FP64 (kind): log x for the KL
    comparators, sqrt x for Hellinger, x for Euclidean. */
 int knnd_ctx_get_log_table(knnd_ctx* c, double* L, int32_t on_device);

@@ -38,7 +38,7 @@ EXPORTED = [
     "knnd_build_ex", "knnd_ctx_create", "knnd_ctx_init_graph", "knnd_ctx_set_graph",
     "knnd_ctx_round", "knnd_ctx_round_share", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
     "knnd_ctx_destroy", "knnd_build_batched", "knnd_exact_knn", "knnd_release_cache",
-    "knnd_build_noalloc",
+    "knnd_build_noalloc", "knnd_ctx_get_cofriends",
 ]
 KNND_NOALLOC_MAX_BYTES = 256 << 20
 
@@ -109,6 +109,7 @@ def lib():
         "knnd_ctx_round_share": (ctypes.c_int, [vp, i64, i64, P(knnd_round_stats)]),
         "knnd_ctx_get_graph": (ctypes.c_int, [vp, vp, vp, i32]),
         "knnd_ctx_get_log_table": (ctypes.c_int, [vp, vp, i32]),
+        "knnd_ctx_get_cofriends": (ctypes.c_int, [vp, vp, vp, i32]),
         "knnd_ctx_rounds": (ctypes.c_int, [vp]),
         "knnd_ctx_destroy": (ctypes.c_int, [vp]),
         "knnd_build_batched": (ctypes.c_int, [P(knnd_instance), i32, P(knnd_params), i32, vp]),
@@ -388,6 +389,17 @@ class Context:
         if st != KNND_OK:
             raise KnndError(st, "knnd_ctx_get_graph")
         return idx, kl
+
+    def cofriends(self):
+        """(rowptr [n+1] int64, col [nK] int32): the co-friend lists of the
+        current graph, each segment in increasing order (host arrays)."""
+        n = self.points.shape[0]
+        rowptr = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(n * self.K, dtype=np.int32)
+        st = lib().knnd_ctx_get_cofriends(self.h, rowptr.ctypes.data, col.ctypes.data, 0)
+        if st < 0:
+            raise KnndError(st, "knnd_ctx_get_cofriends")
+        return rowptr, col
 
     def log_table(self):
         L = _empty(self.points, (self.n, self.d + 1), np.float64)

@@ -7,6 +7,7 @@
 // synchronises once, to read the counters the stop test needs (Section 3.3).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1248,6 +1249,20 @@ int knnd_ctx_round_share(knnd_ctx* h, int64_t first, int64_t count, knnd_round_s
 int knnd_ctx_get_graph(knnd_ctx* h, int32_t* idx, double* kl, int32_t on_device) {
   if (!h || !idx || !h->c.have_graph) return KNND_ERR_ARG;
   return get_graph(h->c, idx, kl, on_device);
+}
+
+int knnd_ctx_get_cofriends(knnd_ctx* h, int64_t* rowptr, int32_t* col, int32_t on_device) {
+  if (!h || !rowptr || !col || !h->c.have_graph) return KNND_ERR_ARG;
+  if (on_device) return KNND_ERR_UNSUPPORTED;
+  Ctx& c = h->c;
+  const size_t nK = (size_t)c.n * c.K;
+  KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
+  KNND_HIP(hipMemcpyAsync(rowptr, c.rowptr, ((size_t)c.n + 1) * 8, hipMemcpyDeviceToHost, c.stream));
+  KNND_HIP(hipMemcpyAsync(col, c.col, nK * 4, hipMemcpyDeviceToHost, c.stream));
+  KNND_HIP(hipStreamSynchronize(c.stream));
+  for (size_t e = 0; e < nK; ++e) col[e] = (int32_t)((uint32_t)col[e] & knnd::IDMASK_HOST);
+  for (int64_t y = 0; y < c.n; ++y) std::sort(col + rowptr[y], col + rowptr[y + 1]);
+  return KNND_OK;
 }
 
 int knnd_ctx_get_log_table(knnd_ctx* h, double* L, int32_t on_device) {

@@ -1013,6 +1013,7 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
   const int lane = lane_id();
   const int col = lane & 15, kb = lane >> 4;
   const int64_t nwaves = (int64_t)gridDim.x * 4;
+  __shared__ int s_rows[4][WAVE];  // share rounds: packed row numbers, per wave
   int64_t my_perf = 0;
   for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < a.n; v += nwaves) {
     if (inactive(a, v)) continue;  // whole wave
@@ -1040,80 +1041,104 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
         blo[ct][s] = fl;
       }
     }
-    for (int k0 = 0; k0 < nR; k0 += 16) {
-      // metadata of row k0 + col (the four lanes sharing col compute the same)
-      const int row = k0 + col;
-      bool on = row < nR;
-      const uint32_t fsp = (uint32_t)__shfl((int)fv, (row >= cv && row < nR) ? row - cv : 0, WAVE);
-      int64_t r = 0, b0 = -1, b1 = -1;  // b0 < 0: no row to write (out of range or not owned)
-      uint32_t rnew = 0;
-      int excl = -1;
-      if (on) {
-        if (row < cv) {
-          const uint32_t e = a.col[rp + row];
-          r = e & IDMASK;
-          rnew = e & NEWBIT;
-          b0 = (r * K + a.colslot[rp + row]) * K;  // FF
-        } else {
-          const int sp = row - cv;
-          r = fsp & IDMASK;
-          rnew = fsp & NEWBIT;
-          excl = sp;
-          b0 = a.nKK + (v * K + sp) * a.Ks;  // FC
-          b1 = a.di_off + v * K + sp;        // DI
-        }
-        if (!owned(a, r)) {
-          on = false;
-          b0 = b1 = -1;
-        }
+    // A round over one share of the receivers packs the rows whose receiver
+    // it updates into dense tiles, 64 rows at a time; otherwise row k is
+    // receiver row k.
+    const bool share = a.own0 > 0 || a.own1 < a.n;
+    for (int kc = 0; kc < nR; kc += share ? WAVE : nR) {
+      int nrow = nR;
+      if (share) {
+        const int rr = kc + lane;
+        const uint32_t fq = (uint32_t)__shfl((int)fv, (rr >= cv && rr < nR) ? rr - cv : 0, WAVE);
+        bool keep = false;
+        if (rr < nR) keep = owned(a, rr < cv ? (int64_t)(a.col[rp + rr] & IDMASK) : (int64_t)(fq & IDMASK));
+        const uint64_t km = __ballot(keep);
+        if (keep) s_rows[threadIdx.x >> 6][rank_in(km)] = rr;
+        nrow = __popcll(km);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      const bool want = on && (!a.skip || rnew != 0 || cand_new != 0);
-      if (__ballot(want) == 0) continue;
-      V8 ahi[KS], alo[KS];
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        V8 fh = {}, fl = {};
+      for (int k0 = 0; k0 < nrow; k0 += 16) {
+        // metadata of row k0 + col (the four lanes sharing col compute the same)
+        const int row = share ? (k0 + col < nrow ? s_rows[threadIdx.x >> 6][k0 + col] : nR) : k0 + col;
+        bool on = row < nR;
+        const uint32_t fsp = (uint32_t)__shfl((int)fv, (row >= cv && row < nR) ? row - cv : 0, WAVE);
+        int64_t r = 0, b0 = -1, b1 = -1;  // b0 < 0: no row to write (out of range or not owned)
+        uint32_t rnew = 0;
+        int excl = -1;
         if (on) {
-          fh = *reinterpret_cast<const V8*>(Ph + r * 2 * DK + s * 32 + kb * 8);
-          fl = *reinterpret_cast<const V8*>(Ph + r * 2 * DK + DK + s * 32 + kb * 8);
+          if (row < cv) {
+            const uint32_t e = a.col[rp + row];
+            r = e & IDMASK;
+            rnew = e & NEWBIT;
+            b0 = (r * K + a.colslot[rp + row]) * K;  // FF
+          } else {
+            const int sp = row - cv;
+            r = fsp & IDMASK;
+            rnew = fsp & NEWBIT;
+            excl = sp;
+            b0 = a.nKK + (v * K + sp) * a.Ks;  // FC
+            b1 = a.di_off + v * K + sp;        // DI
+          }
+          if (!owned(a, r)) {
+            on = false;
+            b0 = b1 = -1;
+          }
         }
-        ahi[s] = fh;
-        alo[s] = fl;
-      }
-#pragma unroll
-      for (int ct = 0; ct < MAXCT; ++ct) {
-        if (ct >= nct) break;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const bool want = on && (!a.skip || rnew != 0 || cand_new != 0);
+        if (__ballot(want) == 0) continue;
+        V8 ahi[KS], alo[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          acc = Mfma<H>::mma(alo[s], bhi[ct][s], acc);
-          acc = Mfma<H>::mma(ahi[s], blo[ct][s], acc);
-          acc = Mfma<H>::mma(ahi[s], bhi[ct][s], acc);
+          V8 fh = {}, fl = {};
+          if (on) {
+            fh = *reinterpret_cast<const V8*>(Ph + r * 2 * DK + s * 32 + kb * 8);
+            fl = *reinterpret_cast<const V8*>(Ph + r * 2 * DK + DK + s * 32 + kb * 8);
+          }
+          ahi[s] = fh;
+          alo[s] = fl;
         }
-        const int ci = ct * 16 + col;
-        const bool cnew = ci < K && ((cand_new >> ci) & 1);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int src = 4 * kb + i;  // row k0 + src lives in lanes src, src+16, ...
-          const int64_t rb0 = (int64_t)shfl_u64((uint64_t)b0, src);
-          const int64_t rb1 = (int64_t)shfl_u64((uint64_t)b1, src);
-          const int rex = __shfl(excl, src, WAVE);
-          const uint32_t rnw = shfl_u32(rnew, src);
-          const bool ron = rb0 >= 0;  // in range and owned
-          bool need;
-          int64_t pos;
-          if (ci < K) {
-            need = ron && ci != rex && (!a.skip || rnw || cnew);
-            pos = rb0 + ci;
-          } else {
-            need = ron && ci == K && rb1 >= 0 && (!a.skip || rnw);
-            pos = rb1;
+        for (int ct = 0; ct < MAXCT; ++ct) {
+          if (ct >= nct) break;
+          f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < KS; ++s) {
+            acc = Mfma<H>::mma(alo[s], bhi[ct][s], acc);
+            acc = Mfma<H>::mma(ahi[s], blo[ct][s], acc);
+            acc = Mfma<H>::mma(ahi[s], bhi[ct][s], acc);
           }
-          if (need) {
-            seg32[pos] = acc[i];
-            ++my_perf;
+          const int ci = ct * 16 + col;
+          const bool cnew = ci < K && ((cand_new >> ci) & 1);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int src = 4 * kb + i;  // row k0 + src lives in lanes src, src+16, ...
+            const int64_t rb0 = (int64_t)shfl_u64((uint64_t)b0, src);
+            const int64_t rb1 = (int64_t)shfl_u64((uint64_t)b1, src);
+            const int rex = __shfl(excl, src, WAVE);
+            const uint32_t rnw = shfl_u32(rnew, src);
+            const bool ron = rb0 >= 0;  // in range and owned
+            bool need;
+            int64_t pos;
+            if (ci < K) {
+              need = ron && ci != rex && (!a.skip || rnw || cnew);
+              pos = rb0 + ci;
+            } else {
+              need = ron && ci == K && rb1 >= 0 && (!a.skip || rnw);
+              pos = rb1;
+            }
+            if (need) {
+              seg32[pos] = acc[i];
+              ++my_perf;
+            }
           }
         }
+      }
+      if (share) {  // (s_rows is rewritten by the next 64 rows)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
     hub_count(a, v, my_perf - pf0);

@@ -271,6 +271,29 @@ def test_stop_rule_round_cap_warns():
     assert g["status"] == knnd.KNND_WARN_MAX_ROUNDS and g["rounds"] == 4
 
 
+# Reverse neighbours (Section 3.1): the co-friend lists a round builds from
+# its snapshot, against their construction from the lists themselves; two
+# builds agree bit for bit (rowptr is a count and a scan, and the interface
+# sorts each segment; the join leaves the order inside a segment free).
+@pytest.mark.parametrize("flags", [0, knnd.KNND_FLAG_ATOMIC_CSR], ids=["bucketed", "atomic"])
+def test_cofriend_lists(flags):
+    P = synth.dirichlet(3, 20000, 6, np.float32)
+    with knnd.Context(P, 6, 12, 5, knnd.default_params(flags=flags)) as c:
+        c.init_graph()
+        c.round()
+        idx, _ = c.get_graph()
+        rp1, col1 = c.cofriends()
+        rp2, col2 = c.cofriends()
+    idx = np.asarray(idx)
+    n, K = idx.shape
+    src = np.repeat(np.arange(n), K)
+    deg = np.bincount(idx.ravel(), minlength=n)
+    assert np.array_equal(rp1, np.concatenate([[0], np.cumsum(deg)]))
+    order = np.lexsort((src, idx.ravel()))  # by target, then source
+    assert np.array_equal(col1, src[order].astype(np.int32))
+    assert np.array_equal(rp1, rp2) and np.array_equal(col1, col2)
+
+
 @pytest.mark.parametrize("n,d,K,seed", [(20000, 10, 20, 8), (3001, 20, 30, 7)])
 def test_atomic_reverse_neighbour_build(n, d, K, seed):
     # the per-edge atomic CSR build (used above 2^25 points) gives the same descent
@@ -659,7 +682,7 @@ def test_paper_tables_statistics_on_gpu():
     from paper_2202_00517_amd import paper_tables as pt
     t3 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_table3.json")))["rows"]
     t4 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_table4.json")))
-    for i, p in enumerate(t3[:4]):  # n = 2e4 and 2e5, 10 coordinates
+    for i, p in enumerate(t3):  # n = 2e4, 2e5 and 2e6, 10 coordinates
         r = pt.run_row(p["n"], p["coordinates"], p["K"], 3100 + i, 3200 + i, torch, knnd.KNND_PREC_MIXED_BF16)
         say(f"table 3 row {i}: {r}")
         assert r["rounds"] <= p["round_bound"] and abs(r["rounds"] - p["rounds"]) <= 2
