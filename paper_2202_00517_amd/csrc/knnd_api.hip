@@ -509,8 +509,11 @@ int init_graph(Ctx& c, knnd_round_stats* st) {
 
 // ---------------------------------------------------------------------------
 // Autotuner of the join's schedule.  Candidates: the exact hub form with the
-// register-staged hub kernel (k_hub_reg) or the LDS-staged one (k_hub_lds),
-// and, under KNND_PREC_AUTO, the BF16 mixed form.  Every candidate computes
+// register-staged hub kernel (k_hub_reg, one hub per wave; for small K also
+// two or four hubs per wave, k_hub_reg_sub) or the LDS-staged one
+// (k_hub_lds), and, under KNND_PREC_AUTO, the BF16 mixed form; then, with
+// the fastest of those, the smallest receiver classes one wave per receiver
+// (k_recv_wave) for none, one or two classes.  Every candidate computes
 // the same lists, keys and counts, so a choice changes only speed: the join
 // of the coming round (binning, hub kernel, receiver pass) is run once per
 // candidate from the round-start snapshot, timed with HIP events, and the
@@ -518,11 +521,14 @@ int init_graph(Ctx& c, knnd_round_stats* st) {
 // by workload shape (K, coordinates, size class, single or batched,
 // comparator, precision mode) for the rest of the process and, when
 // KNND_TUNE_CACHE names a file, in that file: one line per shape,
-// "<shape> | <mixed> <hub_lds> | <ms of each candidate>".
+// "<shape> | <mixed> <hub_lds> <hubs per wave> <wave receivers> | <ms of
+// each candidate>".
 // ---------------------------------------------------------------------------
 struct Sched {
   bool mixed;
   bool hub_lds;
+  int hpw;    // hubs per wave of the register hub kernel
+  int rwave;  // smallest receiver classes one wave per receiver (0, 1 or 2 classes)
 };
 
 std::mutex g_tune_mu;
@@ -539,11 +545,13 @@ void tune_load_locked() {
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
     const char* bar = std::strchr(line, '|');
-    int m = 0, h = 0;
-    if (!bar || std::sscanf(bar + 1, "%d %d", &m, &h) != 2) continue;
+    int m = 0, h = 0, w = 1, rw = 0;
+    if (!bar || std::sscanf(bar + 1, "%d %d %d %d", &m, &h, &w, &rw) != 4 || (w != 1 && w != 2 && w != 4) ||
+        rw < 0 || rw > 2)
+      continue;
     std::string key(line, (size_t)(bar - line));
     while (!key.empty() && key.back() == ' ') key.pop_back();
-    g_tune[key] = Sched{m != 0, h != 0};
+    g_tune[key] = Sched{m != 0, h != 0, w, rw};
   }
   std::fclose(f);
 }
@@ -560,24 +568,48 @@ std::string tune_key(const Ctx& c, bool group) {
 void apply_sched(Ctx& c, Sched s) {
   c.mixed = s.mixed;
   c.hub_lds = s.hub_lds;
+  c.hub_hpw = s.hpw;
+  c.recv_wave = s.rwave;
+}
+
+const char* sched_name(const Sched& s, char* buf, size_t len) {
+  std::snprintf(buf, len, "%s%s%s%s", s.mixed ? "mixed" : "exact",
+                s.hub_lds ? "/lds" : (s.hpw == 4 ? "/hpw4" : (s.hpw == 2 ? "/hpw2" : "")),
+                s.rwave == 2 ? "/wave2" : (s.rwave == 1 ? "/wave1" : ""), "");
+  return buf;
 }
 
 // Choose the join's schedule for context c; its reverse-neighbour lists for
 // the coming round must be built.  group: a batched group (its per-instance
 // and per-point counters are cleared between trials too).
 int tune_join(Ctx& c, bool group) {
-  Sched cand[3];
+  // stage 1: the form and the hub kernel; stage 2: the smallest receiver
+  // classes one wave per receiver or not, with the stage-1 choice
+  Sched cand[8];
   int nc = 0;
   const bool lds_fits = (size_t)(c.K + 1) * c.Ds * sizeof(double) <= 64 * 1024;
   if (c.plain_ok && (c.auto_prec || !c.mixed)) {
-    cand[nc++] = Sched{false, false};
-    if (lds_fits) cand[nc++] = Sched{false, true};
+    cand[nc++] = Sched{false, false, 1, 0};
+    if (c.D <= 24 && c.K <= 32) cand[nc++] = Sched{false, false, 2, 0};  // (the register kernel's row bound)
+    if (c.D <= 24 && c.K <= 16) cand[nc++] = Sched{false, false, 4, 0};
+    if (lds_fits) cand[nc++] = Sched{false, true, 1, 0};
   }
-  if (c.mixed_ok && (c.auto_prec || c.mixed)) cand[nc++] = Sched{true, false};
+  if (c.mixed_ok && (c.auto_prec || c.mixed)) cand[nc++] = Sched{true, false, 1, 0};
   if (nc == 0 || !c.evj0) return KNND_OK;
-  if (nc == 1) {
-    apply_sched(c, cand[0]);
-    return KNND_OK;
+  const bool waves = c.use_hub && c.K < 64;  // (stage 2 applies, to the exact form)
+  // KNND_TUNE_FORCE="<mixed> <hub_lds> <hubs per wave> <wave receivers>"
+  // fixes the schedule when it is a candidate (no trials, nothing cached)
+  if (const char* force = std::getenv("KNND_TUNE_FORCE")) {
+    int m = 0, h = 0, w = 1, rw = 0;
+    if (std::sscanf(force, "%d %d %d %d", &m, &h, &w, &rw) == 4 && rw >= 0 && rw <= 2 &&
+        (rw == 0 || (waves && m == 0)))
+      for (int i = 0; i < nc; ++i)
+        if (cand[i].mixed == (m != 0) && cand[i].hub_lds == (h != 0) && cand[i].hpw == w) {
+          Sched f = cand[i];
+          f.rwave = rw;
+          apply_sched(c, f);
+          return KNND_OK;
+        }
   }
   const std::string key = tune_key(c, group);
   {
@@ -589,10 +621,11 @@ int tune_join(Ctx& c, bool group) {
       return KNND_OK;
     }
   }
-  float ms[3] = {0.f, 0.f, 0.f};
-  int best = 0;
-  for (int i = 0; i < nc; ++i) {
-    apply_sched(c, cand[i]);
+  float ms[8] = {};
+  Sched tried[8];
+  int nt = 0;
+  auto trial = [&](Sched sc, float* out) -> int {
+    apply_sched(c, sc);
     KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
     if (group) {
       KNND_HIP(knnd::launch_zero_i64(c.istats, (int64_t)c.nb * knnd::STAT_N, c.stream));
@@ -604,18 +637,37 @@ int tune_join(Ctx& c, bool group) {
     KNND_HIP(knnd::launch_join_recv(c, c.dstats));
     KNND_HIP(hipEventRecord(c.evj1, c.stream));
     KNND_HIP(hipStreamSynchronize(c.stream));
-    KNND_HIP(hipEventElapsedTime(&ms[i], c.evj0, c.evj1));
-    if (ms[i] < ms[best]) best = i;
+    KNND_HIP(hipEventElapsedTime(out, c.evj0, c.evj1));
+    return KNND_OK;
+  };
+  int best = 0;
+  for (int i = 0; i < nc; ++i) {
+    tried[nt] = cand[i];
+    const int st = trial(cand[i], &ms[nt]);
+    if (st != KNND_OK) return st;
+    if (ms[nt] < ms[best]) best = nt;
+    ++nt;
   }
-  apply_sched(c, cand[best]);
+  if (waves && !tried[best].mixed)
+    for (int rw = 1; rw <= 2; ++rw) {
+      Sched sc = tried[best];
+      sc.rwave = rw;
+      tried[nt] = sc;
+      const int st = trial(sc, &ms[nt]);
+      if (st != KNND_OK) return st;
+      if (ms[nt] < ms[best]) best = nt;
+      ++nt;
+    }
+  apply_sched(c, tried[best]);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[key] = cand[best];
+  g_tune[key] = tried[best];
   const char* path = std::getenv("KNND_TUNE_CACHE");
   if (path && *path) {
     if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "%s | %d %d |", key.c_str(), cand[best].mixed ? 1 : 0, cand[best].hub_lds ? 1 : 0);
-      for (int i = 0; i < nc; ++i)
-        std::fprintf(f, " %s%s:%.3f", cand[i].mixed ? "mixed" : "exact", cand[i].hub_lds ? "/lds" : "", ms[i]);
+      const Sched& b = tried[best];
+      std::fprintf(f, "%s | %d %d %d %d |", key.c_str(), b.mixed ? 1 : 0, b.hub_lds ? 1 : 0, b.hpw, b.rwave);
+      char nm[48];
+      for (int i = 0; i < nt; ++i) std::fprintf(f, " %s:%.3f", sched_name(tried[i], nm, sizeof nm), ms[i]);
       std::fprintf(f, "\n");
       std::fclose(f);
     }

@@ -110,6 +110,8 @@ struct Ctx {
   // knnd_api.hip): the exact hub form runs k_hub_lds instead of k_hub_reg
   bool hub_lds = false;
   mutable int hub_lds_grid = 0;  // its grid, fixed on first use
+  int hub_hpw = 1;               // hubs per wave of the register hub kernel (1, 2 or 4; small K)
+  int recv_wave = 0;             // smallest receiver classes one wave per receiver (0: none, 1: 512 slots, 2: and 1024)
   bool auto_prec = false;        // KNND_PREC_AUTO: the tuner picks exact or mixed
   bool tune = false;             // time the candidate schedules on the first round
   bool tuned = false;

@@ -926,6 +926,123 @@ void k_hub_reg(JoinArgs a, const double* __restrict__ L,
   if (threadIdx.x == 0 && pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
 }
 
+// The register form with HPW hubs per wave (HPW = 2 or 4): for small K a
+// hub has few receivers (about 2K), so one hub per wave leaves most lanes
+// idle; here each group of 64/HPW lanes takes its own hub (K <= 64/HPW), one
+// lane per receiver, and reads its hub's candidate rows with vector loads
+// (the lanes of a group read the same row).  Same keys, same slots, same
+// counts as k_hub_reg; which form is faster is left to the tuner.
+template <int MAXD, typename PT, int CK, int HPW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hub_reg_waves_per_eu<MAXD>())))
+void k_hub_reg_sub(JoinArgs a, const double* __restrict__ L, const PT* __restrict__ P,
+                   const double* __restrict__ Pd) {
+  constexpr int LG = WAVE / HPW;  // lanes per hub
+  constexpr int CH = 16;          // candidates per LDS tile
+  __shared__ double s_keys[4][WAVE][CH + 1];
+  __shared__ int64_t s_b0[4][WAVE];
+  __shared__ uint64_t s_need[4][WAVE];
+  const int K = a.K, D = a.D, Dp = a.Dp;
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const int grp = lane / LG, sub = lane - grp * LG;
+  const uint64_t gmask = (LG == 64 ? ~0ull : ((1ull << LG) - 1)) << (grp * LG);
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  int64_t my_perf = 0;
+  for (int64_t v0 = ((int64_t)blockIdx.x * 4 + wv) * HPW; v0 < a.n; v0 += nwaves * HPW) {
+    const int64_t v = v0 + grp;
+    const bool hv = v < a.n && !inactive(a, v);
+    const int64_t pf0 = my_perf;
+    const int64_t rp = hv ? a.rowptr[v] : 0;
+    const int cv = hv ? (int)(a.rowptr[v + 1] - rp) : 0;
+    const uint32_t fv = (hv && sub < K) ? a.F[v * a.Ks + sub] : 0u;  // lane sub of the group holds F(v)[sub]
+    const uint64_t cand_new = (__ballot((fv & NEWBIT) != 0) & gmask) >> (grp * LG);
+    const int nR = hv ? cv + K : 0;
+    for (int k0 = 0; __ballot(k0 < nR) != 0; k0 += LG) {
+      const int k = k0 + sub;
+      const bool in = k < nR;
+      const uint32_t fsp = (uint32_t)__shfl((int)fv, grp * LG + ((k >= cv && k < nR) ? k - cv : 0), WAVE);
+      int64_t r = 0, b0 = 0, b1 = -1;
+      uint32_t rnew = 0;
+      int excl = -1;
+      if (in) {
+        if (k < cv) {
+          const uint32_t e = a.col[rp + k];
+          r = e & IDMASK;
+          rnew = e & NEWBIT;
+          b0 = (r * K + a.colslot[rp + k]) * K;  // FF
+        } else {
+          const int sp = k - cv;
+          r = fsp & IDMASK;
+          rnew = fsp & NEWBIT;
+          excl = sp;
+          b0 = a.nKK + (v * K + sp) * a.Ks;  // FC
+          b1 = a.di_off + v * K + sp;        // DI
+        }
+      }
+      const bool on = in && owned(a, r);
+      uint64_t need = 0;
+      if (on) {
+        const uint64_t all = K >= 64 ? ~0ull : ((1ull << K) - 1);
+        need = (!a.skip || rnew) ? all : (cand_new & all);
+        if (excl >= 0) need &= ~(1ull << excl);
+      }
+      const bool need_v = on && b1 >= 0 && (!a.skip || rnew);
+      if (__ballot(need != 0 || need_v) == 0) continue;
+      s_b0[wv][lane] = b0;
+      s_need[wv][lane] = need;
+      double pr[MAXD], lr[MAXD];
+      const PT* prow = P + (on ? r : 0) * D;
+      const double* lrow = L + (on ? r : 0) * Dp;
+#pragma unroll
+      for (int i = 0; i < MAXD; ++i) {
+        const double pv = (double)prow[i];
+        const double lv = lrow[i];
+        pr[i] = i < D ? pv : 0.0;
+        lr[i] = i < D ? lv : 0.0;
+      }
+      for (int c0 = 0; c0 < K; c0 += CH) {
+        for (int cj = 0; cj < CH && c0 + cj < K; ++cj) {
+          const int ci = c0 + cj;
+          const bool nd = ((need >> ci) & 1) != 0;
+          if (__ballot(nd) == 0) continue;
+          const uint32_t craw = (uint32_t)__shfl((int)fv, grp * LG + ci, WAVE);
+          const int64_t cidx = nd ? (int64_t)(craw & IDMASK) : 0;
+          s_keys[wv][lane][cj] = hub_fold<MAXD, CK>(pr, lr, Pd + cidx * D, L + cidx * Dp, D);
+          my_perf += nd ? 1 : 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int g = 0; g < WAVE / 4; ++g) {  // 4 receivers x 16 consecutive slots per store
+          const int rl = 4 * g + (lane >> 4);
+          const int cj = lane & 15;
+          const int ci = c0 + cj;
+          if (ci < K && ((s_need[wv][rl] >> ci) & 1)) a.seg[s_b0[wv][rl] + ci] = s_keys[wv][rl][cj];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      if (__ballot(need_v)) {
+        const double key = hub_fold<MAXD, CK>(pr, lr, Pd + (hv ? v : 0) * D, L + (hv ? v : 0) * Dp, D);
+        if (need_v) {
+          a.seg[b1] = key;
+          ++my_perf;
+        }
+      }
+    }
+    if (a.vcnt) {  // keys computed by hub v: the sum over its lane group
+      int64_t d = my_perf - pf0;
+#pragma unroll
+      for (int o = LG / 2; o > 0; o >>= 1) d += (int64_t)shfl_xor_u64((uint64_t)d, o);
+      if (sub == 0 && hv) a.vcnt[v * VC_N + VC_HUBPERF] = (int32_t)d;
+    }
+  }
+  __shared__ int64_t s_red[4];
+  const int64_t pf = block_sum(my_perf, s_red);
+  if (threadIdx.x == 0 && pf) atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)pf);
+}
+
 // ---------------------------------------------------------------------------
 // Mixed precision (a3 on MFMA).  The cross term C(x,c) = sum_i x_i log c_i of
 // a hub's receivers x against its candidates c is a small dense product
@@ -2006,6 +2123,281 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIX ? 5 : 1
 }
 
 // ---------------------------------------------------------------------------
+// a2..a5 for the smallest tables (CAP = 512 or 1024 slots, hub form): one
+// wave per receiver, four independent waves per block and no block barrier.
+// The steps are those of k_recv (exclusion of x and F(x), enumeration of
+// every occurrence with the first insertion counted, listing of candidates
+// reached through a new edge that can beat the round-start K-th key), but
+// the wave keeps its counters in registers and merges its own list: the
+// listed candidates are taken 64 at a time, those that cannot beat the
+// current K-th entry are dropped (compare-to-last, Section 4.2), and the
+// rest are sorted and merged into the list held in registers; in the mixed
+// form a first pass finds Theta, the K-th smallest upper bound, and only the
+// candidates whose lower bound is at most Theta get their canonical FP64 key
+// (a count that does not depend on the order of the list).  The tuner offers
+// this kernel for the exact form only: in the mixed form the cross term of
+// one pair, computed by different hubs in different positions of a matrix
+// tile, was seen to differ in its last bits, so the rescue count (never the
+// result) would depend on which occurrence listed a candidate.  Small
+// receivers (small K) are latency bound; this form keeps more of them in
+// flight per CU.  The tuner picks it or k_recv per group.
+// ---------------------------------------------------------------------------
+template <int CAP>
+constexpr int recv_wave_waves_per_eu() {
+  return CAP <= 512 ? 4 : 3;  // (LDS of four such waves per block: six blocks per CU at 512 slots, three at 1024)
+}
+
+template <int CAP, typename PT, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(recv_wave_waves_per_eu<CAP>())))
+void k_recv_wave(JoinArgs a, const int32_t* __restrict__ lists, const int32_t* __restrict__ counts, int cls) {
+  constexpr bool MIX = MODE == 2;
+  constexpr int U = 4;             // occurrences per lane in flight
+  constexpr int CC = CAP / 2;      // distinct candidates fit (exact table sizing)
+  using KT = typename std::conditional<MIX, float, double>::type;
+  __shared__ __align__(16) uint32_t s_tab[4][CAP];
+  __shared__ uint32_t s_cid[4][CC];
+  __shared__ KT s_ck[4][CC];
+  __shared__ uint32_t s_fx[4][WAVE];
+  __shared__ uint32_t s_col[4][WAVE];
+  __shared__ uint8_t s_csl[4][WAVE];
+  __shared__ double s_xr[MIX ? 4 : 1][MIX ? HUB_MAXD + 16 : 1], s_lr[MIX ? 4 : 1][MIX ? HUB_MAXD + 16 : 1];
+  const int lane = lane_id();
+  const int w = threadIdx.x >> 6;
+  const int K = a.K, D = a.D, Dp = a.Dp;
+  const int64_t n = a.n;
+  const int32_t* list = lists + (int64_t)cls * n;
+  uint32_t* tab = s_tab[w];
+  constexpr uint32_t mask = CAP - 1;
+  const PT* P = reinterpret_cast<const PT*>(a.P);
+  const int nitems = counts[cls];
+  int64_t my_evals = 0, my_upd = 0, my_err = 0, my_resc = 0;
+  auto wsync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  for (int item = blockIdx.x * 4 + w; item < nitems; item += gridDim.x * 4) {
+    const int64_t x = list[item];
+    const int64_t rp = a.rowptr[x];
+    const int64_t c = a.rowptr[x + 1] - rp;
+    const int64_t KK = (int64_t)K * K;
+    const int64_t T = c + KK + c * K;
+    const double tau0 = a.keys[x * K + K - 1];
+    const double Sx = MIX ? a.S[x] : 0.0;
+    // clear the table; stage x's list, its co-friends (when at most 64) and,
+    // mixed, its row and logs
+    {
+      const uint4 e4 = {EMPTY, EMPTY, EMPTY, EMPTY};
+#pragma unroll
+      for (int s0 = 4 * lane; s0 < CAP; s0 += 4 * WAVE) *reinterpret_cast<uint4*>(tab + s0) = e4;
+    }
+    const bool staged = c <= WAVE;
+    if (staged && lane < c) {
+      s_col[w][lane] = a.col[rp + lane];
+      s_csl[w][lane] = a.colslot[rp + lane];
+    }
+    const uint32_t old = lane < K ? a.F[x * a.Ks + lane] : 0u;
+    uint64_t lk = lane < K ? key_bits(a.keys[x * K + lane]) : KEY_SENTINEL;
+    uint32_t li = lane < K ? (old & IDMASK) : IDMASK;
+    if (lane < K) s_fx[w][lane] = old;
+    if (MIX && lane < D) {
+      s_xr[w][lane] = (double)P[x * D + lane];
+      s_lr[w][lane] = a.L[x * Dp + lane];
+    }
+    wsync();
+    if (lane < K)
+      tab_insert(tab, mask, old & IDMASK, EXCLBIT);
+    else if (lane == K)
+      tab_insert(tab, mask, (uint32_t)x, EXCLBIT);
+    wsync();
+    // enumerate every occurrence, U per lane in flight
+    int ncand = 0;
+    int item_evals = 0;
+    for (int64_t t0 = 0; t0 < T; t0 += U * WAVE) {
+      int rg[U], ss[U];
+      uint32_t cw[U], fw[U], sl[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t t = t0 + lane + WAVE * u;
+        const bool inC = t < c;
+        const bool inFF = !inC && t < c + KK;
+        const bool inFC = !inC && !inFF && t < T;
+        rg[u] = inC ? 1 : (inFF ? 2 : (inFC ? 3 : 0));
+        const int64_t uu = inFF ? t - c : t - (c + KK);
+        const int64_t q = uu / K;
+        ss[u] = (int)(uu - q * K);
+        const int64_t qi = inC ? t : (inFC ? q : -1);
+        if (staged) {
+          const int i = qi < 0 ? 0 : (int)qi;
+          cw[u] = s_col[w][i];
+          sl[u] = s_csl[w][i];
+        } else {
+          const int64_t g = qi < 0 ? 0 : rp + qi;
+          cw[u] = a.col[g];
+          sl[u] = (uint32_t)a.colslot[g];
+        }
+        fw[u] = s_fx[w][inFF ? (int)q : 0];
+      }
+      uint32_t zr[U];
+      KT kr[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t srcw = rg[u] == 2 ? fw[u] : cw[u];
+        const int64_t v = srcw & IDMASK;
+        const int64_t t = t0 + lane + WAVE * u;
+        zr[u] = a.F[rg[u] >= 2 ? v * a.Ks + ss[u] : 0];
+        const int64_t kp = rg[u] == 1   ? a.di_off + v * K + sl[u]
+                           : rg[u] == 2 ? x * KK + (t - c)
+                           : rg[u] == 3 ? a.nKK + (v * K + sl[u]) * a.Ks + ss[u]
+                                        : 0;
+        kr[u] = MIX ? (KT)a.seg32[kp] : (KT)a.seg[kp];
+      }
+      uint32_t z[U], nw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t srcw = rg[u] == 2 ? fw[u] : cw[u];
+        z[u] = rg[u] == 1 ? (srcw & IDMASK) : (zr[u] & IDMASK);
+        nw[u] = (rg[u] == 1 ? srcw : (srcw | zr[u])) & NEWBIT;
+      }
+      uint32_t old0[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        old0[u] = 0;
+        if (rg[u] != 0) old0[u] = atomicCAS(&tab[tab_slot(z[u], mask)], EMPTY, z[u] | (a.skip ? nw[u] : NEWBIT));
+      }
+      uint32_t appm = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (rg[u] != 0) {
+          const int r = tab_finish(tab, mask, z[u], a.skip ? nw[u] : NEWBIT, tab_slot(z[u], mask), old0[u]);
+          item_evals += r & 1;
+          if (r & 2) {
+            const double kv = MIX ? Sx - (double)kr[u] : (double)kr[u];
+            if (MIX ? kv - mix_eps(a, Sx, kv) <= tau0 : kv <= tau0) appm |= 1u << u;
+          }
+        }
+      }
+      // list them (positions from a prefix count across the wave)
+      const int napp = __popc(appm);
+      const int pre = wave_exscan(napp);
+      int at = ncand + pre;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!((appm >> u) & 1)) continue;
+        if (at < CC) {
+          s_cid[w][at] = z[u];
+          s_ck[w][at] = kr[u];
+        } else {
+          ++my_err;  // (cannot happen: distinct candidates fit the table at load 1/2)
+        }
+        ++at;
+      }
+      ncand += __shfl(pre + napp, WAVE - 1, WAVE);
+    }
+    if (ncand > CC) ncand = CC;
+    wsync();
+    // Mixed form: Theta = the K-th smallest upper bound among the old list
+    // (exact keys) and the listed candidates (k~ + eps), by the same merge;
+    // a candidate whose lower bound k~ - eps exceeds Theta has K entries
+    // strictly better than it, every other one gets its canonical key.
+    uint64_t theta = KEY_SENTINEL;
+    if (MIX && ncand > 0) {
+      uint64_t tk = lk;
+      uint32_t ti = li;
+      for (int b0 = 0; b0 < ncand; b0 += WAVE) {
+        const int i = b0 + lane;
+        uint64_t ub = KEY_SENTINEL;
+        uint32_t zz = IDMASK;
+        if (i < ncand) {
+          const double kt = Sx - (double)s_ck[w][i];
+          ub = key_bits(kt + mix_eps(a, Sx, kt));
+          zz = s_cid[w][i] | NEWBIT;
+        }
+        if (__ballot(i < ncand && ke_less(ub, zz, shfl_u64(tk, K - 1), shfl_u32(ti, K - 1))) == 0) continue;
+        wave_sort(ub, zz);
+        wave_merge(tk, ti, ub, zz);
+      }
+      theta = shfl_u64(tk, K - 1);
+    }
+    // merge: 64 listed candidates at a time into the list in registers
+    int resc = 0;
+    for (int b0 = 0; b0 < ncand; b0 += WAVE) {
+      const int i = b0 + lane;
+      const bool valid = i < ncand;
+      const uint64_t kk = shfl_u64(lk, K - 1);
+      const uint32_t ki = shfl_u32(li, K - 1);
+      uint64_t kb = KEY_SENTINEL;
+      uint32_t zz = IDMASK;
+      bool surv = false;
+      if (valid) {
+        zz = s_cid[w][i];
+        if (MIX) {
+          const double kt = Sx - (double)s_ck[w][i];
+          if (key_bits(kt - mix_eps(a, Sx, kt)) <= theta) {
+            kb = key_bits(canonical_key_lds(s_xr[w], s_lr[w], a.L + (int64_t)zz * Dp, D));
+            ++resc;
+            surv = ke_less(kb, zz, kk, ki);
+          }
+        } else {
+          kb = key_bits((double)s_ck[w][i]);
+          surv = ke_less(kb, zz, kk, ki);
+        }
+      }
+      const uint64_t sm = __ballot(surv);
+      if (sm == 0) continue;
+      if (__popcll(sm) <= 4) {
+        uint64_t mm = sm;
+        while (mm) {
+          const int src = __ffsll((unsigned long long)mm) - 1;
+          mm &= mm - 1;
+          const uint64_t ck = shfl_u64(kb, src);
+          const uint32_t cz = shfl_u32(zz, src) | NEWBIT;
+          if (ke_less(ck, cz, shfl_u64(lk, K - 1), shfl_u32(li, K - 1))) wave_insert(lk, li, ck, cz);
+        }
+      } else {
+        uint64_t bk = surv ? kb : KEY_SENTINEL;
+        uint32_t bi = surv ? (zz | NEWBIT) : IDMASK;
+        wave_sort(bk, bi);
+        wave_merge(lk, li, bk, bi);
+      }
+    }
+    write_row(a, x, K, lane, lk, li, old, my_upd, my_err);
+    // evaluations and rescues of this receiver (wave sums)
+    int ev = item_evals, rs = resc;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      ev += __shfl_xor(ev, o, WAVE);
+      rs += __shfl_xor(rs, o, WAVE);
+    }
+    if (lane == 0) {
+      my_evals += ev;
+      my_resc += rs;
+      a.sl_n[x] = -1;  // merged here (k_merge skips it)
+      if (a.vcnt) {
+        a.vcnt[x * VC_N + VC_EVALS] = ev;
+        a.vcnt[x * VC_N + VC_RECVPERF] = rs;
+        a.vcnt[x * VC_N + VC_RESC] = rs;
+      }
+    }
+    wsync();  // (the next item overwrites this wave's LDS)
+  }
+  __shared__ int64_t s_red[4];
+  const int64_t ev = block_sum(my_evals, s_red);
+  const int64_t up = block_sum(my_upd, s_red);
+  const int64_t er = block_sum(my_err, s_red);
+  const int64_t rs = block_sum(my_resc, s_red);
+  if (threadIdx.x == 0) {
+    if (ev) atomicAdd((unsigned long long*)&a.stats[STAT_EVALS], (unsigned long long)ev);
+    if (up) atomicAdd((unsigned long long*)&a.stats[STAT_UPDATES], (unsigned long long)up);
+    if (er) atomicAdd((unsigned long long*)&a.stats[STAT_ERR], (unsigned long long)er);
+    if (rs) {
+      atomicAdd((unsigned long long*)&a.stats[STAT_RESCUES], (unsigned long long)rs);
+      atomicAdd((unsigned long long*)&a.stats[STAT_PERF], (unsigned long long)rs);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 // Resident blocks per CU of a kernel without dynamic LDS, queried once per
@@ -2188,11 +2580,35 @@ static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
   }
 }
 
+template <int CAP, typename PT, int MODE>
+static hipError_t launch_recv_wave(const Ctx& c, const JoinArgs& a, int cls) {
+  const int per_cu = occupancy<k_recv_wave<CAP, PT, MODE>, 256>();
+  const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu);
+  hipLaunchKernelGGL((k_recv_wave<CAP, PT, MODE>), dim3(grid), dim3(256), 0, c.stream, a, c.class_list,
+                     c.class_count, cls);
+  return hipGetLastError();
+}
+
 template <typename PT, int MODE>
 static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
   hipError_t e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 0, PT, MODE>(c, a, 0)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 1, PT, MODE>(c, a, 1)) != hipSuccess) return e;
+  // (exact hub form: the smallest classes in the wave-per-receiver form when
+  // the tuner chose it: recv_wave 1 = the 512-slot class, 2 = also 1024)
+  if constexpr (MODE == 1) {
+    if (c.recv_wave >= 1 && c.K < WAVE) {
+      if ((e = launch_recv_wave<CLASS_CAP_MIN << 0, PT, MODE>(c, a, 0)) != hipSuccess) return e;
+    } else if ((e = launch_recv_class<CLASS_CAP_MIN << 0, PT, MODE>(c, a, 0)) != hipSuccess) {
+      return e;
+    }
+    if (c.recv_wave >= 2 && c.K < WAVE) {
+      if ((e = launch_recv_wave<CLASS_CAP_MIN << 1, PT, MODE>(c, a, 1)) != hipSuccess) return e;
+    } else if ((e = launch_recv_class<CLASS_CAP_MIN << 1, PT, MODE>(c, a, 1)) != hipSuccess) {
+      return e;
+    }
+  } else {
+    if ((e = launch_recv_class<CLASS_CAP_MIN << 0, PT, MODE>(c, a, 0)) != hipSuccess) return e;
+    if ((e = launch_recv_class<CLASS_CAP_MIN << 1, PT, MODE>(c, a, 1)) != hipSuccess) return e;
+  }
   if ((e = launch_recv_class<CLASS_CAP_MIN << 2, PT, MODE>(c, a, 2)) != hipSuccess) return e;
   if ((e = launch_recv_class<CLASS_CAP_MIN << 3, PT, MODE>(c, a, 3)) != hipSuccess) return e;
   if ((e = launch_recv_class<CLASS_CAP_MIN << 4, PT, MODE>(c, a, 4)) != hipSuccess) return e;
@@ -2203,6 +2619,23 @@ static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
 
 template <int MAXD, typename PT, int CK>
 static hipError_t launch_hub_reg(const Ctx& c, const JoinArgs& a) {
+  // several hubs per wave (the tuner's choice, small K only)
+  if constexpr (MAXD <= 24) {
+  if (c.hub_hpw == 4 && c.K <= 16) {
+    const int per_cu = occupancy<k_hub_reg_sub<MAXD, PT, CK, 4>, 256>();
+    const int grid = (int)std::min<int64_t>((c.n + 15) / 16, (int64_t)per_cu * c.num_cu * 4);
+    const double* Pd = c.Pw ? c.Pw : reinterpret_cast<const double*>(c.P);
+    hipLaunchKernelGGL((k_hub_reg_sub<MAXD, PT, CK, 4>), dim3(grid), dim3(256), 0, c.stream, a, c.L, (const PT*)c.P, Pd);
+    return hipGetLastError();
+  }
+  if (c.hub_hpw == 2 && c.K <= 32) {
+    const int per_cu = occupancy<k_hub_reg_sub<MAXD, PT, CK, 2>, 256>();
+    const int grid = (int)std::min<int64_t>((c.n + 7) / 8, (int64_t)per_cu * c.num_cu * 4);
+    const double* Pd = c.Pw ? c.Pw : reinterpret_cast<const double*>(c.P);
+    hipLaunchKernelGGL((k_hub_reg_sub<MAXD, PT, CK, 2>), dim3(grid), dim3(256), 0, c.stream, a, c.L, (const PT*)c.P, Pd);
+    return hipGetLastError();
+  }
+  }
   auto kern = k_hub_reg<MAXD, PT, CK>;
   const int per_cu = occupancy<k_hub_reg<MAXD, PT, CK>, 256>();
   const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu * 4);
