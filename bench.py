@@ -64,22 +64,52 @@ def measured_traffic(precision):
     return rec.get("bytes_per_launch", {}).get(precision)
 
 
+def read_tuner_file(path):
+    """The join schedules the library's tuner chose (one line per workload
+    shape: the shape, the choice, the measured milliseconds of each
+    candidate's first-round join)."""
+    out = []
+    try:
+        with open(path) as f:
+            for line in f:
+                parts = [x.strip() for x in line.split("|")]
+                if len(parts) == 3:
+                    out.append({"shape": parts[0], "choice": parts[1], "trials_ms": parts[2]})
+    except OSError:
+        pass
+    return out
+
+
 def batched_leg(knnd, synth, torch, steps):
     """The batched workload (512 instances of uneven n, d, K) as one batched
-    call, next to the same instances run one by one through knnd_build_ex;
-    both on device-resident points, plain FP64 keys."""
+    call (rounds after the second replayed from captured graphs, join
+    schedules chosen by the library's tuner on the warm-up call), next to the
+    same instances run one by one through knnd_build_ex; device-resident
+    points, plain FP64 keys.  Also timed: the tuner choosing the precision
+    form per group (KNND_PREC_AUTO), and the call with rounds enqueued
+    kernel by kernel (no graphs)."""
+    import tempfile
+    tune_file = os.path.join(tempfile.mkdtemp(prefix="knnd_tune_"), "tune.txt")
+    os.environ["KNND_TUNE_CACHE"] = tune_file
     inst = []
     for b in range(synth.BATCH_INSTANCES):
         n, d, K, ds, s = synth.instance(synth.BATCH_BASE_SEED, b)
         inst.append((torch.from_numpy(synth.dirichlet(ds, n, d, np.float32)).cuda(), d, K, s))
+
+    def timed_calls(prm, reps):
+        knnd.knnd_build_batched(inst, prm)  # warm-up (tunes on first use of a shape)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, outs = knnd.knnd_build_batched(inst, prm)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, outs
+
     prm = knnd.default_params(precision=knnd.KNND_PREC_FP64)
-    knnd.knnd_build_batched(inst, prm)  # warm-up
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(steps):
-        _, outs = knnd.knnd_build_batched(inst, prm)
-    torch.cuda.synchronize()
-    batched_s = (time.perf_counter() - t) / steps
+    batched_s, outs = timed_calls(prm, steps)
+    auto_s, _ = timed_calls(knnd.default_params(precision=knnd.KNND_PREC_AUTO), steps)
+    eager_s, _ = timed_calls(knnd.default_params(precision=knnd.KNND_PREC_FP64, flags=knnd.KNND_FLAG_NO_GRAPH),
+                             max(1, steps // 2))
     evals = sum(s["evals_alg"] for o in outs for s in o["stats"])
     t = time.perf_counter()
     ev1 = 0
@@ -94,7 +124,8 @@ def batched_leg(knnd, synth, torch, steps):
             "batched_ms": round(1e3 * batched_s, 2), "one_by_one_ms": round(1e3 * single_s, 2),
             "speedup": round(single_s / batched_s, 3), "evals_alg": evals,
             "value": evals / batched_s, "unit": "evals/s",
-            "max_rounds": max(o["rounds"] for o in outs)}
+            "auto_precision_ms": round(1e3 * auto_s, 2), "no_graph_ms": round(1e3 * eager_s, 2),
+            "max_rounds": max(o["rounds"] for o in outs), "tuner": read_tuner_file(tune_file)}
 
 
 def share_leg(knnd, Pd, d, K, seed, precision, shares=8, reps=3):
