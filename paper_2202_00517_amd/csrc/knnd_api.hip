@@ -513,7 +513,9 @@ int init_graph(Ctx& c, knnd_round_stats* st) {
 // two or four hubs per wave, k_hub_reg_sub) or the LDS-staged one
 // (k_hub_lds), and, under KNND_PREC_AUTO, the BF16 mixed form; then, with
 // the fastest of those, the smallest receiver classes one wave per receiver
-// (k_recv_wave) for none, one or two classes.  Every candidate computes
+// (k_recv_wave) for none, one or two classes; then receivers of the
+// 8192-slot class whose distinct candidates probably fit a 4096-slot table
+// there, guarded (an overflowing receiver is redone in the 8192-slot class).  Every candidate computes
 // the same lists, keys and counts, so a choice changes only speed: the join
 // of the coming round (binning, hub kernel, receiver pass) is run once per
 // candidate from the round-start snapshot, timed with HIP events, and the
@@ -521,14 +523,15 @@ int init_graph(Ctx& c, knnd_round_stats* st) {
 // by workload shape (K, coordinates, size class, single or batched,
 // comparator, precision mode) for the rest of the process and, when
 // KNND_TUNE_CACHE names a file, in that file: one line per shape,
-// "<shape> | <mixed> <hub_lds> <hubs per wave> <wave receivers> | <ms of
-// each candidate>".
+// "<shape> | <mixed> <hub_lds> <hubs per wave> <wave receivers> <guarded
+// 4096> | <ms of each candidate>".
 // ---------------------------------------------------------------------------
 struct Sched {
   bool mixed;
   bool hub_lds;
   int hpw;    // hubs per wave of the register hub kernel
   int rwave;  // smallest receiver classes one wave per receiver (0, 1 or 2 classes)
+  int opt;    // guarded 4096-slot tables for receivers of the 8192-slot class that probably fit
 };
 
 std::mutex g_tune_mu;
@@ -545,13 +548,13 @@ void tune_load_locked() {
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
     const char* bar = std::strchr(line, '|');
-    int m = 0, h = 0, w = 1, rw = 0;
-    if (!bar || std::sscanf(bar + 1, "%d %d %d %d", &m, &h, &w, &rw) != 4 || (w != 1 && w != 2 && w != 4) ||
-        rw < 0 || rw > 2)
+    int m = 0, h = 0, w = 1, rw = 0, op = 0;
+    if (!bar || std::sscanf(bar + 1, "%d %d %d %d %d", &m, &h, &w, &rw, &op) != 5 ||
+        (w != 1 && w != 2 && w != 4) || rw < 0 || rw > 2)
       continue;
     std::string key(line, (size_t)(bar - line));
     while (!key.empty() && key.back() == ' ') key.pop_back();
-    g_tune[key] = Sched{m != 0, h != 0, w, rw};
+    g_tune[key] = Sched{m != 0, h != 0, w, rw, op != 0 ? 1 : 0};
   }
   std::fclose(f);
 }
@@ -570,12 +573,13 @@ void apply_sched(Ctx& c, Sched s) {
   c.hub_lds = s.hub_lds;
   c.hub_hpw = s.hpw;
   c.recv_wave = s.rwave;
+  c.opt4096 = s.opt != 0;
 }
 
 const char* sched_name(const Sched& s, char* buf, size_t len) {
   std::snprintf(buf, len, "%s%s%s%s", s.mixed ? "mixed" : "exact",
                 s.hub_lds ? "/lds" : (s.hpw == 4 ? "/hpw4" : (s.hpw == 2 ? "/hpw2" : "")),
-                s.rwave == 2 ? "/wave2" : (s.rwave == 1 ? "/wave1" : ""), "");
+                s.rwave == 2 ? "/wave2" : (s.rwave == 1 ? "/wave1" : ""), s.opt ? "/opt4096" : "");
   return buf;
 }
 
@@ -584,29 +588,33 @@ const char* sched_name(const Sched& s, char* buf, size_t len) {
 // and per-point counters are cleared between trials too).
 int tune_join(Ctx& c, bool group) {
   // stage 1: the form and the hub kernel; stage 2: the smallest receiver
-  // classes one wave per receiver or not, with the stage-1 choice
+  // classes one wave per receiver or not (exact form), with the stage-1
+  // choice (the guarded 4096-slot tables are tried on the second round,
+  // tune_opt: on the first every distinct candidate is listed)
   Sched cand[8];
   int nc = 0;
   const bool lds_fits = (size_t)(c.K + 1) * c.Ds * sizeof(double) <= 64 * 1024;
   if (c.plain_ok && (c.auto_prec || !c.mixed)) {
-    cand[nc++] = Sched{false, false, 1, 0};
-    if (c.D <= 24 && c.K <= 32) cand[nc++] = Sched{false, false, 2, 0};  // (the register kernel's row bound)
-    if (c.D <= 24 && c.K <= 16) cand[nc++] = Sched{false, false, 4, 0};
-    if (lds_fits) cand[nc++] = Sched{false, true, 1, 0};
+    cand[nc++] = Sched{false, false, 1, 0, 0};
+    if (c.D <= 24 && c.K <= 32) cand[nc++] = Sched{false, false, 2, 0, 0};  // (the register kernel's row bound)
+    if (c.D <= 24 && c.K <= 16) cand[nc++] = Sched{false, false, 4, 0, 0};
+    if (lds_fits) cand[nc++] = Sched{false, true, 1, 0, 0};
   }
-  if (c.mixed_ok && (c.auto_prec || c.mixed)) cand[nc++] = Sched{true, false, 1, 0};
+  if (c.mixed_ok && (c.auto_prec || c.mixed)) cand[nc++] = Sched{true, false, 1, 0, 0};
   if (nc == 0 || !c.evj0) return KNND_OK;
   const bool waves = c.use_hub && c.K < 64;  // (stage 2 applies, to the exact form)
-  // KNND_TUNE_FORCE="<mixed> <hub_lds> <hubs per wave> <wave receivers>"
-  // fixes the schedule when it is a candidate (no trials, nothing cached)
+  // KNND_TUNE_FORCE="<mixed> <hub_lds> <hubs per wave> <wave receivers>
+  // <guarded 4096>" fixes the schedule when it is a candidate (no trials,
+  // nothing cached)
   if (const char* force = std::getenv("KNND_TUNE_FORCE")) {
-    int m = 0, h = 0, w = 1, rw = 0;
-    if (std::sscanf(force, "%d %d %d %d", &m, &h, &w, &rw) == 4 && rw >= 0 && rw <= 2 &&
+    int m = 0, h = 0, w = 1, rw = 0, op = 0;
+    if (std::sscanf(force, "%d %d %d %d %d", &m, &h, &w, &rw, &op) == 5 && rw >= 0 && rw <= 2 &&
         (rw == 0 || (waves && m == 0)))
       for (int i = 0; i < nc; ++i)
         if (cand[i].mixed == (m != 0) && cand[i].hub_lds == (h != 0) && cand[i].hpw == w) {
           Sched f = cand[i];
           f.rwave = rw;
+          f.opt = op != 0 ? 1 : 0;
           apply_sched(c, f);
           return KNND_OK;
         }
@@ -621,8 +629,8 @@ int tune_join(Ctx& c, bool group) {
       return KNND_OK;
     }
   }
-  float ms[8] = {};
-  Sched tried[8];
+  float ms[10] = {};
+  Sched tried[10];
   int nt = 0;
   auto trial = [&](Sched sc, float* out) -> int {
     apply_sched(c, sc);
@@ -665,10 +673,69 @@ int tune_join(Ctx& c, bool group) {
   if (path && *path) {
     if (FILE* f = std::fopen(path, "a")) {
       const Sched& b = tried[best];
-      std::fprintf(f, "%s | %d %d %d %d |", key.c_str(), b.mixed ? 1 : 0, b.hub_lds ? 1 : 0, b.hpw, b.rwave);
+      std::fprintf(f, "%s | %d %d %d %d %d |", key.c_str(), b.mixed ? 1 : 0, b.hub_lds ? 1 : 0, b.hpw, b.rwave,
+                   b.opt);
       char nm[48];
       for (int i = 0; i < nt; ++i) std::fprintf(f, " %s:%.3f", sched_name(tried[i], nm, sizeof nm), ms[i]);
       std::fprintf(f, "\n");
+      std::fclose(f);
+    }
+  }
+  return KNND_OK;
+}
+
+// The second tuning point: on the second round (most lists are short from
+// there on) time the join with and without guarded 4096-slot tables for the
+// receivers of the 8192-slot class that probably fit, and keep the faster.
+// Cached per shape like tune_join's choice.
+int tune_opt(Ctx& c, bool group) {
+  if (!c.use_hub || !c.evj0) return KNND_OK;
+  if (const char* force = std::getenv("KNND_TUNE_FORCE")) {
+    int m = 0, h = 0, w = 1, rw = 0, op = 0;
+    if (std::sscanf(force, "%d %d %d %d %d", &m, &h, &w, &rw, &op) == 5) {
+      c.opt4096 = op != 0;
+      return KNND_OK;
+    }
+  }
+  const std::string key = tune_key(c, group) + " round=2";
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      c.opt4096 = it->second.opt != 0;
+      return KNND_OK;
+    }
+  }
+  float ms[2] = {0.f, 0.f};
+  for (int o = 0; o < 2; ++o) {
+    c.opt4096 = o != 0;
+    KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
+    if (group) {
+      KNND_HIP(knnd::launch_zero_i64(c.istats, (int64_t)c.nb * knnd::STAT_N, c.stream));
+      KNND_HIP(knnd::launch_zero_i32(c.vcnt, c.n * knnd::VC_N, c.stream));
+    }
+    KNND_HIP(knnd::launch_bin(c, false));
+    KNND_HIP(hipEventRecord(c.evj0, c.stream));
+    KNND_HIP(knnd::launch_join_hub(c, c.dstats));
+    KNND_HIP(knnd::launch_join_recv(c, c.dstats));
+    KNND_HIP(hipEventRecord(c.evj1, c.stream));
+    KNND_HIP(hipStreamSynchronize(c.stream));
+    KNND_HIP(hipEventElapsedTime(&ms[o], c.evj0, c.evj1));
+  }
+  c.opt4096 = ms[1] < ms[0];
+  Sched rec = Sched{c.mixed, c.hub_lds, c.hub_hpw, c.recv_wave, c.opt4096 ? 1 : 0};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = rec;
+  const char* path = std::getenv("KNND_TUNE_CACHE");
+  if (path && *path) {
+    if (FILE* f = std::fopen(path, "a")) {
+      char nm[48];
+      rec.opt = 0;
+      std::fprintf(f, "%s | %d %d %d %d %d | %s:%.3f", key.c_str(), c.mixed ? 1 : 0, c.hub_lds ? 1 : 0, c.hub_hpw,
+                   c.recv_wave, c.opt4096 ? 1 : 0, sched_name(rec, nm, sizeof nm), ms[0]);
+      rec.opt = 1;
+      std::fprintf(f, " %s:%.3f\n", sched_name(rec, nm, sizeof nm), ms[1]);
       std::fclose(f);
     }
   }
@@ -680,10 +747,11 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
   KNND_HIP(rec(c.ev0, c.stream));
   KNND_HIP(knnd::launch_csr(c, c.F[c.cur]));
-  if (c.tune && !c.tuned && c.own0 == 0 && c.own1 == c.n) {
-    // (the first round's time includes the trials)
+  if (c.tune && c.own0 == 0 && c.own1 == c.n && (!c.tuned || (c.round == 1 && !c.tuned2))) {
+    // (the first and second rounds' times include the trials)
+    const int t = c.tuned ? tune_opt(c, false) : tune_join(c, false);
+    if (c.tuned) c.tuned2 = true;
     c.tuned = true;
-    const int t = tune_join(c, false);
     if (t != KNND_OK) return t;
     KNND_HIP(knnd::launch_zero_i64(c.dstats, knnd::STAT_N, c.stream));
   }
@@ -1058,7 +1126,8 @@ int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t 
   int running = B;
   for (int r = 0; running > 0; ++r) {
     if (hipEventRecord(bt.e0, strm) != hipSuccess) return fail(KNND_ERR_DEVICE);
-    bool replay = graphs && r >= 2;
+    // (graphs from the third round on, after the tuner's second-round trials)
+    bool replay = graphs && r >= 3;
     if (replay) {
       std::vector<char> now;
       for (const Group& g : groups) now.push_back(g.running > 0);
@@ -1072,10 +1141,11 @@ int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t 
       for (size_t q = 0; q < groups.size(); ++q) {
         Ctx& c = groups[q].c;
         if (groups[q].running == 0) continue;
-        if (r == 1 && c.tune && !c.tuned) {  // the join's schedule, from this round's snapshot
-          c.tuned = true;
+        if ((r == 1 || r == 2) && c.tune && (r == 1 ? !c.tuned : !c.tuned2)) {
+          // the join's schedule, from this round's snapshot (round 0 only builds the initial lists)
           if (knnd::launch_csr(c, c.F[c.cur]) != hipSuccess) return fail(KNND_ERR_DEVICE);
-          if ((st = tune_join(c, true)) != KNND_OK) return fail(st);
+          if ((st = r == 1 ? tune_join(c, true) : tune_opt(c, true)) != KNND_OK) return fail(st);
+          (r == 1 ? c.tuned : c.tuned2) = true;
         }
         if ((st = enqueue_group_round(bt, q, r, nullptr)) != KNND_OK) return fail(st);
       }

@@ -112,9 +112,11 @@ struct Ctx {
   mutable int hub_lds_grid = 0;  // its grid, fixed on first use
   int hub_hpw = 1;               // hubs per wave of the register hub kernel (1, 2 or 4; small K)
   int recv_wave = 0;             // smallest receiver classes one wave per receiver (0: none, 1: 512 slots, 2: and 1024)
+  bool opt4096 = false;          // receivers of the 8192-slot class that probably fit try a guarded 4096-slot table
   bool auto_prec = false;        // KNND_PREC_AUTO: the tuner picks exact or mixed
   bool tune = false;             // time the candidate schedules on the first round
   bool tuned = false;
+  bool tuned2 = false;           // the second-round trials (guarded 4096-slot tables) are done
   bool mixed_ok = false;         // the mixed form's operands and bound are ready
   bool plain_ok = false;         // the exact hub form's key slots are ready
   // short candidate lists handed from the receiver kernel to k_merge (hub form)

@@ -540,7 +540,7 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
                                              int64_t own1, const uint32_t* __restrict__ F, int Ks,
                                              const uint32_t* __restrict__ col, const int32_t* __restrict__ vchg,
                                              const int32_t* __restrict__ vev, int32_t* __restrict__ sl_n,
-                                             int64_t* __restrict__ stats) {
+                                             int64_t* __restrict__ stats, int opt4096) {
   __shared__ int s_wcnt[NCLASS][4];
   __shared__ int s_base[NCLASS];
   const int lane = lane_id();
@@ -571,6 +571,11 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
       if (need2 <= (int64_t)(CLASS_CAP_MIN << 4)) {  // exact bound fits a small table
         cls = 0;
         while (need2 > (int64_t)(CLASS_CAP_MIN << cls)) ++cls;
+        if (opt4096 && cls == 4) {
+          // optimistic: a 4096-slot table guarded at 2560 distinct candidates
+          const int64_t T = c + (int64_t)K * K + c * K;
+          if ((min(T, n - 1 - K) * 5) / 8 + K + 1 <= (int64_t)(CLASS_CAP_MIN << 3) * 5 / 8) cls = 3;
+        }
       } else {
         // Large receivers: distinct candidates are typically 30-60% of the
         // occurrences, so size optimistically; the two guarded classes hand
@@ -1495,7 +1500,11 @@ constexpr int recv_waves_per_eu() {
   return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? (MODE == 2 ? 4 : 3) : (CAP == 8192 ? 4 : 1));
 }
 
-template <int CAP, typename PT, int MODE, int NW>
+// GRD: the class sizes its tables optimistically and hands a receiver that
+// overflows to a larger class (the 16384- and 32768-slot classes always, to
+// the global-memory class; the 4096-slot class when the tuner chose it, to
+// the 8192-slot class).
+template <int CAP, typename PT, int MODE, int NW, bool GRD = (CAP > 8192)>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(recv_waves_per_eu<CAP, MODE>())))
 void k_recv(JoinArgs a, int32_t* __restrict__ lists,
                                                   int32_t* __restrict__ counts, int cls) {
@@ -1504,7 +1513,8 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   constexpr int NT = NW * 64;
   constexpr bool GLOB = (CAP == 0);
   constexpr bool BIG = (CAP >= 8192);  // table in LDS, candidate list in global memory
-  constexpr bool GUARD = CAP > 8192;   // optimistically sized table (see k_bin)
+  constexpr bool GUARD = GRD;          // optimistically sized table (see k_bin)
+  constexpr int OVF = CAP > 8192 ? NCLASS - 1 : 4;  // the class that redoes an overflowing receiver
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
   // occurrences per thread in flight (the 16384- and 32768-slot classes are
@@ -1763,10 +1773,10 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
     }
     if (a.vcnt && item_evals) atomicAdd(&s_iev, (int)item_evals);
     __syncthreads();
-    if (GUARD && s_over) {  // table too small: the global-memory class redoes this receiver
+    if (GUARD && s_over) {  // table or list too small: a larger class redoes this receiver
       if (tid == 0) {
-        const int pos = atomicAdd(&counts[NCLASS - 1], 1);
-        lists[(int64_t)(NCLASS - 1) * n + pos] = (int32_t)x;
+        const int pos = atomicAdd(&counts[OVF], 1);
+        lists[(int64_t)OVF * n + pos] = (int32_t)x;
       }
       __syncthreads();
       continue;
@@ -2555,13 +2565,13 @@ hipError_t launch_bin(const Ctx& c, bool carry) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c.stream, c.class_count, (int64_t)NCLASS);
   hipLaunchKernelGGL(k_bin, dim3(grid_for(c.n, 256, 8192)), dim3(256), 0, c.stream, c.rowptr, c.n, c.K,
                      c.class_count, c.class_list, c.inst_of, c.iactive, c.own0, c.own1, c.F[c.cur], c.Ks, c.col,
-                     carry ? c.vchg : nullptr, c.vev, c.sl_n, c.dstats);
+                     carry ? c.vchg : nullptr, c.vev, c.sl_n, c.dstats, (c.opt4096 && c.use_hub) ? 1 : 0);
   // this round's flags are gathered afresh (after the test above has read the last round's)
   if (c.tracking) hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.vchg, c.n);
   return hipGetLastError();
 }
 
-template <int CAP, typename PT, int MODE>
+template <int CAP, typename PT, int MODE, bool GRD = (CAP > 8192)>
 static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
   if constexpr (CAP == 0) {
     // few, very large receivers: 1024 threads each, global-memory tables
@@ -2571,8 +2581,8 @@ static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
   } else {
     // small tables: two waves per receiver, twice the receivers in flight
     constexpr int NWC = CAP <= SMALL_NW_CAP ? 2 : 4;
-    auto kern = k_recv<CAP, PT, MODE, NWC>;
-    const int per_cu = occupancy<k_recv<CAP, PT, MODE, NWC>, NWC * 64>();
+    auto kern = k_recv<CAP, PT, MODE, NWC, GRD>;
+    const int per_cu = occupancy<k_recv<CAP, PT, MODE, NWC, GRD>, NWC * 64>();
     int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
     if (CAP >= 8192) grid = std::min(grid, c.bblocks);  // one global candidate region per block
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NWC * 64), 0, c.stream, a, c.class_list, c.class_count, cls);
@@ -2610,7 +2620,15 @@ static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
     if ((e = launch_recv_class<CLASS_CAP_MIN << 1, PT, MODE>(c, a, 1)) != hipSuccess) return e;
   }
   if ((e = launch_recv_class<CLASS_CAP_MIN << 2, PT, MODE>(c, a, 2)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 3, PT, MODE>(c, a, 3)) != hipSuccess) return e;
+  if constexpr (MODE >= 1) {
+    if (c.opt4096) {  // (the tuner's choice: optimistic 4096-slot tables, guarded)
+      if ((e = launch_recv_class<CLASS_CAP_MIN << 3, PT, MODE, true>(c, a, 3)) != hipSuccess) return e;
+    } else if ((e = launch_recv_class<CLASS_CAP_MIN << 3, PT, MODE>(c, a, 3)) != hipSuccess) {
+      return e;
+    }
+  } else if ((e = launch_recv_class<CLASS_CAP_MIN << 3, PT, MODE>(c, a, 3)) != hipSuccess) {
+    return e;
+  }
   if ((e = launch_recv_class<CLASS_CAP_MIN << 4, PT, MODE>(c, a, 4)) != hipSuccess) return e;
   if ((e = launch_recv_class<CLASS_CAP_MIN << 5, PT, MODE>(c, a, 5)) != hipSuccess) return e;
   if ((e = launch_recv_class<CLASS_CAP_MIN << 6, PT, MODE>(c, a, 6)) != hipSuccess) return e;

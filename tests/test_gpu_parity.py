@@ -600,8 +600,9 @@ def test_batched_autotuned_vs_oracle(tmp_path, monkeypatch):
     assert lines, "no tuned shape recorded"
     for ln in lines:
         key, choice, trials = (x.strip() for x in ln.split("|"))
-        mixed, lds, hpw, rwave = (int(v) for v in choice.split())
+        mixed, lds, hpw, rwave, opt = (int(v) for v in choice.split())
         assert len(trials.split()) >= 2 and not (mixed and lds) and hpw in (1, 2, 4) and rwave in (0, 1, 2)
+        assert opt in (0, 1)
     # a second call reuses the cached choices (no trials) and gives the same result
     st2, again = knnd.knnd_build_batched(inst, knnd.default_params(precision=knnd.KNND_PREC_AUTO))
     assert st2 == st
@@ -611,8 +612,8 @@ def test_batched_autotuned_vs_oracle(tmp_path, monkeypatch):
 
 # Every schedule the tuner can pick gives the oracle's result (forced one at
 # a time; a schedule that is not a candidate for a group leaves it tuned).
-@pytest.mark.parametrize("force", ["0 0 1 0", "0 0 2 0", "0 0 4 1", "0 1 1 2", "1 0 1 0"],
-                         ids=["reg", "reg_hpw2", "reg_hpw4_wave1", "lds_wave2", "mixed"])
+@pytest.mark.parametrize("force", ["0 0 1 0 0", "0 0 2 0 1", "0 0 4 1 0", "0 1 1 2 1", "1 0 1 0 0", "1 0 1 0 1"],
+                         ids=["reg", "reg_hpw2_opt", "reg_hpw4_wave1", "lds_wave2_opt", "mixed", "mixed_opt"])
 def test_batched_forced_schedules_vs_oracle(force, monkeypatch):
     monkeypatch.setenv("KNND_TUNE_FORCE", force)
     inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX]
@@ -626,13 +627,27 @@ def test_batched_forced_schedules_vs_oracle(force, monkeypatch):
 # Single descents under forced schedules with one wave per small receiver
 # (small K fills the 512- and 1024-slot classes), and the fixed-point rule so
 # that late rounds carry unchanged receivers over as well.
-@pytest.mark.parametrize("force", ["0 0 1 2", "0 0 4 1", "0 0 2 2"], ids=["wave2", "hpw4_wave1", "hpw2_wave2"])
+@pytest.mark.parametrize("force", ["0 0 1 2 0", "0 0 4 1 1", "0 0 2 2 0"],
+                         ids=["wave2", "hpw4_wave1_opt", "hpw2_wave2"])
 @pytest.mark.parametrize("n,d,K,ds,seed", [(5000, 4, 8, 9, 3), (20000, 10, 10, 6, 8), (777, 2, 5, 4, 4)])
 def test_single_forced_wave_receivers_vs_oracle(n, d, K, ds, seed, force, monkeypatch):
     monkeypatch.setenv("KNND_TUNE_FORCE", force)
     P = synth.dirichlet(ds, n, d, np.float32)
     full_compare(P, d, K, seed, precision=knnd.KNND_PREC_AUTO)
     full_compare(P, d, K, seed, precision=knnd.KNND_PREC_AUTO, stop_rule=knnd.KNND_STOP_FIXED_POINT)
+
+
+# Guarded 4096-slot tables: at K = 32 most receivers exceed the exact bound
+# of that table (T just above 2048) and, optimistically sized, fit it; those
+# that do not are redone in the 8192-slot class (round 1 lists every
+# distinct candidate, so some overflow the list).
+@pytest.mark.parametrize("force", ["0 0 1 0 1", "1 0 1 0 1"], ids=["exact_opt", "mixed_opt"])
+def test_single_forced_guarded_4096_vs_oracle(force, monkeypatch):
+    monkeypatch.setenv("KNND_TUNE_FORCE", force)
+    P = synth.dirichlet(31, 20000, 10, np.float32)
+    full_compare(P, 10, 32, 9, precision=knnd.KNND_PREC_AUTO)
+    P = synth.dirichlet(32, 3001, 20, np.float32)
+    full_compare(P, 20, 30, 7, precision=knnd.KNND_PREC_AUTO)
 
 
 @pytest.mark.parametrize("n,d,K,ds,seed", [(3001, 20, 30, 5, 7), (20000, 10, 20, 6, 8)])
