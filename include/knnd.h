@@ -88,7 +88,10 @@ typedef enum {
     KNND_PREC_AUTO = 3          /* the exact FP64 form or the BF16 mixed form,
                                    whichever the library's autotuner measures
                                    faster on the first round's join (per group
-                                   in batched calls); choices are cached per
+                                   in batched calls, which tune in every
+                                   mode; the second round's join then tries
+                                   guarded 4096-slot receiver tables);
+                                   choices are cached per
                                    workload shape in the process and, when the
                                    environment variable KNND_TUNE_CACHE names a
                                    file, in that file */
@@ -107,7 +110,7 @@ typedef enum {
                                    counting sort (same result) */
 #define KNND_FLAG_NO_GRAPH 0x10 /* batched calls: enqueue every round's kernels
                                    one by one instead of replaying the rounds
-                                   after the second from captured graphs
+                                   after the third from captured graphs
                                    (same result) */
 #define KNND_FLAG_NO_TUNE 0x20  /* no timing of candidate join schedules:
                                    k_hub_reg in the exact form, and
@@ -295,7 +298,7 @@ int knnd_build_noalloc(const void* points, int64_t n, int32_t d, int32_t K, uint
  *               all instances together.
  * Instances are grouped by K and number of coordinates; a group runs as one
  * set of persistent kernel launches per round, and an instance leaves its
- * group's rounds after its own stop test.  Rounds after the second are one
+ * group's rounds after its own stop test.  Rounds after the third are one
  * launch of a captured graph holding every running group's kernels (two
  * graphs, one per parity of the double-buffered lists; captured again when
  * a whole group has stopped; KNND_FLAG_NO_GRAPH enqueues the kernels one by
