@@ -814,7 +814,9 @@ __device__ __forceinline__ double hub_fold(const double (&pr)[MAXD], const doubl
 // Rows of up to 24 coordinates run three waves per SIMD: at 24 the compiler
 // would hold both rows in registers at two waves (195 VGPRs); three waves
 // with a few spilled values take the round's hub pass at 10^6 points from
-// 16.5 to 15.1 ms.  Wider rows spill too much at three.
+// 16.5 to 15.1 ms.  Wider rows spill too much at three.  Rows are held to
+// the next of 8, 12, 16, 20, 22, 24 coordinates (22 instead of 24 for 21:
+// 64 instead of 124 bytes spilled per lane, 15.1 to 14.0 ms).
 template <int MAXD>
 constexpr int hub_reg_waves_per_eu() {
   return MAXD <= 24 ? 3 : 1;
@@ -2669,6 +2671,8 @@ static hipError_t launch_hub(const Ctx& c, const JoinArgs& a) {
     if (c.D <= 8) return launch_hub_reg<8, PT, CK>(c, a);
     if (c.D <= 12) return launch_hub_reg<12, PT, CK>(c, a);
     if (c.D <= 16) return launch_hub_reg<16, PT, CK>(c, a);
+    if (c.D <= 20) return launch_hub_reg<20, PT, CK>(c, a);
+    if (c.D <= 22) return launch_hub_reg<22, PT, CK>(c, a);
     if (c.D <= 24) return launch_hub_reg<24, PT, CK>(c, a);
     if (c.D <= 32) return launch_hub_reg<32, PT, CK>(c, a);
     if (c.D <= 40) return launch_hub_reg<40, PT, CK>(c, a);
