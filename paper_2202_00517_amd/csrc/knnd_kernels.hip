@@ -309,10 +309,19 @@ __global__ void k_emit(const uint32_t* __restrict__ F, int64_t off, int64_t cnt,
 // scatter.  The order inside a co-friend list is arbitrary (the round's result
 // does not depend on it).
 // ---------------------------------------------------------------------------
-__global__ void k_degree(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks, int32_t* __restrict__ deg) {
+// A round over one share [own0, own1) of the receivers lists only the edges
+// it reads: those from a receiver of the share (a hub's co-friends that it
+// updates) or to one (a receiver's own co-friends); a full round lists all.
+__device__ __forceinline__ bool csr_keep(int64_t x, uint32_t v, int64_t own0, int64_t own1) {
+  return (x >= own0 && x < own1) || ((int64_t)v >= own0 && (int64_t)v < own1);
+}
+
+__global__ void k_degree(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks, int64_t own0, int64_t own1,
+                         int32_t* __restrict__ deg) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = e / K;
-    atomicAdd(&deg[F[x * Ks + (e - x * K)] & IDMASK], 1);
+    const uint32_t v = F[x * Ks + (e - x * K)] & IDMASK;
+    if (csr_keep(x, v, own0, own1)) atomicAdd(&deg[v], 1);
   }
 }
 
@@ -384,13 +393,14 @@ __global__ void k_scan_add(int64_t* __restrict__ rowptr, int64_t n, const int64_
 
 // Edge e = x*K + j (x -> v = F[x][j]) lands at position q of coF(v):
 // col[rowptr[v] + q] = x | new-flag, colslot[...] = j.
-__global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks,
+__global__ void k_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks, int64_t own0, int64_t own1,
                           const int64_t* __restrict__ rowptr, int32_t* __restrict__ fill, uint32_t* __restrict__ col,
                           uint8_t* __restrict__ colslot) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nK; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = e / K;
     const uint32_t raw = F[x * Ks + (e - x * K)];
     const uint32_t v = raw & IDMASK;
+    if (!csr_keep(x, v, own0, own1)) continue;
     const int q = atomicAdd(&fill[v], 1);
     const int64_t pos = rowptr[v] + q;
     col[pos] = (uint32_t)x | (raw & NEWBIT);
@@ -417,7 +427,7 @@ __device__ __forceinline__ uint32_t edge_raw(const uint32_t* __restrict__ F, int
 }
 
 __global__ __launch_bounds__(1024) void k_part_count(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks,
-                                                     int chunk, int shift, int nb,
+                                                     int chunk, int shift, int nb, int64_t own0, int64_t own1,
                                                      unsigned long long* __restrict__ bcount) {
   __shared__ int32_t h[CSR_MAXB];
   for (int t = threadIdx.x; t < nb; t += blockDim.x) h[t] = 0;
@@ -425,8 +435,10 @@ __global__ __launch_bounds__(1024) void k_part_count(const uint32_t* __restrict_
   const int64_t e0 = (int64_t)blockIdx.x * chunk;
   const int64_t e1 = min(e0 + chunk, nK);
   const int64_t x0 = e0 / K;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-    atomicAdd(&h[(edge_raw(F, e0, x0, e, K, Ks) & IDMASK) >> shift], 1);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const uint32_t v = edge_raw(F, e0, x0, e, K, Ks) & IDMASK;
+    if (csr_keep(e / K, v, own0, own1)) atomicAdd(&h[v >> shift], 1);
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < nb; t += blockDim.x)
     if (h[t]) atomicAdd(&bcount[t], (unsigned long long)h[t]);
@@ -454,7 +466,7 @@ __global__ __launch_bounds__(256) void k_exscan_small(const unsigned long long* 
 }
 
 __global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks,
-                                                       int chunk, int shift, int nb,
+                                                       int chunk, int shift, int nb, int64_t own0, int64_t own1,
                                                        const int64_t* __restrict__ bbase,
                                                        unsigned long long* __restrict__ bfill,
                                                        uint64_t* __restrict__ T) {
@@ -465,8 +477,10 @@ __global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restric
   const int64_t e0 = (int64_t)blockIdx.x * chunk;  // chunk is a multiple of K
   const int64_t e1 = min(e0 + chunk, nK);
   const int64_t x0 = e0 / K;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-    atomicAdd(&h[(edge_raw(F, e0, x0, e, K, Ks) & IDMASK) >> shift], 1);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const uint32_t v = edge_raw(F, e0, x0, e, K, Ks) & IDMASK;
+    if (csr_keep(e / K, v, own0, own1)) atomicAdd(&h[v >> shift], 1);
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < nb; t += blockDim.x) {
     if (h[t]) base[t] = bbase[t] + (int64_t)atomicAdd(&bfill[t], (unsigned long long)h[t]);
@@ -477,6 +491,7 @@ __global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restric
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const uint32_t raw = edge_raw(F, e0, x0, e, K, Ks);
     const uint32_t v = raw & IDMASK;
+    if (!csr_keep(e / K, v, own0, own1)) continue;
     const int b = (int)(v >> shift);
     const int q = atomicAdd(&h[b], 1);
     const uint32_t r = (uint32_t)(e - e0);
@@ -2545,21 +2560,22 @@ hipError_t launch_csr(const Ctx& c, const uint32_t* F) {
     const unsigned blocks = (unsigned)((nK + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_zero_i64, dim3(grid_for(nb, 256, 64)), dim3(256), 0, c.stream, c.csr_bcount, (int64_t)nb);
     hipLaunchKernelGGL(k_part_count, dim3(blocks), dim3(1024), 0, c.stream, F, nK, c.K, c.Ks, chunk, c.csr_shift, nb,
-                       (unsigned long long*)c.csr_bcount);
+                       c.own0, c.own1, (unsigned long long*)c.csr_bcount);
     hipLaunchKernelGGL(k_exscan_small, dim3(1), dim3(256), 0, c.stream, (const unsigned long long*)c.csr_bcount,
                        (int64_t)nb, c.csr_bbase, (unsigned long long*)c.csr_bfill);
     hipLaunchKernelGGL(k_part_scatter, dim3(blocks), dim3(1024), 0, c.stream, F, nK, c.K, c.Ks, chunk, c.csr_shift, nb,
-                       c.csr_bbase, (unsigned long long*)c.csr_bfill, c.csr_T);
+                       c.own0, c.own1, c.csr_bbase, (unsigned long long*)c.csr_bfill, c.csr_T);
     hipLaunchKernelGGL(k_bucket_csr, dim3((unsigned)nb), dim3(256), 0, c.stream, c.csr_T, c.csr_bbase, c.n,
                        c.csr_shift, nb, c.rowptr, c.col, c.colslot);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.deg, c.n);
   hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(c.n, 256, 4096)), dim3(256), 0, c.stream, c.fill, c.n);
-  hipLaunchKernelGGL(k_degree, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.Ks, c.deg);
+  hipLaunchKernelGGL(k_degree, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.Ks, c.own0,
+                     c.own1, c.deg);
   launch_scan(c, 1, 0, c.rowptr);
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.Ks,
-                     c.rowptr, c.fill, c.col, c.colslot);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(nK, 256, 8192)), dim3(256), 0, c.stream, F, nK, c.K, c.Ks, c.own0,
+                     c.own1, c.rowptr, c.fill, c.col, c.colslot);
   return hipGetLastError();
 }
 
