@@ -299,7 +299,8 @@ int knnd_build_noalloc(const void* points, int64_t n, int32_t d, int32_t K, uint
  * Instances are grouped by K and number of coordinates; a group runs as one
  * set of persistent kernel launches per round, and an instance leaves its
  * group's rounds after its own stop test.  Rounds after the third are one
- * launch of a captured graph holding every running group's kernels (two
+ * launch of a captured graph holding every running group's kernels, each
+ * group a branch of its own (two
  * graphs, one per parity of the double-buffered lists; captured again when
  * a whole group has stopped; KNND_FLAG_NO_GRAPH enqueues the kernels one by
  * one instead).  `ms` in an instance's stats is the device time of the

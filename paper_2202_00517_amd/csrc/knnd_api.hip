@@ -978,6 +978,11 @@ struct Batch {
   int64_t* hall = nullptr;     // pinned host copy
   int64_t* dround = nullptr;   // device round index of graph-launched rounds
   hipStream_t cs = nullptr;    // capture stream
+  // branch streams of the captured round (each running group's kernels form
+  // a branch of their own, forked from and joined into the capture stream)
+  std::vector<hipStream_t> bs;
+  std::vector<hipEvent_t> bev;  // their join events
+  hipEvent_t fork = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::vector<char> captured;  // running groups the graphs hold
@@ -1021,11 +1026,28 @@ int enqueue_group_round(Batch& bt, size_t gi, int r, const int64_t* round_dev) {
   return KNND_OK;
 }
 
+// The branch streams (one per group, at most 16) and their events.
+int make_branches(Batch& bt) {
+  if (!bt.fork) KNND_HIP(hipEventCreateWithFlags(&bt.fork, hipEventDisableTiming));
+  const size_t nbr = std::min<size_t>(bt.groups.size(), 16);
+  while (bt.bs.size() < nbr) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    KNND_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));  // (default priority)
+    bt.bs.push_back(s);
+    KNND_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    bt.bev.push_back(e);
+  }
+  return KNND_OK;
+}
+
 // Capture the round of every running group, for both parities.  On failure
 // the call goes on with rounds enqueued one by one.
 int capture_graphs(Batch& bt) {
   drop_graphs(bt);
   if (!bt.cs) KNND_HIP(hipStreamCreateWithFlags(&bt.cs, hipStreamNonBlocking));
+  if (make_branches(bt) != KNND_OK) return KNND_ERR_DEVICE;
+  const size_t nbr = bt.bs.size();
   for (int p = 0; p < 2; ++p) {
     std::vector<std::pair<hipStream_t, int>> saved;
     for (Group& g : bt.groups) {
@@ -1035,8 +1057,19 @@ int capture_graphs(Batch& bt) {
     }
     int st = KNND_OK;
     if (hipStreamBeginCapture(bt.cs, hipStreamCaptureModeRelaxed) != hipSuccess) st = KNND_ERR_DEVICE;
-    for (size_t gi = 0; gi < bt.groups.size() && st == KNND_OK; ++gi)
-      if (bt.groups[gi].running > 0) st = enqueue_group_round(bt, gi, 1, bt.dround);
+    if (st == KNND_OK && hipEventRecord(bt.fork, bt.cs) != hipSuccess) st = KNND_ERR_DEVICE;
+    size_t used = 0;  // branch streams in use
+    for (size_t gi = 0; gi < bt.groups.size() && st == KNND_OK; ++gi) {
+      if (bt.groups[gi].running == 0) continue;
+      hipStream_t s = bt.bs[used % nbr];
+      if (used < nbr && hipStreamWaitEvent(s, bt.fork, 0) != hipSuccess) st = KNND_ERR_DEVICE;
+      bt.groups[gi].c.stream = s;
+      if (st == KNND_OK) st = enqueue_group_round(bt, gi, 1, bt.dround);
+      ++used;
+    }
+    for (size_t i = 0; i < std::min(used, nbr); ++i)  // (joined on failure too, before the capture ends)
+      if (hipEventRecord(bt.bev[i], bt.bs[i]) != hipSuccess || hipStreamWaitEvent(bt.cs, bt.bev[i], 0) != hipSuccess)
+        st = KNND_ERR_DEVICE;
     if (st == KNND_OK && knnd::launch_add_i64(bt.dround, 1, bt.cs) != hipSuccess) st = KNND_ERR_DEVICE;
     hipGraph_t gr = nullptr;
     const hipError_t ee = hipStreamEndCapture(bt.cs, &gr);  // (ends a capture that failed midway too)
@@ -1103,6 +1136,12 @@ int build_batched(knnd_instance* inst, int32_t B, const knnd_params* p, int32_t 
     (void)hipStreamSynchronize(strm);
     drop_graphs(bt);
     if (bt.cs) (void)hipStreamDestroy(bt.cs);
+    for (hipStream_t s : bt.bs) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : bt.bev) (void)hipEventDestroy(e);
+    if (bt.fork) (void)hipEventDestroy(bt.fork);
+    bt.bs.clear();
+    bt.bev.clear();
+    bt.fork = nullptr;
     for (Group& g : groups) free_group(g);
     knnd::pool_free(bt.dall);
     knnd::pool_free(bt.dround);
