@@ -830,8 +830,8 @@ __device__ __forceinline__ double hub_fold(const double (&pr)[MAXD], const doubl
 // would hold both rows in registers at two waves (195 VGPRs); three waves
 // with a few spilled values take the round's hub pass at 10^6 points from
 // 16.5 to 15.1 ms.  Wider rows spill too much at three.  Rows are held to
-// the next of 8, 12, 16, 20, 22, 24 coordinates (22 instead of 24 for 21:
-// 64 instead of 124 bytes spilled per lane, 15.1 to 14.0 ms).
+// the next of 8, 12, 16, 20, 21, 22, 24 coordinates (21 instead of 24 at
+// d = 20: 40 instead of 124 bytes spilled per lane, 15.1 to 13.5 ms).
 template <int MAXD>
 constexpr int hub_reg_waves_per_eu() {
   return MAXD <= 24 ? 3 : 1;
@@ -2688,6 +2688,7 @@ static hipError_t launch_hub(const Ctx& c, const JoinArgs& a) {
     if (c.D <= 12) return launch_hub_reg<12, PT, CK>(c, a);
     if (c.D <= 16) return launch_hub_reg<16, PT, CK>(c, a);
     if (c.D <= 20) return launch_hub_reg<20, PT, CK>(c, a);
+    if (c.D <= 21) return launch_hub_reg<21, PT, CK>(c, a);
     if (c.D <= 22) return launch_hub_reg<22, PT, CK>(c, a);
     if (c.D <= 24) return launch_hub_reg<24, PT, CK>(c, a);
     if (c.D <= 32) return launch_hub_reg<32, PT, CK>(c, a);
