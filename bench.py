@@ -82,8 +82,9 @@ def read_tuner_file(path):
 
 def batched_leg(knnd, synth, torch, steps):
     """The batched workload (512 instances of uneven n, d, K) as one batched
-    call (rounds after the second replayed from captured graphs, join
-    schedules chosen by the library's tuner on the warm-up call), next to the
+    call (rounds after the third replayed from captured graphs, each group a
+    branch of its own; join schedules chosen by the library's tuner on the
+    warm-up call), next to the
     same instances run one by one through knnd_build_ex; device-resident
     points, plain FP64 keys.  Also timed: the tuner choosing the precision
     form per group (KNND_PREC_AUTO), and the call with rounds enqueued
