@@ -14,8 +14,9 @@ import synth
 pytestmark = pytest.mark.gpu
 
 FORMS = [(0, knnd.KNND_PREC_FP64), (knnd.KNND_FLAG_PULL, knnd.KNND_PREC_FP64),
-         (0, knnd.KNND_PREC_MIXED_BF16), (0, knnd.KNND_PREC_MIXED_FP16)]
-FORM_IDS = ["hub", "pull", "bf16", "fp16"]
+         (0, knnd.KNND_PREC_MIXED_BF16), (0, knnd.KNND_PREC_MIXED_FP16),
+         (knnd.KNND_FLAG_ATOMIC_CSR, knnd.KNND_PREC_FP64), (knnd.KNND_FLAG_ATOMIC_CSR, knnd.KNND_PREC_MIXED_BF16)]
+FORM_IDS = ["hub", "pull", "bf16", "fp16", "atomic_csr", "atomic_csr_bf16"]
 
 
 def say(msg):
@@ -61,6 +62,13 @@ def test_shares_partition_the_full_round(form):
             st = c.round_share(a, b - a)
             assert c.rounds == 2
             gi, gk = c.get_graph()
+            # a share round lists only the reverse edges it reads; the
+            # context's co-friend lists afterwards are whole again
+            rp, col = c.cofriends()
+        src = np.repeat(np.arange(n), K)
+        deg = np.bincount(np.asarray(gi).ravel(), minlength=n)
+        assert np.array_equal(rp, np.concatenate([[0], np.cumsum(deg)])), (a, b)
+        assert np.array_equal(col, src[np.lexsort((src, np.asarray(gi).ravel()))].astype(np.int32)), (a, b)
         own = np.zeros(n, dtype=bool)
         own[a:b] = True
         assert np.array_equal(gi[own], F_idx[own]), (a, b)
