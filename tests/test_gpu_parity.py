@@ -127,6 +127,40 @@ def one_round(P, d, K, seed, F0=None, k0=None, flags=0, precision=0, cmp=0):
     return st
 
 
+# Checkpoint and resume: a round's state is its lists, keys and round index
+# (every random draw is a hash of the seed and indices), so a descent saved
+# after round r and resumed in a fresh context follows the uninterrupted one
+# exactly: the same lists, keys, update, evaluation and FCR counts in every
+# later round (only the evaluations performed differ: the resumed round
+# counts every edge as new and skips no pair).
+def _resume_case(P, d, K, seed, prm, save_at, total):
+    with knnd.Context(P, d, K, seed, prm) as c:
+        c.init_graph()
+        ref = []
+        for r in range(1, total + 1):
+            st = c.round()
+            if r == save_at:
+                si, sk = c.get_graph()
+            ref.append(st)
+        fi, fk = c.get_graph()
+    with knnd.Context(P, d, K, seed, prm) as c:
+        c.set_graph(si, sk, save_at)
+        got = [c.round() for _ in range(save_at + 1, total + 1)]
+        gi, gk = c.get_graph()
+    for a, b in zip(ref[save_at:], got):
+        assert (a["updates"], a["evals_alg"], a["fcr_hits"]) == (b["updates"], b["evals_alg"], b["fcr_hits"]), (a, b)
+    assert np.array_equal(fi, gi) and np.array_equal(bits(fk), bits(gk))
+
+
+@pytest.mark.parametrize("form", [(0, knnd.KNND_PREC_FP64), (0, knnd.KNND_PREC_MIXED_BF16),
+                                  (knnd.KNND_FLAG_PULL, knnd.KNND_PREC_FP64)], ids=["hub", "bf16", "pull"])
+@pytest.mark.parametrize("save_at", [1, 3])
+def test_resume_from_a_saved_round(form, save_at):
+    P = synth.dirichlet(41, 20000, 10, np.float32)
+    say(f"resume after round {save_at}, form {form}")
+    _resume_case(P, 10, 16, 5, knnd.default_params(flags=form[0], precision=form[1]), save_at, 6)
+
+
 JOIN_FORMS = [0, knnd.KNND_FLAG_PULL]
 # (flags, precision): exact hub form, pull form, BF16 and FP16 mixed forms
 FORMS = [(0, knnd.KNND_PREC_FP64), (knnd.KNND_FLAG_PULL, knnd.KNND_PREC_FP64),
