@@ -220,6 +220,29 @@ void knnd_default_params(knnd_params* p);
  */
 int knnd_release_cache(void);
 
+/*
+ * Bytes of device memory the library holds: *live in blocks that live
+ * contexts and running calls use, *cached in the cache above (either pointer
+ * may be NULL).  Every call and every destroyed context gives its blocks
+ * back, so between calls *live is the memory of the live contexts (0 when
+ * there are none).  Thread-safe; returns KNND_OK.
+ */
+int knnd_memory_stats(int64_t* live, int64_t* cached);
+
+/*
+ * Test support (failure injection): after knnd_test_fail_alloc(k) with
+ * k >= 1, the k-th device allocation the library makes from then on fails as
+ * if the device were out of memory (once); k <= 0 disarms.  Returns how many
+ * allocations were still to go before the armed failure (0 when none was
+ * armed or it has fired), so that a caller can tell whether a call reached
+ * it.  A buffer the method needs turns such a failure into KNND_ERR_NOMEM
+ * with every block given back; an optional one (the hub and mixed-precision
+ * forms' buffers, the neighbourhood-tracking flags) makes the call run the
+ * next form instead, with the same results.  Process-wide, not meant for
+ * concurrent calls.
+ */
+int64_t knnd_test_fail_alloc(int64_t k);
+
 /* Human-readable name of a knnd_status value (static storage). */
 const char* knnd_status_string(int status);
 

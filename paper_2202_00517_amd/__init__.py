@@ -38,7 +38,7 @@ EXPORTED = [
     "knnd_build_ex", "knnd_ctx_create", "knnd_ctx_init_graph", "knnd_ctx_set_graph",
     "knnd_ctx_round", "knnd_ctx_round_share", "knnd_ctx_get_graph", "knnd_ctx_get_log_table", "knnd_ctx_rounds",
     "knnd_ctx_destroy", "knnd_build_batched", "knnd_exact_knn", "knnd_release_cache",
-    "knnd_build_noalloc", "knnd_ctx_get_cofriends",
+    "knnd_build_noalloc", "knnd_ctx_get_cofriends", "knnd_memory_stats", "knnd_test_fail_alloc",
 ]
 KNND_NOALLOC_MAX_BYTES = 256 << 20
 
@@ -115,6 +115,8 @@ def lib():
         "knnd_build_batched": (ctypes.c_int, [P(knnd_instance), i32, P(knnd_params), i32, vp]),
         "knnd_exact_knn": (ctypes.c_int, [vp, i64, i32, i32, i32, i32, vp, i64, vp, i32, vp, vp, vp]),
         "knnd_release_cache": (ctypes.c_int, []),
+        "knnd_memory_stats": (ctypes.c_int, [vp, vp]),
+        "knnd_test_fail_alloc": (i64, [i64]),
         "knnd_build_noalloc": (ctypes.c_int, [vp, i64, i32, i32, u64, P(knnd_params), vp, vp, vp,
                                               P(knnd_round_stats), vp]),
     }
@@ -136,6 +138,22 @@ def status_string(status):
 def release_cache():
     """Return the library's cached device memory to the device."""
     return lib().knnd_release_cache()
+
+
+def memory_stats():
+    """(live, cached): bytes of device memory in use by live contexts and
+    running calls, and held in the library's cache."""
+    live, cached = ctypes.c_int64(), ctypes.c_int64()
+    lib().knnd_memory_stats(ctypes.byref(live), ctypes.byref(cached))
+    return live.value, cached.value
+
+
+def inject_alloc_failure(k):
+    """Failure injection (tests): the k-th device allocation from now on
+    fails as out of memory (k <= 0 disarms).  Returns how many allocations
+    were still to go before the previously armed failure (0: none armed, or
+    it fired)."""
+    return lib().knnd_test_fail_alloc(int(k))
 
 
 def default_params(**kw):

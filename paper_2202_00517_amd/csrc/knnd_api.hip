@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -68,8 +69,11 @@ void free_block(const PoolBlock& b) {
 }
 }  // namespace
 
+std::atomic<int64_t> g_fail_at{0};  // test support: allocations to go before an injected failure
+
 hipError_t pool_malloc(void** out, size_t bytes) {
   *out = nullptr;
+  if (g_fail_at.load() > 0 && g_fail_at.fetch_sub(1) == 1) return hipErrorOutOfMemory;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -122,6 +126,14 @@ void pool_free(void* p) {
     }
   }
   for (const PoolBlock& b : drop) free_block(b);
+}
+
+void pool_stats(int64_t* live, int64_t* cached) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  size_t l = 0;
+  for (const auto& kv : g_live) l += kv.second.bytes;
+  if (live) *live = (int64_t)l;
+  if (cached) *cached = (int64_t)g_cached_bytes;
 }
 
 void pool_release() {
@@ -620,13 +632,23 @@ int tune_join(Ctx& c, bool group) {
         }
   }
   const std::string key = tune_key(c, group);
+  // A cached choice applies when it is one of this context's candidates: a
+  // context whose optional buffers did not all fit (so that a form is
+  // missing) chooses among the forms it has, and its choice is not cached.
+  bool cacheable = true;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
-      apply_sched(c, it->second);
-      return KNND_OK;
+      const Sched& h = it->second;
+      for (int i = 0; i < nc; ++i)
+        if (cand[i].mixed == h.mixed && cand[i].hub_lds == h.hub_lds && cand[i].hpw == h.hpw &&
+            (h.rwave == 0 || (waves && !h.mixed))) {
+          apply_sched(c, h);
+          return KNND_OK;
+        }
+      cacheable = false;
     }
   }
   float ms[10] = {};
@@ -667,6 +689,7 @@ int tune_join(Ctx& c, bool group) {
       ++nt;
     }
   apply_sched(c, tried[best]);
+  if (!cacheable) return KNND_OK;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[key] = tried[best];
   const char* path = std::getenv("KNND_TUNE_CACHE");
@@ -1351,6 +1374,16 @@ int knnd_abi_version(void) { return KNND_ABI_VERSION; }
 int knnd_release_cache(void) {
   knnd::pool_release();
   return KNND_OK;
+}
+
+int knnd_memory_stats(int64_t* live, int64_t* cached) {
+  knnd::pool_stats(live, cached);
+  return KNND_OK;
+}
+
+int64_t knnd_test_fail_alloc(int64_t k) {
+  const int64_t left = knnd::g_fail_at.exchange(k > 0 ? k : 0);
+  return left > 0 ? left : 0;
 }
 
 int knnd_ctx_create(const void* points, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_params* p,

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include <algorithm>
 
 namespace knnd {
@@ -214,6 +216,8 @@ struct JoinArgs {
 hipError_t pool_malloc(void** p, size_t bytes);
 void pool_free(void* p);
 void pool_release();
+void pool_stats(int64_t* live, int64_t* cached);
+extern std::atomic<int64_t> g_fail_at;
 template <class T>
 hipError_t pmalloc(T** p, size_t bytes) {
   return pool_malloc(reinterpret_cast<void**>(p), bytes);

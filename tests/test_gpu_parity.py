@@ -586,11 +586,12 @@ BATCH_MIX = [(900, 12, 8, 11, 21), (2500, 13, 8, 12, 22), (1300, 15, 8, 13, 23),
              (5000, 9, 32, 19, 29), (64, 30, 32, 20, 30), (1200, 1, 2, 21, 31), (6000, 19, 16, 22, 32)]
 
 
-@pytest.mark.parametrize("prec", [knnd.KNND_PREC_FP64, knnd.KNND_PREC_MIXED_BF16], ids=["plain", "bf16"])
-def test_batched_mix_vs_oracle(prec):
+@pytest.mark.parametrize("prec,flags", [(knnd.KNND_PREC_FP64, 0), (knnd.KNND_PREC_MIXED_BF16, 0),
+                                        (knnd.KNND_PREC_FP64, knnd.KNND_FLAG_PULL)], ids=["plain", "bf16", "pull"])
+def test_batched_mix_vs_oracle(prec, flags):
     inst = [(synth.dirichlet(ds, n, d, np.float32), d, K, s) for n, d, K, ds, s in BATCH_MIX]
-    say(f"batched: {len(inst)} instances, precision {prec}")
-    st, outs = knnd.knnd_build_batched(inst, knnd.default_params(precision=prec))
+    say(f"batched: {len(inst)} instances, precision {prec}, flags {flags}")
+    st, outs = knnd.knnd_build_batched(inst, knnd.default_params(precision=prec, flags=flags))
     assert st == knnd.KNND_OK
     for (P, d, K, s), g in zip(inst, outs):
         _compare_instance(g, P, d, K, s, f"instance n={P.shape[0]} d={d} K={K}")
