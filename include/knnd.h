@@ -212,8 +212,9 @@ void knnd_default_params(knnd_params* p);
 /*
  * Device memory.  Scratch blocks a finished call or a destroyed context
  * gives back are kept in a per-process cache (per device, by rounded size,
- * at most half of the first device's memory; the oldest are freed first)
- * and reused by later calls, so
+ * at most half of the first device's memory or, if more, as much as the
+ * library has had in use at once since the cache was last released; the
+ * oldest are freed first) and reused by later calls, so
  * that repeated calls skip hipMalloc and hipFree.  knnd_release_cache()
  * returns every cached block to the device (blocks in use by live contexts
  * stay).  Thread-safe; returns KNND_OK.

@@ -48,6 +48,8 @@ std::mutex g_pool_mu;
 std::vector<PoolBlock> g_cached;
 std::unordered_map<void*, PoolBlock> g_live;
 size_t g_cached_bytes = 0;
+size_t g_live_bytes = 0;
+size_t g_peak_live = 0;  // the most the library has had in use at once
 size_t g_cap = 0;  // set on the first allocation (under g_pool_mu)
 
 // Sizes are rounded up (to 256 bytes, above 1 MiB to an eighth of their
@@ -90,6 +92,8 @@ hipError_t pool_malloc(void** out, size_t bytes) {
         g_cached.erase(g_cached.begin() + (std::ptrdiff_t)i);
         g_cached_bytes -= rb;
         g_live.emplace(b.p, b);
+        g_live_bytes += rb;
+        g_peak_live = std::max(g_peak_live, g_live_bytes);
         *out = b.p;
         return hipSuccess;
       }
@@ -105,6 +109,8 @@ hipError_t pool_malloc(void** out, size_t bytes) {
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lk(g_pool_mu);
   g_live.emplace(p, PoolBlock{p, rb, dev});
+  g_live_bytes += rb;
+  g_peak_live = std::max(g_peak_live, g_live_bytes);
   *out = p;
   return hipSuccess;
 }
@@ -118,8 +124,13 @@ void pool_free(void* p) {
     if (it == g_live.end()) return;  // (every library block comes from pool_malloc)
     g_cached.push_back(it->second);
     g_cached_bytes += it->second.bytes;
+    g_live_bytes -= it->second.bytes;
     g_live.erase(it);
-    while (g_cached_bytes > g_cap && !g_cached.empty()) {
+    // the cache keeps up to half the device's memory, or as much as the
+    // library has had in use at once if that is more (so that a call larger
+    // than half the memory, repeated, reuses its blocks)
+    const size_t cap = std::max(g_cap, g_peak_live);
+    while (g_cached_bytes > cap && !g_cached.empty()) {
       drop.push_back(g_cached.front());
       g_cached_bytes -= g_cached.front().bytes;
       g_cached.erase(g_cached.begin());
@@ -130,9 +141,7 @@ void pool_free(void* p) {
 
 void pool_stats(int64_t* live, int64_t* cached) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  size_t l = 0;
-  for (const auto& kv : g_live) l += kv.second.bytes;
-  if (live) *live = (int64_t)l;
+  if (live) *live = (int64_t)g_live_bytes;
   if (cached) *cached = (int64_t)g_cached_bytes;
 }
 
@@ -142,6 +151,7 @@ void pool_release() {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     drop.swap(g_cached);
     g_cached_bytes = 0;
+    g_peak_live = g_live_bytes;  // (the cap starts over)
   }
   for (const PoolBlock& b : drop) free_block(b);
 }
