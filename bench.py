@@ -84,11 +84,11 @@ def batched_leg(knnd, synth, torch, steps):
     """The batched workload (512 instances of uneven n, d, K) as one batched
     call (rounds after the third replayed from captured graphs, each group a
     branch of its own; join schedules chosen by the library's tuner on the
-    warm-up call), next to the
-    same instances run one by one through knnd_build_ex; device-resident
-    points, plain FP64 keys.  Also timed: the tuner choosing the precision
-    form per group (KNND_PREC_AUTO), and the call with rounds enqueued
-    kernel by kernel (no graphs)."""
+    warm-up call) with the tuner also choosing each group's precision form
+    (KNND_PREC_AUTO: exact FP64 or split BF16 with FP64 rescue, the same
+    lists either way); device-resident points.  Also timed: the exact form
+    throughout, the same with rounds enqueued kernel by kernel (no graphs),
+    and the instances one by one through knnd_build_ex."""
     import tempfile
     tune_file = os.path.join(tempfile.mkdtemp(prefix="knnd_tune_"), "tune.txt")
     os.environ["KNND_TUNE_CACHE"] = tune_file
@@ -108,7 +108,7 @@ def batched_leg(knnd, synth, torch, steps):
 
     prm = knnd.default_params(precision=knnd.KNND_PREC_FP64)
     batched_s, outs = timed_calls(prm, steps)
-    auto_s, _ = timed_calls(knnd.default_params(precision=knnd.KNND_PREC_AUTO), steps)
+    auto_s, outs_auto = timed_calls(knnd.default_params(precision=knnd.KNND_PREC_AUTO), steps)
     eager_s, _ = timed_calls(knnd.default_params(precision=knnd.KNND_PREC_FP64, flags=knnd.KNND_FLAG_NO_GRAPH),
                              max(1, steps // 2))
     evals = sum(s["evals_alg"] for o in outs for s in o["stats"])
@@ -120,21 +120,25 @@ def batched_leg(knnd, synth, torch, steps):
     torch.cuda.synchronize()
     single_s = time.perf_counter() - t
     assert ev1 == evals, "batched and one-by-one evaluation counts differ"
+    for a, b in zip(outs, outs_auto):  # the tuned precision form gives the same lists
+        assert np.array_equal(a["idx"].cpu().numpy(), b["idx"].cpu().numpy()), "tuned form differs"
     return {"workload": f"{len(inst)} instances, n in [500, 20000], d+1 in [4, 21], K in {{8,16,32}}, "
                         f"base seed {synth.BATCH_BASE_SEED}, {sum(p.shape[0] for p, *_ in inst)} points",
-            "batched_ms": round(1e3 * batched_s, 2), "one_by_one_ms": round(1e3 * single_s, 2),
-            "speedup": round(single_s / batched_s, 3), "evals_alg": evals,
-            "value": evals / batched_s, "unit": "evals/s",
-            "auto_precision_ms": round(1e3 * auto_s, 2), "no_graph_ms": round(1e3 * eager_s, 2),
-            "max_rounds": max(o["rounds"] for o in outs), "tuner": read_tuner_file(tune_file)}
+            "batched_ms": round(1e3 * auto_s, 2), "value": evals / auto_s, "unit": "evals/s",
+            "form": "precision form and join schedules per group chosen by the library's tuner",
+            "exact_form_ms": round(1e3 * batched_s, 2), "no_graph_ms": round(1e3 * eager_s, 2),
+            "one_by_one_ms": round(1e3 * single_s, 2),
+            "speedup_exact_over_one_by_one": round(single_s / batched_s, 3),
+            "evals_alg": evals, "max_rounds": max(o["rounds"] for o in outs), "tuner": read_tuner_file(tune_file)}
 
 
 def share_leg(knnd, Pd, d, K, seed, precision, shares=8, reps=3):
     """One GPU's share of a descent split by receivers over `shares` GPUs:
     round 2 (from the graph a full round 1 left) restricted to the first
     1/shares of the receivers, against the same round over all of them.  The
-    share still builds the reverse lists of the whole graph and runs every
-    hub, as each GPU would after an all-gather of the lists.  Device time of
+    share builds the reverse lists it reads (edges from or to its receivers)
+    and runs every hub, as each GPU would after an all-gather of the lists.
+    Device time of
     the round from the library's HIP events; median of `reps`."""
     n = Pd.shape[0]
     prm = knnd.default_params(precision=precision)
