@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define KNND_ABI_VERSION 6
+#define KNND_ABI_VERSION 7
 
 typedef enum {
     KNND_OK = 0,

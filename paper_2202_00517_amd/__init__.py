@@ -43,7 +43,7 @@ EXPORTED = [
 KNND_NOALLOC_MAX_BYTES = 256 << 20
 
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 
 class knnd_params(ctypes.Structure):
@@ -92,6 +92,10 @@ def lib():
         raise RuntimeError(f"{LIB_PATH} is missing; build it first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")
     L = ctypes.CDLL(LIB_PATH)
+    L.knnd_abi_version.restype = ctypes.c_int
+    if L.knnd_abi_version() != ABI_VERSION:  # (before binding names an old library may lack)
+        raise RuntimeError(f"{LIB_PATH} has ABI version {L.knnd_abi_version()}, this binding "
+                           f"expects {ABI_VERSION}; rebuild the library")
     vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
     P = ctypes.POINTER
     sig = {
@@ -124,9 +128,6 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    if L.knnd_abi_version() != ABI_VERSION:
-        raise RuntimeError(f"{LIB_PATH} has ABI version {L.knnd_abi_version()}, this binding "
-                           f"expects {ABI_VERSION}; rebuild the library")
     _lib = L
     return L
 
