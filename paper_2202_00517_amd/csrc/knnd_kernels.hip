@@ -1514,7 +1514,7 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
 // thread in flight.
 template <int CAP, int MODE>
 constexpr int recv_waves_per_eu() {
-  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? (MODE == 2 ? 4 : 3) : (CAP == 8192 ? 4 : 1));
+  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? 4 : (CAP == 8192 ? 4 : 1));
 }
 
 // GRD: the class sizes its tables optimistically and hands a receiver that
@@ -1529,7 +1529,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   constexpr bool MIX = MODE == 2;  // cross terms from MFMA, exact keys only where needed
   constexpr int NT = NW * 64;
   constexpr bool GLOB = (CAP == 0);
-  constexpr bool BIG = (CAP >= 8192);  // table in LDS, candidate list in global memory
+  constexpr bool BIG = CAP >= 8192 || (CAP == 4096 && MODE == 1);  // table in LDS, candidate list in global memory
   constexpr bool GUARD = GRD;          // optimistically sized table (see k_bin)
   constexpr int OVF = CAP > 8192 ? NCLASS - 1 : 4;  // the class that redoes an overflowing receiver
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
@@ -1537,7 +1537,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   // occurrences per thread in flight (the 16384- and 32768-slot classes are
   // held to one or two blocks per CU by their tables, which leaves registers
   // for sixteen)
-  constexpr int U = (GLOB || CAP <= 2048 || CAP == 8192 || (CAP == 4096 && MODE == 2)) ? 4 : (CAP >= 16384 ? 16 : 8);
+  constexpr int U = (GLOB || CAP <= 8192) ? 4 : 16;
   // a guarded class overshoots LIMIT by at most one batch (U per thread)
   static_assert(!BIG || LIMIT + U * NT <= BIG_CAND, "candidate list of the big classes too small");
   // occurrence counter: T < 2^32 in the LDS classes (their binning bounds
@@ -2602,7 +2602,7 @@ static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
     auto kern = k_recv<CAP, PT, MODE, NWC, GRD>;
     const int per_cu = occupancy<k_recv<CAP, PT, MODE, NWC, GRD>, NWC * 64>();
     int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
-    if (CAP >= 8192) grid = std::min(grid, c.bblocks);  // one global candidate region per block
+    if (CAP >= 8192 || (CAP == 4096 && MODE == 1)) grid = std::min(grid, c.bblocks);  // one global candidate region per block
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NWC * 64), 0, c.stream, a, c.class_list, c.class_count, cls);
     return hipGetLastError();
   }
