@@ -10,10 +10,14 @@
 
 namespace knnd {
 
-// Receiver classes by hash-table capacity: 512 << k slots for k = 0..6 in LDS
-// (classes 5 and 6 keep their candidate lists in global memory), class 7 in
-// global memory for very large co-friend lists.
-constexpr int NCLASS = 8;
+// Receiver classes by hash-table capacity, tables in LDS: 512 << k slots for
+// classes k = 0..4, MID_CAP slots for class 5 (not a power of two: a 46 KB
+// table leaves room for three blocks per CU), 16384 and 32768 slots for
+// classes 6 and 7; classes 4..7 (and the exact form's class 3) keep their
+// candidate lists in global memory; class 8 has its table there too, for
+// very large co-friend lists.
+constexpr int NCLASS = 9;
+constexpr uint32_t MID_CAP = 11776;
 constexpr int BIG_CAND = 24576;  // candidate-list entries per block of the big LDS classes
 constexpr int HUB_MAXD = 64;     // register hub kernel up to this many coordinates;
                                  // P and L carry HUB_MAXD zeroed elements of tail padding

@@ -597,10 +597,12 @@ __global__ __launch_bounds__(256) void k_bin(const int64_t* __restrict__ rowptr,
         // a receiver that overflows to the global-memory class.
         const int64_t T = c + (int64_t)K * K + c * K;
         const int64_t est = (min(T, n - 1 - K) * 5) / 8 + K + 1;
-        if (est <= (int64_t)(CLASS_CAP_MIN << 5) * 5 / 8)
+        if (est <= (int64_t)MID_CAP * 5 / 8)
           cls = 5;
-        else if (est <= (int64_t)(CLASS_CAP_MIN << 6) * 5 / 8)
+        else if (est <= (int64_t)(CLASS_CAP_MIN << 5) * 5 / 8)
           cls = 6;
+        else if (est <= (int64_t)(CLASS_CAP_MIN << 6) * 5 / 8)
+          cls = 7;
         else
           cls = NCLASS - 1;
       }
@@ -1304,10 +1306,30 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
 // was a candidate then too and lost to K entries that are still at least as
 // good, so it cannot enter: it is counted but not evaluated.
 // ---------------------------------------------------------------------------
+// Table geometry: a power-of-two table takes its slot from the hash's low
+// bits and probes on modulo its size (m = size - 1); a table of another size
+// (NP2) scales the hash to [0, size) and wraps explicitly (m = size).
+template <bool NP2 = false>
+__device__ __forceinline__ uint32_t tab_slot(uint32_t z, uint32_t m) {
+  const uint32_t h0 = z * 0x9E3779B1u;
+  const uint32_t h = h0 ^ (h0 >> 15);
+  if constexpr (NP2)
+    return (uint32_t)(((uint64_t)h * m) >> 32);
+  else
+    return h & m;
+}
+template <bool NP2 = false>
+__device__ __forceinline__ uint32_t tab_next(uint32_t h, uint32_t m) {
+  if constexpr (NP2)
+    return h + 1 == m ? 0u : h + 1;
+  else
+    return (h + 1) & m;
+}
+
+template <bool NP2 = false>
 __device__ __forceinline__ int tab_insert(uint32_t* tab, uint32_t mask, uint32_t z, uint32_t flag) {
   // returns bit 0: first insertion of z; bit 1: this call marked z NEW first
-  uint32_t h = z * 0x9E3779B1u;
-  h = (h ^ (h >> 15)) & mask;
+  uint32_t h = tab_slot<NP2>(z, mask);
   for (;;) {
     const uint32_t old = atomicCAS(&tab[h], EMPTY, z | flag);
     if (old == EMPTY) return 1 | ((flag & NEWBIT) ? 2 : 0);
@@ -1318,12 +1340,13 @@ __device__ __forceinline__ int tab_insert(uint32_t* tab, uint32_t mask, uint32_t
       }
       return 0;
     }
-    h = (h + 1) & mask;
+    h = tab_next<NP2>(h, mask);
   }
 }
 
 // The rest of tab_insert after its first probe at slot h returned `old`
 // (lets a thread issue the first probes of several ids back to back).
+template <bool NP2 = false>
 __device__ __forceinline__ int tab_finish(uint32_t* tab, uint32_t mask, uint32_t z, uint32_t flag, uint32_t h,
                                           uint32_t old) {
   for (;;) {
@@ -1335,14 +1358,9 @@ __device__ __forceinline__ int tab_finish(uint32_t* tab, uint32_t mask, uint32_t
       }
       return 0;
     }
-    h = (h + 1) & mask;
+    h = tab_next<NP2>(h, mask);
     old = atomicCAS(&tab[h], EMPTY, z | flag);
   }
-}
-
-__device__ __forceinline__ uint32_t tab_slot(uint32_t z, uint32_t mask) {
-  const uint32_t h = z * 0x9E3779B1u;
-  return (h ^ (h >> 15)) & mask;
 }
 
 // Exclusive prefix sum of one small int per lane across the wave.
@@ -1514,7 +1532,7 @@ __device__ __forceinline__ void write_row(const JoinArgs& a, int64_t x, int K, i
 // thread in flight.
 template <int CAP, int MODE>
 constexpr int recv_waves_per_eu() {
-  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? 4 : (CAP == 8192 ? 4 : 1));
+  return (CAP > 0 && CAP <= 2048) ? 4 : (CAP == 4096 ? 4 : (CAP == 8192 ? 4 : (CAP == (int)MID_CAP ? 3 : 1)));
 }
 
 // GRD: the class sizes its tables optimistically and hands a receiver that
@@ -1531,13 +1549,15 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   constexpr bool GLOB = (CAP == 0);
   constexpr bool BIG = CAP >= 8192 || (CAP == 4096 && MODE == 1);  // table in LDS, candidate list in global memory
   constexpr bool GUARD = GRD;          // optimistically sized table (see k_bin)
-  constexpr int OVF = CAP > 8192 ? NCLASS - 1 : 4;  // the class that redoes an overflowing receiver
+  // the class that redoes an overflowing receiver
+  constexpr int OVF = CAP == (int)MID_CAP ? 6 : (CAP > 8192 ? NCLASS - 1 : 4);
+  constexpr bool NP2 = CAP > 0 && (CAP & (CAP - 1)) != 0;  // (the MID_CAP class)
   constexpr int CC = (GLOB || BIG) ? 1 : CAP / 2;
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
   // occurrences per thread in flight (the 16384- and 32768-slot classes are
   // held to one or two blocks per CU by their tables, which leaves registers
   // for sixteen)
-  constexpr int U = (GLOB || CAP <= 8192) ? 4 : 16;
+  constexpr int U = (GLOB || CAP <= 8192) ? 4 : (CAP == (int)MID_CAP ? 8 : 16);
   // a guarded class overshoots LIMIT by at most one batch (U per thread)
   static_assert(!BIG || LIMIT + U * NT <= BIG_CAND, "candidate list of the big classes too small");
   // occurrence counter: T < 2^32 in the LDS classes (their binning bounds
@@ -1607,7 +1627,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       cap = CLASS_CAP_MIN;
       while ((int64_t)cap < need2) cap <<= 1;
     }
-    const uint32_t mask = cap - 1;
+    const uint32_t mask = NP2 ? cap : cap - 1;  // (table geometry, see tab_slot)
     int64_t item_evals = 0;
     // the round-start K-th key: a candidate with a larger key cannot enter
     // (the paper's compare-to-last, Section 4.2)
@@ -1651,9 +1671,9 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       const uint32_t raw = a.F[x * a.Ks + tid];
       s_fx[tid] = raw;
       s_kx[tid] = a.keys[x * K + tid];
-      tab_insert(tab, mask, raw & IDMASK, EXCLBIT);
+      tab_insert<NP2>(tab, mask, raw & IDMASK, EXCLBIT);
     } else if (tid == K) {
-      tab_insert(tab, mask, (uint32_t)x, EXCLBIT);
+      tab_insert<NP2>(tab, mask, (uint32_t)x, EXCLBIT);
     }
     __syncthreads();
     // C: enumerate candidate occurrences, U per thread in flight.  The key
@@ -1730,14 +1750,15 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       for (int u = 0; u < U; ++u) {
         old0[u] = 0;
         if (t0 + tid + NT * u < (IT)T)
-          old0[u] = atomicCAS(&tab[tab_slot(z[u], mask)], EMPTY, z[u] | (a.skip ? nw[u] : NEWBIT));
+          old0[u] = atomicCAS(&tab[tab_slot<NP2>(z[u], mask)], EMPTY, z[u] | (a.skip ? nw[u] : NEWBIT));
       }
       int fresh = 0;
       uint32_t newm = 0;  // bit u: occurrence u marked its candidate new first
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (t0 + tid + NT * u < (IT)T) {
-          const int r = tab_finish(tab, mask, z[u], a.skip ? nw[u] : NEWBIT, tab_slot(z[u], mask), old0[u]);
+          const int r =
+              tab_finish<NP2>(tab, mask, z[u], a.skip ? nw[u] : NEWBIT, tab_slot<NP2>(z[u], mask), old0[u]);
           fresh += r & 1;
           newm |= (uint32_t)((r >> 1) & 1) << u;
         }
@@ -2648,9 +2669,10 @@ static hipError_t launch_recv_all(const Ctx& c, const JoinArgs& a) {
     return e;
   }
   if ((e = launch_recv_class<CLASS_CAP_MIN << 4, PT, MODE>(c, a, 4)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 5, PT, MODE>(c, a, 5)) != hipSuccess) return e;
-  if ((e = launch_recv_class<CLASS_CAP_MIN << 6, PT, MODE>(c, a, 6)) != hipSuccess) return e;
-  return launch_recv_class<0, PT, MODE>(c, a, 7);
+  if ((e = launch_recv_class<(int)MID_CAP, PT, MODE>(c, a, 5)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 5, PT, MODE>(c, a, 6)) != hipSuccess) return e;
+  if ((e = launch_recv_class<CLASS_CAP_MIN << 6, PT, MODE>(c, a, 7)) != hipSuccess) return e;
+  return launch_recv_class<0, PT, MODE>(c, a, NCLASS - 1);
 }
 
 template <int MAXD, typename PT, int CK>
