@@ -811,16 +811,18 @@ int run_round(Ctx& c, knnd_round_stats* st) {
   const bool carry = c.tracking && c.track_ok && !c.no_skip_next &&
                      !(c.flags & (KNND_FLAG_NO_SKIP | KNND_FLAG_NO_CARRY)) && c.last_updates * 1000 <= nK;
   KNND_HIP(knnd::launch_bin(c, carry));
-  if (!full) KNND_HIP(knnd::launch_keep_rows(c));
   KNND_HIP(rec(c.evj0, c.stream));
   KNND_HIP(knnd::launch_join_hub(c, c.dstats));
   KNND_HIP(rec(c.evh, c.stream));
   KNND_HIP(knnd::launch_join_recv(c, c.dstats));
   KNND_HIP(rec(c.evj1, c.stream));
   if (c.tracking) KNND_HIP(knnd::launch_track(c));
-  KNND_HIP(knnd::launch_fcr(c, c.F[c.cur ^ 1], c.round + 1, c.dstats + knnd::STAT_HITS));
+  // (a restricted round copies its receivers' lists back over the
+  // round-start ones instead of carrying every other list over)
+  if (!full) KNND_HIP(knnd::launch_put_rows(c));
+  KNND_HIP(knnd::launch_fcr(c, c.F[full ? c.cur ^ 1 : c.cur], c.round + 1, c.dstats + knnd::STAT_HITS));
   KNND_HIP(rec(c.ev1, c.stream));
-  c.cur ^= 1;
+  if (full) c.cur ^= 1;
   c.round += 1;
   c.no_skip_next = !full;
   c.track_ok = c.tracking;

@@ -239,7 +239,7 @@ hipError_t launch_join_hub(const Ctx& c, int64_t* stats);
 hipError_t launch_join_recv(const Ctx& c, int64_t* stats);
 hipError_t launch_prep_mixed(const Ctx& c, unsigned long long* maxbits);
 hipError_t launch_strip(const Ctx& c, const uint32_t* F, int32_t* out);
-hipError_t launch_keep_rows(const Ctx& c);
+hipError_t launch_put_rows(const Ctx& c);
 hipError_t launch_track(const Ctx& c);
 hipError_t launch_load_idx(const Ctx& c, const int32_t* idx, uint32_t* F, int32_t* bad);
 // batched groups

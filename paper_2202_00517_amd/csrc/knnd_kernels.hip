@@ -63,19 +63,20 @@ __global__ __launch_bounds__(256) void k_track(const uint32_t* __restrict__ Fo, 
   }
 }
 
-// A round restricted to the receivers [own0, own1) carries every other list
-// over unchanged, its edges marked new (as for a snapshot loaded from
-// outside; the round after a restricted one skips no pair anyway).
-__global__ void k_keep_rows(const uint32_t* __restrict__ F, const double* __restrict__ keys, int64_t n, int K,
-                            int Ks, int64_t own0, int64_t own1, uint32_t* __restrict__ Fn,
-                            double* __restrict__ keysn) {
-  const int64_t cnt = n * K;
+// A round restricted to the receivers [own0, own1) writes their new lists
+// into the idle buffer; they are copied back over their round-start lists,
+// which then hold the whole graph after the round (every other list, flags
+// included, is left as it was: the round after a restricted one skips no
+// pair, so no flag of its snapshot is read).
+__global__ void k_put_rows(const uint32_t* __restrict__ Fn, const double* __restrict__ keysn, int64_t own0,
+                           int64_t own1, int K, int Ks, uint32_t* __restrict__ F, double* __restrict__ keys) {
+  const int64_t cnt = (own1 - own0) * K;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t x = i / K;
-    if (x >= own0 && x < own1) continue;
-    const int64_t j = i - x * K;
-    Fn[x * Ks + j] = (F[x * Ks + j] & IDMASK) | NEWBIT;
-    keysn[i] = keys[i];
+    const int64_t q = i / K;
+    const int64_t x = own0 + q;
+    const int64_t j = i - q * K;
+    F[x * Ks + j] = Fn[x * Ks + j];
+    keys[x * K + j] = keysn[x * K + j];
   }
 }
 // F = idx | NEWBIT (an externally supplied snapshot: every edge counts as
@@ -2865,10 +2866,10 @@ hipError_t launch_track(const Ctx& c) {
   return hipGetLastError();
 }
 
-hipError_t launch_keep_rows(const Ctx& c) {
-  const int64_t cnt = c.n * c.K;
-  hipLaunchKernelGGL(k_keep_rows, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, c.F[c.cur],
-                     c.keys[c.cur], c.n, c.K, c.Ks, c.own0, c.own1, c.F[c.cur ^ 1], c.keys[c.cur ^ 1]);
+hipError_t launch_put_rows(const Ctx& c) {
+  const int64_t cnt = (c.own1 - c.own0) * c.K;
+  hipLaunchKernelGGL(k_put_rows, dim3(grid_for(cnt, 256, 8192)), dim3(256), 0, c.stream, c.F[c.cur ^ 1],
+                     c.keys[c.cur ^ 1], c.own0, c.own1, c.K, c.Ks, c.F[c.cur], c.keys[c.cur]);
   return hipGetLastError();
 }
 
