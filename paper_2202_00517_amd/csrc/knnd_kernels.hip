@@ -1557,8 +1557,8 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   constexpr int LIMIT = CAP / 2 + CAP / 8;  // distinct entries before a guarded class gives up
   // occurrences per thread in flight (the 16384- and 32768-slot classes are
   // held to one or two blocks per CU by their tables, which leaves registers
-  // for sixteen)
-  constexpr int U = (GLOB || CAP <= 8192) ? 4 : (CAP == (int)MID_CAP ? 8 : 16);
+  // for sixteen; eight in the 32768-slot class's eight-wave blocks)
+  constexpr int U = (GLOB || CAP <= 8192) ? 4 : (CAP == (int)MID_CAP || NW >= 8 ? 8 : 16);
   // a guarded class overshoots LIMIT by at most one batch (U per thread)
   static_assert(!BIG || LIMIT + U * NT <= BIG_CAND, "candidate list of the big classes too small");
   // occurrence counter: T < 2^32 in the LDS classes (their binning bounds
@@ -2619,8 +2619,11 @@ static hipError_t launch_recv_class(const Ctx& c, const JoinArgs& a, int cls) {
                        c.class_count, cls);
     return hipGetLastError();
   } else {
-    // small tables: two waves per receiver, twice the receivers in flight
-    constexpr int NWC = CAP <= SMALL_NW_CAP ? 2 : 4;
+    // small tables: two waves per receiver, twice the receivers in flight;
+    // the 32768-slot table leaves room for one block per CU, which then
+    // takes eight waves (its registers allow two per SIMD): its few, long
+    // receivers each finish in about half the time
+    constexpr int NWC = CAP <= SMALL_NW_CAP ? 2 : (CAP == (CLASS_CAP_MIN << 6) ? 8 : 4);
     auto kern = k_recv<CAP, PT, MODE, NWC, GRD>;
     const int per_cu = occupancy<k_recv<CAP, PT, MODE, NWC, GRD>, NWC * 64>();
     int grid = (int)std::min<int64_t>(c.n, (int64_t)per_cu * c.num_cu);
