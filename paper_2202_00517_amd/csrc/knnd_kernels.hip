@@ -1434,31 +1434,32 @@ __device__ __forceinline__ double mix_eps(const JoinArgs& a, double Sx, double k
   return fma(a.eps_relq, cabs + a.eps_abs, a.eps_abs + 0x1p-44 * (fabs(Sx) + cabs + 1.0));
 }
 
-// An upper bound T on the K-th smallest of {old keys} u {k~_i + eps_i}: the
-// largest value in the first bins (of a monotone histogram over values <= hi)
-// that together hold at least K values.
-template <int NW, typename KGet>
-__device__ double kth_upper_bound(int K, int ncand, const double* kx, double hi, KGet ktilde,
-                                  const JoinArgs& a, double Sx, int32_t* hist, int* s_bstar, int64_t* s_red,
-                                  double* s_dred) {
+// An upper bound T on the K-th smallest of {old keys} u {k~_i + eps_i}: a
+// monotone histogram over [lo, hi] of the values <= hi (lo: the smallest of
+// them, from the smallest listed k~, as k~ + eps grows with k~), and the
+// first bin b* whose prefix count reaches K.  EDGE: every value binned at or
+// below b* is below the upper edge of bin b* + 1 (one bin of slack for the
+// rounding of the binning), which is returned (or hi, if smaller);
+// otherwise one more pass returns the largest such value.  Clears *s_ns for
+// the compaction that follows.
+template <int NW, bool EDGE, typename KGet>
+__device__ double kth_upper_bound(int K, int ncand, const double* kx, double hi, double kmin, KGet ktilde,
+                                  const JoinArgs& a, double Sx, int32_t* hist, int* s_bstar, int* s_ns,
+                                  int64_t* s_red, double* s_dred) {
   constexpr int NT = NW * 64;
   const int tid = threadIdx.x;
-  auto ub = [&](int i) {
-    const double kt = ktilde(i);
-    return kt + mix_eps(a, Sx, kt);
-  };
-  double lo = kx[0];
-  for (int i = tid; i < ncand; i += NT) lo = fmin(lo, ub(i));
-  lo = block_min<NW>(lo, s_dred);
+  auto ub = [&](double kt) { return kt + mix_eps(a, Sx, kt); };
+  const double lo = fmin(kx[0], ub(kmin));
   const double scale = hi > lo ? (double)SEL_BINS / (hi - lo) : 0.0;
   auto bin_of = [&](double k) {
     const int b = (int)((k - lo) * scale);
     return b < 0 ? 0 : (b >= SEL_BINS ? SEL_BINS - 1 : b);
   };
   for (int b = tid; b < SEL_BINS; b += NT) hist[b] = 0;
+  if (tid == 0) *s_ns = 0;
   __syncthreads();
   for (int i = tid; i < ncand; i += NT) {
-    const double u = ub(i);
+    const double u = ub(ktilde(i));
     if (u <= hi) atomicAdd(&hist[bin_of(u)], 1);
   }
   if (tid < K) atomicAdd(&hist[bin_of(kx[tid])], 1);
@@ -1483,13 +1484,18 @@ __device__ double kth_upper_bound(int K, int ncand, const double* kx, double hi,
   }
   __syncthreads();
   const int bstar = *s_bstar;
-  double m = -INFINITY;
-  for (int i = tid; i < ncand; i += NT) {
-    const double u = ub(i);
-    if (u <= hi && bin_of(u) <= bstar) m = fmax(m, u);
+  if constexpr (EDGE) {
+    if (scale == 0.0 || bstar >= SEL_BINS - 2) return hi;
+    return fmin(hi, lo + (double)(bstar + 2) / scale);
+  } else {
+    double m = -INFINITY;
+    for (int i = tid; i < ncand; i += NT) {
+      const double u = ub(ktilde(i));
+      if (u <= hi && bin_of(u) <= bstar) m = fmax(m, u);
+    }
+    if (tid < K && bin_of(kx[tid]) <= bstar) m = fmax(m, kx[tid]);
+    return -block_min<NW>(-m, s_dred);
   }
-  if (tid < K && bin_of(kx[tid]) <= bstar) m = fmax(m, kx[tid]);
-  return -block_min<NW>(-m, s_dred);
 }
 
 // Lanes 0..K-1 of a wave write receiver x's new list.  An index outside
@@ -1596,6 +1602,12 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
   __shared__ int s_iev, s_ipf, s_irs;  // batched groups: this receiver's counters
   __shared__ int64_t s_red[NW];
   __shared__ double s_dred[NW];
+  __shared__ float s_cmax[MODE == 2 ? NW : 1];
+  // The mixed form's selection of long lists takes the smallest listed k~
+  // from the enumeration and bounds Theta by a bin edge, two passes over the
+  // list fewer; the 11776-slot class keeps both passes, whose registers it
+  // cannot spare in its enumeration.
+  constexpr bool FASTSEL = CAP != (int)MID_CAP;
 
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -1682,6 +1694,9 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
     // key is loaded together with the candidate id, before the table says
     // whether this occurrence is the one that lists the candidate (slots of
     // edges the hub kernel skipped hold stale values that are never used).
+    // (mixed form) the largest cross term C~ this thread listed: the
+    // smallest listed k~ = S(x) - C~ (one FP32 register through the loop)
+    float cmax_t = -INFINITY;
     for (IT t0 = 0; t0 < (IT)T; t0 += U * NT) {
       // Every load below is issued unconditionally (an occurrence that does
       // not need it reads entry 0, which always exists) so that all U loads
@@ -1773,7 +1788,10 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       for (int u = 0; u < U; ++u) {
         if (!((newm >> u) & 1)) continue;
         const double kv = key_of(u);
-        if (!SEG || (MIX ? kv - mix_eps(a, Sx, kv) <= tau0 : kv <= tau0)) appm |= 1u << u;
+        if (!SEG || (MIX ? kv - mix_eps(a, Sx, kv) <= tau0 : kv <= tau0)) {
+          appm |= 1u << u;
+          if (MIX && FASTSEL) cmax_t = fmaxf(cmax_t, (float)kr[u]);
+        }
       }
       {
         const int napp = __popc(appm);
@@ -1811,6 +1829,11 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       }
     }
     if (a.vcnt && item_evals) atomicAdd(&s_iev, (int)item_evals);
+    if (MIX && FASTSEL) {
+#pragma unroll
+      for (int o = WAVE / 2; o > 0; o >>= 1) cmax_t = fmaxf(cmax_t, __shfl_xor(cmax_t, o, WAVE));
+      if (lane == 0) s_cmax[wave] = cmax_t;
+    }
     __syncthreads();
     if (GUARD && s_over) {  // table or list too small: a larger class redoes this receiver
       if (tid == 0) {
@@ -1857,10 +1880,22 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       // it.  Every other candidate gets its canonical FP64 key (the rescue)
       // and only those are merged with the old list.
       const bool all = ncand <= 2 * WAVE;  // short list: rescue every candidate
-      if (tid == 0) s_ns = all ? ncand : 0;
-      if (!all) {
-        const double theta =
-            kth_upper_bound<NW>(K, ncand, kx, tau0, ktil, a, Sx, s_hist, &s_bstar, s_red, s_dred);
+      if (all) {
+        if (tid == 0) s_ns = ncand;
+      } else {
+        double kmin;  // the smallest listed k~
+        if constexpr (FASTSEL) {
+          float cmax = s_cmax[0];
+#pragma unroll
+          for (int w = 1; w < NW; ++w) cmax = fmaxf(cmax, s_cmax[w]);
+          kmin = Sx - (double)cmax;
+        } else {
+          kmin = INFINITY;
+          for (int i = tid; i < ncand; i += NT) kmin = fmin(kmin, ktil(i));
+          kmin = block_min<NW>(kmin, s_dred);
+        }
+        const double theta = kth_upper_bound<NW, FASTSEL>(K, ncand, kx, tau0, kmin, ktil, a, Sx, s_hist, &s_bstar,
+                                                           &s_ns, s_red, s_dred);
         if (tid == 0) s_theta = theta;
         // compact the rescue set (its positions in the candidate list)
         for (int i = tid; i < ncand; i += NT) {
@@ -1876,8 +1911,8 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       my_resc += tid == 0 ? ns : 0;
       if (tid == 0) s_irs = ns;  // (read after the item's last barrier)
       if (ns <= SEL_SURV) {
-        // canonical keys of the rescue set, then wave 0 merges them into the
-        // old list
+        // canonical keys of the rescue set (one gather per thread), then
+        // wave 0 merges them into the old list
         for (int j = tid; j < ns; j += NT) {
           const uint32_t z = cid[all ? j : s_si[j]];
           s_sk[j] = key_bits(canonical_key_lds(s_xr, s_lr, a.L + (int64_t)z * Dp, D));
