@@ -1920,7 +1920,34 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
         }
         __syncthreads();
         done = true;
-        if (wave == 0) {
+        if constexpr (FASTSEL) {
+          // each wave merges its own 64-wide batches (wave 0 into the old
+          // list), then wave 0 merges the other waves' lists
+          uint64_t lk = KEY_SENTINEL;
+          uint32_t li = IDMASK;
+          if (wave == 0 && lane < K) {
+            lk = key_bits(kx[lane]);
+            li = s_fx[lane] & IDMASK;
+          }
+          for (int b0 = wave * WAVE; b0 < ns; b0 += NT) {
+            const bool ok = b0 + lane < ns;
+            uint64_t bk = ok ? s_sk[b0 + lane] : KEY_SENTINEL;
+            uint32_t bi = ok ? s_si[b0 + lane] : IDMASK;
+            wave_sort(bk, bi);
+            wave_merge(lk, li, bk, bi);
+          }
+          const int nwl = min(NW, (ns + WAVE - 1) / WAVE);  // waves holding a list (block-uniform)
+          if (nwl > 1) {
+            if (wave > 0 && wave < nwl) {
+              s_lk[wave - 1][lane] = lk;
+              s_li[wave - 1][lane] = li;
+            }
+            __syncthreads();
+            if (wave == 0)
+              for (int w = 0; w < nwl - 1; ++w) wave_merge(lk, li, s_lk[w][lane], s_li[w][lane]);
+          }
+          if (wave == 0) write_row(a, x, K, lane, lk, li, lane < K ? s_fx[lane] : 0u, my_upd, my_err);
+        } else if (wave == 0) {  // (the 11776-slot class: wave 0 alone, for its registers)
           uint64_t lk = lane < K ? key_bits(kx[lane]) : KEY_SENTINEL;
           uint32_t li = lane < K ? (s_fx[lane] & IDMASK) : IDMASK;
           for (int b0 = 0; b0 < ns; b0 += WAVE) {
