@@ -1646,6 +1646,27 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
     // (the paper's compare-to-last, Section 4.2)
     const double tau0 = a.keys[x * K + K - 1];
     const double Sx = MIX ? a.S[x] : 0.0;  // sum_i x_i log x_i
+    // x's list and keys, its co-friends (a list of at most NT entries is
+    // staged in LDS, so that enumerating friends of co-friends needs one
+    // global round trip instead of two) and, mixed, x's row and logs for the
+    // rescue: loaded before the table is cleared, so that their latency
+    // overlaps the clearing and its barrier
+    const bool staged = c <= NT;
+    uint32_t pcol = 0, pcsl = 0, praw = 0;
+    double pkey = 0.0;
+    if (staged && tid < c) {
+      pcol = a.col[rp + tid];
+      pcsl = a.colslot[rp + tid];
+    }
+    if (tid < K) {
+      praw = a.F[x * a.Ks + tid];
+      pkey = a.keys[x * K + tid];
+    }
+    double xr_pre = 0.0, lr_pre = 0.0;  // (written to LDS after the enumeration)
+    if (MIX && tid < D) {
+      xr_pre = (double)P[x * D + tid];
+      lr_pre = a.L[x * Dp + tid];
+    }
 
     // A: clear
     if (GLOB) {
@@ -1665,26 +1686,15 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
       s_tau = key_bits(a.keys[x * K + K - 1]);
     }
     __syncthreads();
-    // x's row and logs for the rescue: loaded now, written to LDS after the
-    // enumeration (their latency overlaps phases B and C)
-    double xr_pre = 0.0, lr_pre = 0.0;
-    if (MIX && tid < D) {
-      xr_pre = (double)P[x * D + tid];
-      lr_pre = a.L[x * Dp + tid];
-    }
-    // B: excluded entries; a co-friend list of at most NT entries is staged
-    // in LDS (its loads overlap those of x's own list), so that enumerating
-    // friends of co-friends needs one global round trip instead of two
-    const bool staged = c <= NT;
+    // B: excluded entries; the staged co-friend list
     if (staged && tid < c) {
-      s_col[tid] = a.col[rp + tid];
-      s_csl[tid] = a.colslot[rp + tid];
+      s_col[tid] = pcol;
+      s_csl[tid] = (uint8_t)pcsl;
     }
     if (tid < K) {
-      const uint32_t raw = a.F[x * a.Ks + tid];
-      s_fx[tid] = raw;
-      s_kx[tid] = a.keys[x * K + tid];
-      tab_insert<NP2>(tab, mask, raw & IDMASK, EXCLBIT);
+      s_fx[tid] = praw;
+      s_kx[tid] = pkey;
+      tab_insert<NP2>(tab, mask, praw & IDMASK, EXCLBIT);
     } else if (tid == K) {
       tab_insert<NP2>(tab, mask, (uint32_t)x, EXCLBIT);
     }
