@@ -77,6 +77,35 @@ __device__ __forceinline__ dd dd_mul_d(dd a, double b) {
   return quick_two_sum(p.h, p.l + a.l * b);
 }
 
+// 1/(2k+1) for k = 0..22 as double-double pairs: hi = 1/(2k+1) rounded, lo =
+// (1 - hi (2k+1)) / (2k+1) rounded (1 - hi (2k+1) is exact), the values the
+// series below would otherwise form with two divisions per term.
+static __constant__ const dd kOddRecip[23] = {
+    {0x1.0000000000000p+0, 0.0},
+    {0x1.5555555555555p-2, 0x1.5555555555555p-56},
+    {0x1.999999999999ap-3, -0x1.999999999999ap-57},
+    {0x1.2492492492492p-3, 0x1.2492492492492p-57},
+    {0x1.c71c71c71c71cp-4, 0x1.c71c71c71c71cp-58},
+    {0x1.745d1745d1746p-4, -0x1.745d1745d1746p-59},
+    {0x1.3b13b13b13b14p-4, -0x1.3b13b13b13b14p-58},
+    {0x1.1111111111111p-4, 0x1.1111111111111p-60},
+    {0x1.e1e1e1e1e1e1ep-5, 0x1.e1e1e1e1e1e1ep-61},
+    {0x1.af286bca1af28p-5, 0x1.af286bca1af28p-59},
+    {0x1.8618618618618p-5, 0x1.8618618618618p-59},
+    {0x1.642c8590b2164p-5, 0x1.642c8590b2164p-60},
+    {0x1.47ae147ae147bp-5, -0x1.eb851eb851eb8p-61},
+    {0x1.2f684bda12f68p-5, 0x1.2f684bda12f68p-59},
+    {0x1.1a7b9611a7b96p-5, 0x1.1a7b9611a7b96p-61},
+    {0x1.0842108421084p-5, 0x1.0842108421084p-60},
+    {0x1.f07c1f07c1f08p-6, -0x1.f07c1f07c1f08p-61},
+    {0x1.d41d41d41d41dp-6, 0x1.0750750750750p-60},
+    {0x1.bacf914c1bad0p-6, -0x1.bacf914c1bad0p-60},
+    {0x1.a41a41a41a41ap-6, 0x1.0690690690690p-60},
+    {0x1.8f9c18f9c18fap-6, -0x1.f3831f3831f38p-61},
+    {0x1.7d05f417d05f4p-6, 0x1.7d05f417d05f4p-62},
+    {0x1.6c16c16c16c17p-6, -0x1.f49f49f49f49fp-61},
+};
+
 __device__ inline double crlog(double x) {
   // x is finite and > 0 (validated by the caller).
   int e = 0;
@@ -103,18 +132,8 @@ __device__ inline double crlog(double x) {
   // Horner on sum_{k=0}^{22} w^k / (2k+1); w <= 0.0295, so the first omitted
   // term is below 2^-114 of the sum.
   const int N = 22;
-  dd acc;
-  {
-    const double c = 2.0 * N + 1.0;
-    const double hi = 1.0 / c;
-    acc = {hi, fma(-hi, c, 1.0) / c};
-  }
-  for (int k = N - 1; k >= 0; --k) {
-    const double c = 2.0 * k + 1.0;
-    const double hi = 1.0 / c;
-    const dd ck = {hi, fma(-hi, c, 1.0) / c};
-    acc = dd_add(dd_mul(acc, w), ck);
-  }
+  dd acc = kOddRecip[N];
+  for (int k = N - 1; k >= 0; --k) acc = dd_add(dd_mul(acc, w), kOddRecip[k]);
   dd y = dd_mul(s, acc);
   y.h *= 2.0;
   y.l *= 2.0;
