@@ -427,6 +427,27 @@ __device__ __forceinline__ uint32_t edge_raw(const uint32_t* __restrict__ F, int
   return F[(x0 + xr) * Ks + (r - xr * (uint32_t)K)];
 }
 
+// The block's histogram of the kept edges [e0, e1) over the target buckets,
+// eight edge loads per thread in flight before their table updates (a loop
+// of one load and one update each waits on every load in turn).
+constexpr int PART_UB = 8;
+__device__ __forceinline__ void part_hist(const uint32_t* __restrict__ F, int64_t e0, int64_t e1, int64_t x0,
+                                          int K, int Ks, int shift, int64_t own0, int64_t own1, int32_t* h) {
+  for (int64_t b0 = e0 + threadIdx.x; b0 < e1; b0 += (int64_t)blockDim.x * PART_UB) {
+    uint32_t v[PART_UB];
+#pragma unroll
+    for (int j = 0; j < PART_UB; ++j) {
+      const int64_t e = b0 + (int64_t)blockDim.x * j;
+      v[j] = e < e1 ? edge_raw(F, e0, x0, e, K, Ks) & IDMASK : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < PART_UB; ++j) {
+      const int64_t e = b0 + (int64_t)blockDim.x * j;
+      if (e < e1 && csr_keep(e / K, v[j], own0, own1)) atomicAdd(&h[v[j] >> shift], 1);
+    }
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_part_count(const uint32_t* __restrict__ F, int64_t nK, int K, int Ks,
                                                      int chunk, int shift, int nb, int64_t own0, int64_t own1,
                                                      unsigned long long* __restrict__ bcount) {
@@ -436,10 +457,7 @@ __global__ __launch_bounds__(1024) void k_part_count(const uint32_t* __restrict_
   const int64_t e0 = (int64_t)blockIdx.x * chunk;
   const int64_t e1 = min(e0 + chunk, nK);
   const int64_t x0 = e0 / K;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const uint32_t v = edge_raw(F, e0, x0, e, K, Ks) & IDMASK;
-    if (csr_keep(e / K, v, own0, own1)) atomicAdd(&h[v >> shift], 1);
-  }
+  part_hist(F, e0, e1, x0, K, Ks, shift, own0, own1, h);
   __syncthreads();
   for (int t = threadIdx.x; t < nb; t += blockDim.x)
     if (h[t]) atomicAdd(&bcount[t], (unsigned long long)h[t]);
@@ -478,10 +496,7 @@ __global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restric
   const int64_t e0 = (int64_t)blockIdx.x * chunk;  // chunk is a multiple of K
   const int64_t e1 = min(e0 + chunk, nK);
   const int64_t x0 = e0 / K;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const uint32_t v = edge_raw(F, e0, x0, e, K, Ks) & IDMASK;
-    if (csr_keep(e / K, v, own0, own1)) atomicAdd(&h[v >> shift], 1);
-  }
+  part_hist(F, e0, e1, x0, K, Ks, shift, own0, own1, h);
   __syncthreads();
   for (int t = threadIdx.x; t < nb; t += blockDim.x) {
     if (h[t]) base[t] = bbase[t] + (int64_t)atomicAdd(&bfill[t], (unsigned long long)h[t]);
@@ -489,17 +504,27 @@ __global__ __launch_bounds__(1024) void k_part_scatter(const uint32_t* __restric
   }
   __syncthreads();
   const uint32_t tmask = (1u << shift) - 1;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const uint32_t raw = edge_raw(F, e0, x0, e, K, Ks);
-    const uint32_t v = raw & IDMASK;
-    if (!csr_keep(e / K, v, own0, own1)) continue;
-    const int b = (int)(v >> shift);
-    const int q = atomicAdd(&h[b], 1);
-    const uint32_t r = (uint32_t)(e - e0);
-    const uint32_t xr = r / (uint32_t)K;
-    const uint64_t x = (uint64_t)(x0 + xr);
-    const uint64_t j = r - xr * (uint32_t)K;
-    T[base[b] + q] = x | (j << 30) | ((uint64_t)(raw >> 31) << 36) | ((uint64_t)(v & tmask) << 40);
+  for (int64_t b0 = e0 + threadIdx.x; b0 < e1; b0 += (int64_t)blockDim.x * PART_UB) {
+    uint32_t rw[PART_UB];
+#pragma unroll
+    for (int u = 0; u < PART_UB; ++u) {
+      const int64_t e = b0 + (int64_t)blockDim.x * u;
+      rw[u] = e < e1 ? edge_raw(F, e0, x0, e, K, Ks) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < PART_UB; ++u) {
+      const int64_t e = b0 + (int64_t)blockDim.x * u;
+      const uint32_t raw = rw[u];
+      const uint32_t v = raw & IDMASK;
+      if (e >= e1 || !csr_keep(e / K, v, own0, own1)) continue;
+      const int b = (int)(v >> shift);
+      const int q = atomicAdd(&h[b], 1);
+      const uint32_t r = (uint32_t)(e - e0);
+      const uint32_t xr = r / (uint32_t)K;
+      const uint64_t x = (uint64_t)(x0 + xr);
+      const uint64_t j = r - xr * (uint32_t)K;
+      T[base[b] + q] = x | (j << 30) | ((uint64_t)(raw >> 31) << 36) | ((uint64_t)(v & tmask) << 40);
+    }
   }
 }
 
@@ -512,9 +537,19 @@ __global__ __launch_bounds__(256) void k_bucket_csr(const uint64_t* __restrict__
   const int tb = 1 << shift;
   const int64_t lo = bbase[b], hi = bbase[b + 1];
   const int64_t v0 = (int64_t)b << shift;
+  // (eight loads per thread in flight before their table updates: a loop
+  // of one load and one update each waits on every load in turn)
+  constexpr int UB = 8;
   for (int t = threadIdx.x; t < tb; t += 256) cnt[t] = 0;
   __syncthreads();
-  for (int64_t p = lo + threadIdx.x; p < hi; p += 256) atomicAdd(&cnt[(int)(T[p] >> 40) & (tb - 1)], 1);
+  for (int64_t p0 = lo + threadIdx.x; p0 < hi; p0 += 256 * UB) {
+    uint64_t u[UB];
+#pragma unroll
+    for (int j = 0; j < UB; ++j) u[j] = p0 + 256 * j < hi ? T[p0 + 256 * j] : 0;
+#pragma unroll
+    for (int j = 0; j < UB; ++j)
+      if (p0 + 256 * j < hi) atomicAdd(&cnt[(int)(u[j] >> 40) & (tb - 1)], 1);
+  }
   __syncthreads();
   // exclusive scan: thread i owns targets [i*per, (i+1)*per)
   const int per = tb / 256;
@@ -530,11 +565,17 @@ __global__ __launch_bounds__(256) void k_bucket_csr(const uint64_t* __restrict__
     run += c;
   }
   __syncthreads();
-  for (int64_t p = lo + threadIdx.x; p < hi; p += 256) {
-    const uint64_t u = T[p];
-    const int q = atomicAdd(&cnt[(int)(u >> 40) & (tb - 1)], 1);
-    col[lo + q] = (uint32_t)(u & IDMASK) | ((uint32_t)(u >> 36) & 1u) << 31;
-    colslot[lo + q] = (uint8_t)((u >> 30) & 63u);
+  for (int64_t p0 = lo + threadIdx.x; p0 < hi; p0 += 256 * UB) {
+    uint64_t u[UB];
+#pragma unroll
+    for (int j = 0; j < UB; ++j) u[j] = p0 + 256 * j < hi ? T[p0 + 256 * j] : 0;
+#pragma unroll
+    for (int j = 0; j < UB; ++j) {
+      if (p0 + 256 * j >= hi) continue;
+      const int q = atomicAdd(&cnt[(int)(u[j] >> 40) & (tb - 1)], 1);
+      col[lo + q] = (uint32_t)(u[j] & IDMASK) | ((uint32_t)(u[j] >> 36) & 1u) << 31;
+      colslot[lo + q] = (uint8_t)((u[j] >> 30) & 63u);
+    }
   }
   if (b == nb - 1 && threadIdx.x == 0) rowptr[n] = hi;
 }
