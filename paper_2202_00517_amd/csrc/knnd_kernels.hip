@@ -148,7 +148,8 @@ __global__ __launch_bounds__(256) void k_init_graph(const PT* __restrict__ P, co
                                                     const int64_t* __restrict__ ioff,
                                                     const uint64_t* __restrict__ iseed) {
   __shared__ uint32_t slot[4][WAVE];
-  const int wave = threadIdx.x >> 6;
+  // (the wave's index is uniform: x's own row is read with scalar loads)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = lane_id();
   const int64_t x = (int64_t)blockIdx.x * 4 + wave;
   if (x >= n) return;  // whole wave; no block-level barrier follows
@@ -891,7 +892,7 @@ void k_hub_reg(JoinArgs a, const double* __restrict__ L,
   __shared__ uint64_t s_need[4][WAVE];
   const int K = a.K, D = a.D, Dp = a.Dp;
   const int lane = lane_id();
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (uniform: hub indices stay scalar)
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   int64_t my_perf = 0;
   for (int64_t v = (int64_t)blockIdx.x * 4 + wv; v < a.n; v += nwaves) {
@@ -1009,7 +1010,7 @@ void k_hub_reg_sub(JoinArgs a, const double* __restrict__ L, const PT* __restric
   __shared__ uint64_t s_need[4][WAVE];
   const int K = a.K, D = a.D, Dp = a.Dp;
   const int lane = lane_id();
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (uniform: hub indices stay scalar)
   const int grp = lane / LG, sub = lane - grp * LG;
   const uint64_t gmask = (LG == 64 ? ~0ull : ((1ull << LG) - 1)) << (grp * LG);
   const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -1198,7 +1199,8 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   __shared__ int s_rows[4][WAVE];  // share rounds: packed row numbers, per wave
   int64_t my_perf = 0;
-  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < a.n; v += nwaves) {
+  for (int64_t v = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); v < a.n;
+       v += nwaves) {
     if (inactive(a, v)) continue;  // whole wave
     const int64_t pf0 = my_perf;
     const int64_t rp = a.rowptr[v];
@@ -2229,7 +2231,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIX ? 5 : 1
   const PT* P = reinterpret_cast<const PT*>(a.P);
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   int64_t my_upd = 0, my_err = 0, my_resc = 0;
-  for (int64_t x = a.own0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); x < a.own1; x += nwaves) {
+  for (int64_t x = a.own0 + (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+       x < a.own1; x += nwaves) {
     if (inactive(a, x)) continue;  // whole wave
     const int nc = a.sl_n[x];
     if (nc < 0) continue;           // merged by the receiver kernel
@@ -2324,7 +2327,7 @@ void k_recv_wave(JoinArgs a, const int32_t* __restrict__ lists, const int32_t* _
   __shared__ uint8_t s_csl[4][WAVE];
   __shared__ double s_xr[MIX ? 4 : 1][MIX ? HUB_MAXD + 16 : 1], s_lr[MIX ? 4 : 1][MIX ? HUB_MAXD + 16 : 1];
   const int lane = lane_id();
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int K = a.K, D = a.D, Dp = a.Dp;
   const int64_t n = a.n;
   const int32_t* list = lists + (int64_t)cls * n;
