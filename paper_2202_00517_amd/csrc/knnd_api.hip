@@ -213,7 +213,7 @@ void free_ctx(Ctx& c) {
                   c.dstats, c.dflag, c.Ph, c.Lh, c.S, c.seg32,
                   c.inst_of, c.ioff, c.iseed, c.iM, c.iD, c.iactive, c.istats, c.vcnt,
                   c.sl_n, c.sl_id, c.sl_key, c.csr_T, c.csr_bcount, c.csr_bfill, c.csr_bbase, c.Pw,
-                  c.vchg, c.vev};
+                  c.vchg, c.vev, c.Hrow};
   // the blocks go back to the cache: the context's work must have finished
   (void)hipStreamSynchronize(c.stream);
   if (!c.arena)
@@ -385,9 +385,20 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
         drop_optional(c, pmark, &c.seg, &c.sl_key);
         ok = c.mixed;  // mixed only
       }
+      // (the register hub kernel's rows; not in fixed-scratch mode)
+      if (pok && !c.arena && c.D <= knnd::HUB_MAXD) {
+        const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
+        c.hstride = (int64_t)(((size_t)c.D * (8 + esz) + 127) / 128 * 128);
+        const size_t hmark = c.arena_used;
+        if (balloc(c, &c.Hrow, (size_t)n * c.hstride + knnd::HUB_MAXD * 16) != hipSuccess) {
+          drop_optional(c, hmark, &c.Hrow);
+          c.hstride = 0;
+        }
+      }
     }
     if (!ok) {
-      drop_optional(c, mark, &c.sl_n, &c.sl_id, &c.Pw, &c.Ph, &c.Lh, &c.S, &c.seg32, &c.seg, &c.sl_key);
+      drop_optional(c, mark, &c.sl_n, &c.sl_id, &c.Pw, &c.Ph, &c.Lh, &c.S, &c.seg32, &c.seg, &c.sl_key, &c.Hrow);
+      c.hstride = 0;
       c.use_hub = false;
       c.mixed = false;
     }
@@ -407,6 +418,7 @@ int finish_create(Ctx& c) {
   KNND_HIP(hipMemsetAsync(c.dflag, 0, sizeof(int32_t), c.stream));
   KNND_HIP(knnd::launch_log_table(c, c.dflag));
   if (c.Pw) KNND_HIP(knnd::launch_widen(c));
+  if (c.Hrow) KNND_HIP(knnd::launch_hub_rows(c));
   int32_t bad = 0;
   KNND_HIP(hipMemcpyAsync(&bad, c.dflag, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
   KNND_HIP(hipStreamSynchronize(c.stream));

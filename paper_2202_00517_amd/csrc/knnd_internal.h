@@ -103,6 +103,12 @@ struct Ctx {
   uint32_t* col = nullptr;    // [nK]
   uint8_t* colslot = nullptr; // [nK] slot of the edge in its source's list
   double* seg = nullptr;      // [nK(K+Ks+1)] candidate keys by snapshot edge (hub form)
+  // Exact hub form: each point's D logs, then its D coordinates (the input
+  // type), in one row of whole 128-byte lines, hstride bytes apart; the
+  // register hub kernel reads these instead of the rows of L and P (which
+  // straddle lines).  Optional: null when it did not fit.
+  double* Hrow = nullptr;
+  int64_t hstride = 0;
   // mixed precision
   bool mixed = false;
   int dk = 0;                 // D padded to 32 or 64 (MFMA K dimension)
@@ -230,6 +236,7 @@ hipError_t pmalloc(T** p, size_t bytes) {
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_log_table(const Ctx& c, int32_t* bad);
 hipError_t launch_widen(const Ctx& c);
+hipError_t launch_hub_rows(const Ctx& c);
 hipError_t launch_init_graph(const Ctx& c);
 hipError_t launch_fcr(const Ctx& c, const uint32_t* F, int64_t round, int64_t* hits,
                       const int64_t* round_dev = nullptr);

@@ -884,13 +884,13 @@ constexpr int hub_reg_waves_per_eu() {
 
 template <int MAXD, typename PT, int CK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hub_reg_waves_per_eu<MAXD>())))
-void k_hub_reg(JoinArgs a, const double* __restrict__ L,
-                                                 const PT* __restrict__ P, const double* __restrict__ Pd) {
+void k_hub_reg(JoinArgs a, const double* __restrict__ L, int64_t lst, const PT* __restrict__ P, int64_t pst,
+               const double* __restrict__ Pd) {
   constexpr int CH = 16;  // candidates per LDS tile
   __shared__ double s_keys[4][WAVE][CH + 1];
   __shared__ int64_t s_b0[4][WAVE];
   __shared__ uint64_t s_need[4][WAVE];
-  const int K = a.K, D = a.D, Dp = a.Dp;
+  const int K = a.K, D = a.D;
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (uniform: hub indices stay scalar)
   const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -942,8 +942,8 @@ void k_hub_reg(JoinArgs a, const double* __restrict__ L,
       // extra terms fma(0, y, acc) (y finite) leave acc unchanged.  Rows are
       // read past their end into the zeroed tail padding of P and L.
       double pr[MAXD], lr[MAXD];
-      const PT* prow = P + (on ? r : 0) * D;
-      const double* lrow = L + (on ? r : 0) * Dp;
+      const PT* prow = P + (on ? r : 0) * pst;
+      const double* lrow = L + (on ? r : 0) * lst;
 #pragma unroll
       for (int i = 0; i < MAXD; ++i) {
         const double pv = (double)prow[i];
@@ -960,7 +960,7 @@ void k_hub_reg(JoinArgs a, const double* __restrict__ L,
           if (__ballot(nd) == 0) continue;
           const uint32_t craw = (uint32_t)__shfl((int)fv, ci, WAVE);
           const int64_t cidx = (int64_t)__builtin_amdgcn_readfirstlane(craw & IDMASK);
-          s_keys[wv][lane][cj] = hub_fold<MAXD, CK>(pr, lr, Pd + cidx * D, L + cidx * Dp, D);  // scalar loads
+          s_keys[wv][lane][cj] = hub_fold<MAXD, CK>(pr, lr, Pd + cidx * D, L + cidx * lst, D);  // scalar loads
           my_perf += nd ? 1 : 0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -979,7 +979,7 @@ void k_hub_reg(JoinArgs a, const double* __restrict__ L,
       }
       // slot K: the hub itself, a co-friend candidate of each of its friends
       if (__ballot(need_v)) {
-        const double key = hub_fold<MAXD, CK>(pr, lr, Pd + v * D, L + v * Dp, D);
+        const double key = hub_fold<MAXD, CK>(pr, lr, Pd + v * D, L + v * lst, D);
         if (need_v) {
           a.seg[b1] = key;
           ++my_perf;
@@ -2599,6 +2599,35 @@ hipError_t launch_widen(const Ctx& c) {
   return hipGetLastError();
 }
 
+// The exact register hub kernel's rows: for each point its D logs, then its
+// D coordinates; the rest of the row and the tail are zero (cleared first).
+template <typename PT>
+__global__ void k_hub_rows(const PT* __restrict__ P, const double* __restrict__ L, int64_t n, int D, int Dp,
+                           int64_t hstride, unsigned char* __restrict__ H) {
+  const int64_t total = n * D;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = t / D;
+    const int i = (int)(t - x * D);
+    unsigned char* row = H + x * hstride;
+    reinterpret_cast<double*>(row)[i] = L[x * Dp + i];
+    reinterpret_cast<PT*>(row + (int64_t)D * 8)[i] = P[x * D + i];
+  }
+}
+
+hipError_t launch_hub_rows(const Ctx& c) {
+  const int64_t words = (c.n * c.hstride + HUB_MAXD * 16) / 8;
+  hipError_t e = launch_zero_i64(reinterpret_cast<int64_t*>(c.Hrow), words, c.stream);
+  if (e != hipSuccess) return e;
+  const int64_t total = c.n * c.D;
+  if (c.dtype == 0)
+    hipLaunchKernelGGL(k_hub_rows<float>, dim3(grid_for(total, 256, 65536)), dim3(256), 0, c.stream,
+                       (const float*)c.P, c.L, c.n, c.D, c.Dp, c.hstride, reinterpret_cast<unsigned char*>(c.Hrow));
+  else
+    hipLaunchKernelGGL(k_hub_rows<double>, dim3(grid_for(total, 256, 65536)), dim3(256), 0, c.stream,
+                       (const double*)c.P, c.L, c.n, c.D, c.Dp, c.hstride, reinterpret_cast<unsigned char*>(c.Hrow));
+  return hipGetLastError();
+}
+
 hipError_t launch_log_table(const Ctx& c, int32_t* bad) {
   const int64_t total = c.n * c.Dp;
   const int g = grid_for(total, 256, 65536);
@@ -2819,7 +2848,13 @@ static hipError_t launch_hub_reg(const Ctx& c, const JoinArgs& a) {
   const int grid = (int)std::min<int64_t>((c.n + 3) / 4, (int64_t)per_cu * c.num_cu * 4);
   // candidate point rows as FP64 (read only by the reverse-KL fold)
   const double* Pd = c.Pw ? c.Pw : reinterpret_cast<const double*>(c.P);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, c.L, (const PT*)c.P, Pd);
+  // logs and coordinates from the line-aligned rows when they exist
+  const double* Lr = c.Hrow ? c.Hrow : c.L;
+  const int64_t lst = c.Hrow ? c.hstride / 8 : c.Dp;
+  const PT* Pr = c.Hrow ? reinterpret_cast<const PT*>(reinterpret_cast<const unsigned char*>(c.Hrow) + (int64_t)c.D * 8)
+                        : (const PT*)c.P;
+  const int64_t pst = c.Hrow ? c.hstride / (int64_t)sizeof(PT) : c.D;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, c.stream, a, Lr, lst, Pr, pst, Pd);
   return hipGetLastError();
 }
 
