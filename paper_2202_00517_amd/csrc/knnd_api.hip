@@ -385,8 +385,9 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
         drop_optional(c, pmark, &c.seg, &c.sl_key);
         ok = c.mixed;  // mixed only
       }
-      // (the register hub kernel's rows; not in fixed-scratch mode)
-      if (pok && !c.arena && c.D <= knnd::HUB_MAXD) {
+      // (the register hub kernel's rows, for rows of at most 24 coordinates,
+      // the kernel's three-wave form; not in fixed-scratch mode)
+      if (pok && !c.arena && c.D <= 24) {
         const size_t esz = c.dtype == KNND_F32 ? 4 : 8;
         c.hstride = (int64_t)(((size_t)c.D * (8 + esz) + 127) / 128 * 128);
         const size_t hmark = c.arena_used;
