@@ -369,7 +369,7 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
       const bool mok = balloc(c, &c.Ph, (size_t)n * c.dk * 4 + 64) == hipSuccess &&
                        balloc(c, &c.Lh, (size_t)n * c.dk * 4 + 64) == hipSuccess &&
                        dalloc(c, &c.S, (size_t)n) == hipSuccess &&
-                       dalloc(c, &c.seg32, nK * (size_t)(K + c.Ks + 1)) == hipSuccess;
+                       dalloc(c, &c.seg32, nK * (size_t)(2 * c.Ks + 1)) == hipSuccess;
       if (!mok) {
         drop_optional(c, mmark, &c.Ph, &c.Lh, &c.S, &c.seg32);
         c.mixed = false;
@@ -379,7 +379,7 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
     // form can run)
     if (ok && (!c.mixed || c.auto_prec)) {
       const size_t pmark = c.arena_used;
-      const bool pok = dalloc(c, &c.seg, nK * (size_t)(K + c.Ks + 1)) == hipSuccess &&
+      const bool pok = dalloc(c, &c.seg, nK * (size_t)(2 * c.Ks + 1)) == hipSuccess &&
                        dalloc(c, &c.sl_key, sl) == hipSuccess;
       if (!pok) {
         drop_optional(c, pmark, &c.seg, &c.sl_key);
@@ -480,7 +480,7 @@ int prepare_mixed(Ctx& c, size_t nK) {
     c.seg32 = nullptr;
     if (!c.plain_ok) {
       const size_t mark = c.arena_used;
-      if (dalloc(c, &c.seg, nK * (size_t)(c.K + c.Ks + 1)) != hipSuccess ||
+      if (dalloc(c, &c.seg, nK * (size_t)(2 * c.Ks + 1)) != hipSuccess ||
           dalloc(c, &c.sl_key, (size_t)c.n * knnd::SHORT_LIST) != hipSuccess) {
         drop_optional(c, mark, &c.seg, &c.sl_key);
         c.use_hub = false;  // pull form: needs neither

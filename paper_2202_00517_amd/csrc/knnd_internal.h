@@ -190,8 +190,8 @@ struct JoinArgs {
   const int64_t* rowptr;
   const uint32_t* col;
   const uint8_t* colslot;
-  int64_t nKK;     // n*K*K: offset of the FC part of seg
-  int64_t di_off;  // n*K*(K+Ks): offset of the DI part of seg
+  int64_t nKK;     // n*K*Ks: offset of the FC part of seg (FF rows of K slots padded to Ks)
+  int64_t di_off;  // 2*n*K*Ks: offset of the DI part of seg
   int Ks;          // row stride of F (and of the FC blocks of seg)
   const float* seg32;
   const double* S;

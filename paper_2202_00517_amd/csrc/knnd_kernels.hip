@@ -781,7 +781,7 @@ __global__ __launch_bounds__(256) void k_hub_lds(JoinArgs a) {
         const uint32_t e = a.col[rp + k];
         r = e & IDMASK;
         rnew = e & NEWBIT;
-        b0 = (r * K + a.colslot[rp + k]) * K;  // FF
+        b0 = (r * K + a.colslot[rp + k]) * a.Ks;  // FF
       } else {
         const int sp = k - cv;
         const uint32_t e = s_fv[sp];
@@ -916,7 +916,7 @@ void k_hub_reg(JoinArgs a, const double* __restrict__ L, int64_t lst, const PT* 
           const uint32_t e = a.col[rp + k];
           r = e & IDMASK;
           rnew = e & NEWBIT;
-          b0 = (r * K + a.colslot[rp + k]) * K;  // FF
+          b0 = (r * K + a.colslot[rp + k]) * a.Ks;  // FF
         } else {
           const int sp = k - cv;
           r = fsp & IDMASK;
@@ -1036,7 +1036,7 @@ void k_hub_reg_sub(JoinArgs a, const double* __restrict__ L, const PT* __restric
           const uint32_t e = a.col[rp + k];
           r = e & IDMASK;
           rnew = e & NEWBIT;
-          b0 = (r * K + a.colslot[rp + k]) * K;  // FF
+          b0 = (r * K + a.colslot[rp + k]) * a.Ks;  // FF
         } else {
           const int sp = k - cv;
           r = fsp & IDMASK;
@@ -1257,7 +1257,7 @@ __global__ __launch_bounds__(256) void k_hub_mfma(JoinArgs a, const H* __restric
             const uint32_t e = a.col[rp + row];
             r = e & IDMASK;
             rnew = e & NEWBIT;
-            b0 = (r * K + a.colslot[rp + row]) * K;  // FF
+            b0 = (r * K + a.colslot[rp + row]) * a.Ks;  // FF
           } else {
             const int sp = row - cv;
             r = fsp & IDMASK;
@@ -1772,6 +1772,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
           const IT q = uu / (IT)K;                              // friend j or co-friend q
           ss[u] = (int)(uu - q * (IT)K);                        // entry s of that row
           fetch(inC ? (int64_t)t : (inFC ? (int64_t)q : -1), cw[u], sl[u]);
+          if (inFF) sl[u] = (uint32_t)(q * (IT)a.Ks) + (uint32_t)ss[u];  // slot in x's block (rows of Ks)
           fw[u] = s_fx[inFF ? (int)q : 0];
         }
       };
@@ -1799,7 +1800,7 @@ void k_recv(JoinArgs a, int32_t* __restrict__ lists,
         zr[u] = a.F[rg[u] >= 2 ? v * a.Ks + ss[u] : 0];
         if (SEG) {
           const int64_t kp = rg[u] == 1   ? a.di_off + v * K + sl[u]
-                             : rg[u] == 2 ? x * KK + (int64_t)(t - (IT)c)
+                             : rg[u] == 2 ? x * K * a.Ks + sl[u]
                              : rg[u] == 3 ? a.nKK + (v * K + sl[u]) * a.Ks + ss[u]
                                           : 0;
           kr[u] = MIX ? (KT)a.seg32[kp] : (KT)a.seg[kp];
@@ -2401,6 +2402,7 @@ void k_recv_wave(JoinArgs a, const int32_t* __restrict__ lists, const int32_t* _
           cw[u] = a.col[g];
           sl[u] = (uint32_t)a.colslot[g];
         }
+        if (inFF) sl[u] = (uint32_t)(q * a.Ks + ss[u]);  // slot in x's block (rows of Ks)
         fw[u] = s_fx[w][inFF ? (int)q : 0];
       }
       uint32_t zr[U];
@@ -2412,7 +2414,7 @@ void k_recv_wave(JoinArgs a, const int32_t* __restrict__ lists, const int32_t* _
         const int64_t t = t0 + lane + WAVE * u;
         zr[u] = a.F[rg[u] >= 2 ? v * a.Ks + ss[u] : 0];
         const int64_t kp = rg[u] == 1   ? a.di_off + v * K + sl[u]
-                           : rg[u] == 2 ? x * KK + (t - c)
+                           : rg[u] == 2 ? x * K * a.Ks + sl[u]
                            : rg[u] == 3 ? a.nKK + (v * K + sl[u]) * a.Ks + ss[u]
                                         : 0;
         kr[u] = MIX ? (KT)a.seg32[kp] : (KT)a.seg[kp];
@@ -2939,7 +2941,7 @@ static JoinArgs join_args(const Ctx& c, int64_t* stats) {
   a.rowptr = c.rowptr;
   a.col = c.col;
   a.colslot = c.colslot;
-  a.nKK = c.n * (int64_t)c.K * c.K;
+  a.nKK = c.n * (int64_t)c.K * c.Ks;
   a.Ks = c.Ks;
   a.di_off = a.nKK + c.n * (int64_t)c.K * c.Ks;
   a.seg = c.seg;
