@@ -349,7 +349,7 @@ int setup(Ctx& c, int64_t n, int32_t d, int32_t K, uint64_t seed, const knnd_par
   }
   if (e != hipSuccess) return map_err(e);
   // Hub form: candidate rows of a hub must fit in LDS, and the key slots
-  // (K(K+Ks+1) per point) must fit in memory; otherwise the pull form.  The
+  // (K(2Ks+1) per point) must fit in memory; otherwise the pull form.  The
   // mixed-precision form needs the hub form, D <= 64 (MFMA K dimension) and
   // the KL comparator (its error bound is derived for that key).  Buffers of
   // the hub and mixed forms are optional: when they do not fit, the next
